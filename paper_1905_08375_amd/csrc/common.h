@@ -1,0 +1,117 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "ndl.h"
+
+namespace ndl {
+
+// ------------------------------------------------------------------ errors
+void set_error(const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what, const char* file, int line);
+
+#define NDL_HIP(expr)                                                          \
+    do {                                                                       \
+        hipError_t e_ = (expr);                                                \
+        if (e_ != hipSuccess) return ::ndl::hip_fail(e_, #expr, __FILE__, __LINE__); \
+    } while (0)
+
+#define NDL_TRY(expr)                   \
+    do {                                \
+        int rc_ = (expr);               \
+        if (rc_ != NDL_OK) return rc_;  \
+    } while (0)
+
+// ------------------------------------------------------------------ lattice
+constexpr int cisqrt(int64_t k)
+{
+    int j = 0;
+    while ((int64_t)(j + 1) * (j + 1) <= k) ++j;
+    return j;
+}
+
+// One offset of the horizon ball: z and q = |z|^2.
+struct Off {
+    int z0, z1, z2, q;
+};
+
+// Offsets z with 0 < |z|^2 <= kmax in `dim` dimensions, sorted by |z|^2 and
+// then lexicographically.  half != 0 keeps one of each pair {z, -z} (the one
+// whose first non-zero component is positive).
+std::vector<Off> ball_offsets(int dim, int64_t kmax, bool half);
+
+// ------------------------------------------------------------------ plan
+struct Plan {
+    ndl_problem prob{};        // caller's descriptor (poly points at `poly`)
+    std::vector<double> poly;  // copied coefficients
+    int dim = 0, ncomp = 1, prec = 0, model = 0, form = 0, kernel = 0, norm = 0;
+    int64_t n = 0, N = 0;      // nodes per axis, n^dim
+    int R = 0;                 // collar
+    int64_t P = 0, NP = 0;     // padded extent n + 2R and (n+2R)^dim
+    double m2 = 0.0;           // second-moment target
+    double expo = 0.0;         // g(|z|/m) = m^-expo |z|^expo for power profiles
+    int64_t kmax = 0, kmin = 0;
+    int J = 0;                 // isqrt(kmax): reach of the direct sum
+
+    // per-node data (device, owned by the plan)
+    int32_t* d_k = nullptr;    // integer cutoff k_i (case (a))
+    void* d_scale = nullptr;   // case (a) scale s_i, element type of prec
+    void* d_invm2 = nullptr;   // POLY: 1/m_i^2 (element type of prec)
+    void* d_split = nullptr;   // fast path: weight of the polynomial part per node
+    double* d_invT = nullptr;  // case (b) discrete normalisation 1/T[k], k = 0..kmax
+
+    // half-ball pair table of the generic direct kernel (device, sorted by q)
+    int4* d_pairs = nullptr;   // (z0, z1, z2, q)
+    void* d_pairw = nullptr;   // weights |z|^expo (diffusion) or |z|^(expo-2) (PD)
+    int npairs = 0;
+    int4* d_full = nullptr;    // full ball (case (b))
+    void* d_fullw = nullptr;
+    int nfull = 0;
+    double avg_ball = 0.0;
+
+    // direct-kernel choice
+    int variant = 0;
+    int tile_x = 0, tile_y = 0, tile_z = 0;
+
+    // fast path (Section 3)
+    bool fast = false;
+    int fast_S = 0;            // largest panel side 2^S used
+    int64_t fast_origin = 0;   // tree node index of the first padded node (per axis)
+    std::vector<int64_t> lev_off;   // offsets of each level in d_pyr (elements)
+    std::vector<int64_t> lev_ext;   // panels per axis on each level
+    double* d_pyr = nullptr;   // partial sums, FP64, all levels
+    int64_t pyr_elems = 0;
+    int32_t* d_cntM = nullptr; // lattice count of the full ball (centre included) per k
+};
+
+// host helpers implemented in the .hip files
+int plan_fields(Plan& p, hipStream_t s);                   // k_i, scales, tables
+int launch_direct(Plan& p, const void* u, void* Lu, int batch, hipStream_t s);
+int launch_div(Plan& p, const void* u, void* Lu, int batch, hipStream_t s);
+int launch_div_diag(Plan& p, void* diag, hipStream_t s);
+int fast_prepare(Plan& p, hipStream_t s);
+int launch_fast(Plan& p, const void* u, void* Lu, int batch, hipStream_t s);
+int fast_decomp_host(Plan& p, const int64_t* node, int32_t* out, int cap, int* count);
+int autotune(Plan& p, hipStream_t s);
+
+// element size of a precision
+inline size_t elem_size(int prec) { return prec == NDL_F64 ? 8 : 4; }
+
+// Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b % 8).  Give each XCD a contiguous run of tiles so that neighbouring tiles,
+// which share halo rows, hit the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb)
+{
+    int per = nb >> 3;
+    if (b >= (per << 3)) return b;
+    return (b & 7) * per + (b >> 3);
+}
+
+}  // namespace ndl
