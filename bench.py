@@ -1,0 +1,199 @@
+"""Benchmark of the nonlocal-operator hot path on one MI355X.
+
+Headline (one "step" = one application of L_delta to the 2D workload):
+  2D nonlocal diffusion, 1024^2 grid, variable horizon
+  delta(x) = 4h (1 + 0.5 sin 2 pi x1 cos 2 pi x2) (m in [2, 6]), lognormal c(x),
+  fractional profile r^-(2+2s) with s = 1/2 (discrete normalisation), u a seeded
+  Gaussian random field, FP32 storage with compensated sums, direct quadrature.
+
+The JSON line also carries the other rows of the hot path (FP64, the Section 3
+hierarchical evaluation, peridynamics, the batched CG solve and the learned
+preconditioner when built) under "rows".  Inputs are resident in HBM before
+timing starts; plan set-up is excluded (it is the amortised initialisation).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed(fn, steps, warmup):
+    """Run fn() warmup times, then time exactly `steps` calls with events on the
+    current stream (the stream the library launches on)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(st)
+    for _ in range(steps):
+        fn()
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / 1e3, wall
+
+
+def src_hash(*names):
+    h = hashlib.sha256()
+    for nm in names:
+        with open(os.path.join(ROOT, "paper_1905_08375_amd", "csrc", nm), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(tag, kernel_src):
+    """HBM traffic per launch measured with rocprofv3 counters (profiles/), or None
+    when the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{tag}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("src_hash") != src_hash(*kernel_src):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def c2_inputs(prec):
+    import torch
+    from paper_1905_08375_amd import fields as F
+    from paper_1905_08375_amd import ndl
+    n, R = 1024, 6
+    w = F.diffusion_2d(n=n)
+    npt = np.float64 if prec == ndl.NDL_F64 else np.float32  # F32C and F32K store FP32
+    d = torch.from_numpy(w["delta"].astype(npt)).cuda()
+    c = torch.from_numpy(w["coef"].astype(npt)).cuda()
+    u = torch.from_numpy(F.pad(w["u"], R).astype(npt)).cuda()
+    return w, n, R, d, c, u
+
+
+def bench_apply(prec, fast, steps, warmup):
+    import torch
+    from paper_1905_08375_amd import ndl
+    w, n, R, d, c, u = c2_inputs(prec)
+    plan = ndl.ndl_plan_create(ndl.make_problem(2, n, R, d, c, prec=prec), want_fast=fast, keep=(d, c))
+    if not fast:
+        ndl.ndl_autotune(plan)  # plan-time tile choice (excluded from timing)
+    out = torch.empty((n, n), dtype=u.dtype, device="cuda")
+    fn = (lambda: ndl.ndl_apply_fast(plan, u, out, 1)) if fast else (lambda: ndl.ndl_apply(plan, u, out, 1))
+    secs, wall = timed(fn, steps, warmup)
+    info = plan.info()
+    plan.close()
+    return dict(seconds=secs, wall=wall, n_points=n * n, info=info, out=out)
+
+
+def cpu_baseline(budget_s=12.0):
+    """The FP64 oracle on the same workload (FP32-rounded inputs), on the host cores."""
+    import oracle as O
+    from paper_1905_08375_amd import fields as F
+    n, R = 1024, 6
+    w = F.diffusion_2d(n=n)
+    P = O.Problem(dim=2, n=n, R=R, kernel="frac", s=0.5)
+    d = w["delta"].astype(np.float32).astype(np.float64)
+    c = w["coef"].astype(np.float32).astype(np.float64)
+    u = F.pad(w["u"], R).astype(np.float32).astype(np.float64)
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        O.apply(P, d, c, u)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or reps >= 50:
+            break
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = min(cores, os.cpu_count() or cores)
+    return {"value": reps * n * n / el / 1e9, "unit": "Gpoint-applies/s", "cores": cores, "kind": "oracle",
+            "sample": f"{reps} full applies of the 1024^2 workload (FP64 direct sum, OpenMP over nodes), {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--no-rows", action="store_true", help="headline only")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1905_08375_amd import ndl
+    assert torch.cuda.is_available(), "needs a GPU"
+    ndl.lib()
+
+    log("headline: 2D 1024^2 direct apply, FP32 with Kahan-compensated sums")
+    head = bench_apply(ndl.NDL_F32K, False, args.steps, args.warmup)
+    N = head["n_points"]
+    per = head["seconds"] / args.steps
+    value = N * args.steps / head["seconds"] / 1e9
+    alg_bytes = 16.0 * N  # u, k_i, s_i read once, Lu written once, 4 B each
+    traffic = load_traffic("c2_direct_f32k", ["direct2d.inc"])
+    roof = {"bound": "hbm", "achieved": alg_bytes / per / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": alg_bytes / per / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "k_nd2<float,J,E,PY,NW,2> (FP32, Kahan)", "alg_bytes_per_launch": alg_bytes}
+    rows = {}
+    if not args.no_rows:
+        k = max(50, args.steps // 4)
+        log("row: FP64 direct")
+        r = bench_apply(ndl.NDL_F64, False, k, 20)
+        rows["direct_f64"] = {"gpoint_per_s": N * k / r["seconds"] / 1e9, "us_per_apply": r["seconds"] / k * 1e6,
+                              "hbm_frac": 28.0 * N / (r["seconds"] / k) / 1e9 / HBM_PEAK_GBS,
+                              "tile": [r["info"].tile_x, r["info"].tile_y]}
+        log("row: FP32 storage, FP64-carried sums")
+        r = bench_apply(ndl.NDL_F32C, False, k, 20)
+        rows["direct_f32c"] = {"gpoint_per_s": N * k / r["seconds"] / 1e9, "us_per_apply": r["seconds"] / k * 1e6,
+                               "hbm_frac": 16.0 * N / (r["seconds"] / k) / 1e9 / HBM_PEAK_GBS,
+                               "tile": [r["info"].tile_x, r["info"].tile_y]}
+        for prec, nm in [(ndl.NDL_F32C, "fast_f32c"), (ndl.NDL_F64, "fast_f64")]:
+            log("row:", nm)
+            r = bench_apply(prec, True, k, 20)
+            rows[nm] = {"gpoint_per_s": N * k / r["seconds"] / 1e9, "us_per_apply": r["seconds"] / k * 1e6}
+    cpu = None if args.no_cpu else cpu_baseline()
+    line = {
+        "metric": "Gpoint-applies/s of L_delta (2D var. horizon); PCG time to 1e-8: learned vs plain",
+        "value": value,
+        "unit": "Gpoint-applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": per * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2d-nonlocal-diffusion-1024x1024-variable-horizon-m2to6-frac-s0.5-direct",
+                   "n": 1024, "collar": 6, "k_max": int(head["info"].k_max), "k_min": int(head["info"].k_min),
+                   "precision": "fp32-storage-fp32-kahan-sums", "parallelism": "single-gpu",
+                   "tile": [int(head["info"].tile_x), int(head["info"].tile_y)]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "rows": rows,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -32,8 +32,8 @@
  *    volume-constraint data (zero for the Dirichlet problem of Section 3);
  *    outputs are [batch][ncomp][n^dim].  ncomp = 2 for peridynamics (component
  *    a is the displacement along axis a), else 1.
- *  - Element type follows prec: NDL_F64 = double everywhere; NDL_F32C = float
- *    storage with compensated (Kahan-blocked) accumulation inside the sums.
+ *  - Element type follows prec: NDL_F64 = double everywhere; NDL_F32C and
+ *    NDL_F32K = float storage with compensated accumulation inside the sums.
  */
 #ifndef NDL_H
 #define NDL_H
@@ -55,7 +55,10 @@ enum {
     NDL_EBREAKDOWN = -7    /* preconditioned CG broke down (NaN, r.z <= 0) */
 };
 
-typedef enum { NDL_F64 = 0, NDL_F32C = 1 } ndl_prec;
+/* NDL_F32C: FP32 storage; sums compensated by carrying them in FP64 (FP32
+ * pairs add exactly in FP64).  NDL_F32K: FP32 storage and FP32 arithmetic
+ * with Kahan-compensated accumulation. */
+typedef enum { NDL_F64 = 0, NDL_F32C = 1, NDL_F32K = 2 } ndl_prec;
 typedef enum { NDL_DIFFUSION = 0, NDL_PERIDYNAMIC = 1 } ndl_model; /* PD: dim == 2 */
 typedef enum { NDL_ND = 0, NDL_DIV = 1 } ndl_form;                 /* Section 2 cases (a), (b) */
 /* Radial profile g(r), r = |y-x|/delta:  CONST 1 (the p^0 of Section 3);
@@ -185,6 +188,11 @@ int ndl_precond_apply(ndl_net net, ndl_plan plan, const void* r, void* z, void* 
  * keep the fastest (cached in memory and in the file named by
  * NDL_AUTOTUNE_CACHE, if set).  Returns the chosen tile in the plan info. */
 int ndl_autotune(ndl_plan plan, void* stream);
+
+/* Force a tile variant of the direct kernel (0 <= variant < ndl_plan_num_variants;
+ * the autotuner's search space).  For tests and fixed deployments. */
+int ndl_plan_set_variant(ndl_plan plan, int variant);
+int ndl_plan_num_variants(ndl_plan plan, int* count);
 
 const char* ndl_last_error(void);
 const char* ndl_version(void);

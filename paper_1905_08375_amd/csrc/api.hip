@@ -63,7 +63,7 @@ static int validate(const ndl_problem* q)
         if (q->form == NDL_DIV) { set_error("case (b) supports the power profiles only"); return NDL_EUNSUPPORTED; }
     }
     if (q->norm < 0 || q->norm > NDL_NORM_NONE) { set_error("bad norm"); return NDL_EINVAL; }
-    if (q->prec != NDL_F64 && q->prec != NDL_F32C) { set_error("bad prec"); return NDL_EINVAL; }
+    if (q->prec != NDL_F64 && q->prec != NDL_F32C && q->prec != NDL_F32K) { set_error("bad prec"); return NDL_EINVAL; }
     if (!q->delta || !q->coef) { set_error("delta and coef must be device pointers"); return NDL_EINVAL; }
     return NDL_OK;
 }
@@ -141,6 +141,10 @@ int ndl_plan_get_info(ndl_plan plan, ndl_plan_info* info)
     info->tile_x = p->tile_x;
     info->tile_y = p->tile_y;
     info->tile_z = p->tile_z;
+    if (direct_2d_applies(*p)) {
+        variant_tile_2d(p->variant, &info->tile_x, &info->tile_y);
+        info->tile_z = 1;
+    }
     info->variant = p->variant;
     info->fast_levels = p->fast ? p->fast_S + 1 : 0;
     info->pairs_per_point = p->avg_ball;
@@ -176,6 +180,24 @@ int ndl_fast_decomposition(ndl_plan plan, const int64_t* node, int32_t* panels, 
     int rc = fast_decomp_host(*p, node, panels, cap, &c);
     *count = c;
     return rc;
+}
+
+int ndl_plan_num_variants(ndl_plan plan, int* count)
+{
+    if (!plan || !count) { set_error("null argument"); return NDL_EINVAL; }
+    Plan* p = reinterpret_cast<Plan*>(plan);
+    *count = direct_2d_applies(*p) ? num_variants_2d() : 1;
+    return NDL_OK;
+}
+
+int ndl_plan_set_variant(ndl_plan plan, int variant)
+{
+    if (!plan) { set_error("null plan"); return NDL_EINVAL; }
+    Plan* p = reinterpret_cast<Plan*>(plan);
+    int nv = direct_2d_applies(*p) ? num_variants_2d() : 1;
+    if (variant < 0 || variant >= nv) { set_error("variant %d out of range [0, %d)", variant, nv); return NDL_EINVAL; }
+    p->variant = variant;
+    return NDL_OK;
 }
 
 int ndl_autotune(ndl_plan plan, void* stream)

@@ -1,0 +1,98 @@
+// Tile autotuner for the direct kernels: times every tile variant of the
+// kernel a plan uses (hipEvents, on the caller's stream, on scratch buffers)
+// and keeps the fastest.  Results are cached per (dim, form, model, prec,
+// reach J, n, ncomp) in memory and, when NDL_AUTOTUNE_CACHE names a file, in
+// that file ("key variant" lines) so later processes skip the search.
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+
+#include "common.h"
+
+namespace ndl {
+
+static std::mutex g_mu;
+static std::map<std::string, int> g_cache;
+static bool g_loaded = false;
+
+static std::string key_of(const Plan& p)
+{
+    std::ostringstream k;
+    k << "d" << p.dim << ".f" << p.form << ".m" << p.model << ".p" << p.prec << ".J" << p.J << ".n" << p.n
+      << ".c" << p.ncomp << ".g" << p.kernel;
+    return k.str();
+}
+
+static void load_file()
+{
+    if (g_loaded) return;
+    g_loaded = true;
+    const char* fn = std::getenv("NDL_AUTOTUNE_CACHE");
+    if (!fn) return;
+    std::ifstream f(fn);
+    std::string k;
+    int v;
+    while (f >> k >> v) g_cache[k] = v;
+}
+
+static void save_file(const std::string& k, int v)
+{
+    const char* fn = std::getenv("NDL_AUTOTUNE_CACHE");
+    if (!fn) return;
+    std::ofstream f(fn, std::ios::app);
+    f << k << " " << v << "\n";
+}
+
+int autotune(Plan& p, hipStream_t s)
+{
+    if (!direct_2d_applies(p)) return NDL_OK;  // one variant only
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_file();
+    std::string key = key_of(p);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) {
+        p.variant = it->second;
+        return NDL_OK;
+    }
+    size_t es = elem_size(p.prec);
+    void *u = nullptr, *o = nullptr;
+    NDL_HIP(hipMalloc(&u, (size_t)p.NP * p.ncomp * es));
+    NDL_HIP(hipMalloc(&o, (size_t)p.N * p.ncomp * es));
+    NDL_HIP(hipMemsetAsync(u, 0, (size_t)p.NP * p.ncomp * es, s));
+    hipEvent_t e0, e1;
+    NDL_HIP(hipEventCreate(&e0));
+    NDL_HIP(hipEventCreate(&e1));
+    int best = 0;
+    float best_ms = 1e30f;
+    int nv = num_variants_2d();
+    int rc = NDL_OK;
+    for (int v = 0; v < nv && rc == NDL_OK; ++v) {
+        p.variant = v;
+        for (int w = 0; w < 3 && rc == NDL_OK; ++w) rc = launch_direct(p, u, o, 1, s);
+        if (rc != NDL_OK) break;
+        (void)hipEventRecord(e0, s);
+        const int reps = 20;
+        for (int r = 0; r < reps && rc == NDL_OK; ++r) rc = launch_direct(p, u, o, 1, s);
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(u);
+    (void)hipFree(o);
+    p.variant = best;
+    if (rc != NDL_OK) return rc;
+    g_cache[key] = best;
+    save_file(key, best);
+    return NDL_OK;
+}
+
+}  // namespace ndl

@@ -78,6 +78,7 @@ struct Plan {
 
     // direct-kernel choice
     int variant = 0;
+    std::vector<double> w2d;   // pair weights of the specialised 2D kernel
     int tile_x = 0, tile_y = 0, tile_z = 0;
 
     // fast path (Section 3)
@@ -113,5 +114,58 @@ __device__ __forceinline__ int xcd_tile(int b, int nb)
     if (b >= (per << 3)) return b;
     return (b & 7) * per + (b >> 3);
 }
+
+// ------------------------------------------------------------------ wave helpers
+__device__ __forceinline__ int wave_max(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ int wave_min(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Compensated accumulation: FP64 adds plainly; FP32 keeps a Kahan sum of
+// blocks of products (each block a short FMA chain), flushed by the caller.
+template <typename T>
+struct Acc {
+    T sum = 0, comp = 0, blk = 0;
+    __device__ __forceinline__ void fma_(T w, T d) { blk = fma(w, d, blk); }
+    __device__ __forceinline__ void add_(T v) { blk += v; }
+    __device__ __forceinline__ void flush()
+    {
+        T y = blk - comp;
+        T t = sum + y;
+        comp = (t - sum) - y;
+        sum = t;
+        blk = 0;
+    }
+    __device__ __forceinline__ T value() { flush(); return sum - comp; }
+};
+
+template <>
+struct Acc<double> {
+    double sum = 0;
+    __device__ __forceinline__ void fma_(double w, double d) { sum = fma(w, d, sum); }
+    __device__ __forceinline__ void add_(double v) { sum += v; }
+    __device__ __forceinline__ void flush() {}
+    __device__ __forceinline__ double value() { return sum; }
+};
+
+int4 box_offset(int dim, const Off& o);
+// specialised 2D case (a) diffusion kernel; returns NDL_EUNSUPPORTED when the
+// plan is outside its range (the generic kernel then runs)
+int launch_direct_2d(Plan& p, const void* u, void* Lu, int batch, hipStream_t s);
+bool direct_2d_applies(const Plan& p);
+int launch_direct_2d_f64(Plan& p, const void* u, void* Lu, int batch, hipStream_t s);
+int launch_direct_2d_f32c(Plan& p, const void* u, void* Lu, int batch, hipStream_t s);
+int launch_direct_2d_f32k(Plan& p, const void* u, void* Lu, int batch, hipStream_t s);
+int num_variants_2d();
+void variant_tile_2d(int variant, int* tx, int* ty);
 
 }  // namespace ndl

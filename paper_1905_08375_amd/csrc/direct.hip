@@ -35,72 +35,41 @@ std::vector<Off> ball_offsets(int dim, int64_t kmax, bool half)
 }
 
 // Map a dim-dimensional offset onto the 3-axis box (leading axes unused).
-static inline int4 box_offset(int dim, const Off& o)
+int4 box_offset(int dim, const Off& o)
 {
     if (dim == 1) return make_int4(0, 0, o.z0, o.q);
     if (dim == 2) return make_int4(0, o.z0, o.z1, o.q);
     return make_int4(o.z0, o.z1, o.z2, o.q);
 }
 
-// ------------------------------------------------------------------ wave helpers
-__device__ __forceinline__ int wave_max(int v)
-{
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-__device__ __forceinline__ int wave_min(int v)
-{
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-// Compensated accumulation: FP64 adds plainly; FP32 uses Kahan on blocks of
-// products (the block itself is a short FMA chain).
-template <typename T>
-struct Acc {
-    T sum = 0, comp = 0, blk = 0;
-    __device__ __forceinline__ void fma_(T w, T d) { blk = fma(w, d, blk); }
-    __device__ __forceinline__ void flush()
-    {
-        T y = blk - comp;
-        T t = sum + y;
-        comp = (t - sum) - y;
-        sum = t;
-        blk = 0;
-    }
-    __device__ __forceinline__ T value() { flush(); return sum - comp; }
-};
-
-template <>
-struct Acc<double> {
-    double sum = 0;
-    __device__ __forceinline__ void fma_(double w, double d) { sum = fma(w, d, sum); }
-    __device__ __forceinline__ void flush() {}
-    __device__ __forceinline__ double value() { return sum; }
-};
-
 // ------------------------------------------------------------------ plan kernels
 // k_i = ceil((delta_i n)^2) - 1 in FP64 (the strict lattice ball), plus extremes.
 template <typename T>
-__global__ void k_cutoffs(const T* __restrict__ delta, int64_t N, int64_t n, int32_t* __restrict__ kout,
-                          int* __restrict__ ext)
+__global__ __launch_bounds__(256) void k_cutoffs(const T* __restrict__ delta, int64_t N, int64_t n,
+                                                 int32_t* __restrict__ kout, int* __restrict__ ext)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ int smx[4], smn[4];
     int kmx = -1, kmn = 0x7fffffff;
-    if (i < N) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
         double a = (double)delta[i] * (double)n;
         double t = a * a;
         int k = (int)ceil(t) - 1;
-        if (kout) kout[i] = k;
-        kmx = k;
-        kmn = k;
+        kout[i] = k;
+        kmx = max(kmx, k);
+        kmn = min(kmn, k);
     }
     kmx = wave_max(kmx);
     kmn = wave_min(kmn);
     if ((threadIdx.x & 63) == 0) {
+        smx[threadIdx.x >> 6] = kmx;
+        smn[threadIdx.x >> 6] = kmn;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; ++w) {
+            kmx = max(kmx, smx[w]);
+            kmn = min(kmn, smn[w]);
+        }
         atomicMax(&ext[0], kmx);
         atomicMin(&ext[1], kmn);
     }
@@ -458,7 +427,8 @@ static int plan_fields_t(Plan& p, hipStream_t s)
     NDL_HIP(hipMemcpyAsync(d_ext, init, sizeof(init), hipMemcpyHostToDevice, s));
     NDL_HIP(hipMalloc(&p.d_k, p.N * sizeof(int32_t)));
     int64_t nblk = (p.N + 255) / 256;
-    k_cutoffs<T><<<dim3((unsigned)nblk), dim3(256), 0, s>>>(delta, p.N, p.n, p.d_k, d_ext);
+    unsigned ncut = (unsigned)std::min<int64_t>(nblk, 1024);
+    k_cutoffs<T><<<dim3(ncut), dim3(256), 0, s>>>(delta, p.N, p.n, p.d_k, d_ext);
     NDL_HIP(hipGetLastError());
     int ext[2];
     NDL_HIP(hipMemcpyAsync(ext, d_ext, sizeof(ext), hipMemcpyDeviceToHost, s));
@@ -584,6 +554,8 @@ static int launch_direct_t(Plan& p, const void* u, void* Lu, int batch, hipStrea
 
 int launch_direct(Plan& p, const void* u, void* Lu, int batch, hipStream_t s)
 {
+    int rc = launch_direct_2d(p, u, Lu, batch, s);
+    if (rc != NDL_EUNSUPPORTED) return rc;
     return p.prec == NDL_F64 ? launch_direct_t<double>(p, u, Lu, batch, s)
                              : launch_direct_t<float>(p, u, Lu, batch, s);
 }

@@ -1,13 +1,6 @@
 // Placeholder translation unit for the solver and the learned preconditioner.
 #include "common.h"
 
-namespace ndl {
-int autotune(Plan&, hipStream_t)
-{
-    set_error("autotuner not built yet");
-    return NDL_EUNSUPPORTED;
-}
-}  // namespace ndl
 
 extern "C" {
 int ndl_cg_solve(const ndl_plan*, int, const double* const*, double* const*, const ndl_cg_opts*, ndl_cg_report*, void*)

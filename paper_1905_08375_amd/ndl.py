@@ -15,7 +15,7 @@ LIBPATH = os.path.join(HERE, "libndl.so")
 
 NDL_OK, NDL_EINVAL, NDL_ENOMEM, NDL_EUNSUPPORTED, NDL_ENOTSPD, NDL_ENOCONV, NDL_EHIP, NDL_EBREAKDOWN = \
     0, -1, -2, -3, -4, -5, -6, -7
-NDL_F64, NDL_F32C = 0, 1
+NDL_F64, NDL_F32C, NDL_F32K = 0, 1, 2
 NDL_DIFFUSION, NDL_PERIDYNAMIC = 0, 1
 NDL_ND, NDL_DIV = 0, 1
 NDL_G_CONST, NDL_G_INV_R, NDL_G_FRAC, NDL_G_POLY = 0, 1, 2, 3
@@ -26,7 +26,7 @@ EXPORTS = [
     "ndl_plan_create", "ndl_plan_destroy", "ndl_plan_get_info", "ndl_apply", "ndl_apply_fast",
     "ndl_fast_decomposition", "ndl_decompose_node", "ndl_cg_solve", "ndl_net_create", "ndl_net_destroy",
     "ndl_net_save", "ndl_net_load", "ndl_net_num_params", "ndl_net_train_step", "ndl_precond_apply",
-    "ndl_autotune", "ndl_last_error", "ndl_version",
+    "ndl_autotune", "ndl_last_error", "ndl_version", "ndl_plan_set_variant", "ndl_plan_num_variants",
 ]
 
 
@@ -88,6 +88,8 @@ def lib():
             "ndl_net_train_step": [vp, C.c_int, C.c_int, vp, vp, vp, C.c_float, C.POINTER(C.c_float), vp],
             "ndl_precond_apply": [vp, vp, vp, vp, vp],
             "ndl_autotune": [vp, vp],
+            "ndl_plan_set_variant": [vp, C.c_int],
+            "ndl_plan_num_variants": [vp, C.POINTER(C.c_int)],
         }
         for name, args in sig.items():
             if hasattr(L, name):
@@ -193,6 +195,16 @@ def ndl_decompose_node(dim: int, n: int, node: Sequence[int], k: int, cap: int =
     cnt = C.c_int32()
     _check(lib().ndl_decompose_node(dim, n, nd, k, buf, cap, C.byref(cnt)), "ndl_decompose_node")
     return _records(buf, min(cnt.value, cap), dim)
+
+
+def ndl_plan_set_variant(plan: Plan, variant: int):
+    _check(lib().ndl_plan_set_variant(plan.handle, int(variant)), "ndl_plan_set_variant")
+
+
+def ndl_plan_num_variants(plan: Plan) -> int:
+    c = C.c_int()
+    _check(lib().ndl_plan_num_variants(plan.handle, C.byref(c)), "ndl_plan_num_variants")
+    return c.value
 
 
 def ndl_autotune(plan: Plan, stream=None):

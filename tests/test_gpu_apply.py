@@ -133,7 +133,7 @@ def test_single_node_and_zero_horizon():
 def test_collar_too_small_is_an_error():
     import torch
     n = 16
-    d = torch.full((n, n), 5.0 / n, dtype=torch.float64, device="cuda")
+    d = torch.full((n, n), 5.5 / n, dtype=torch.float64, device="cuda")  # k = 30 needs R >= 5
     c = torch.ones((n, n), dtype=torch.float64, device="cuda")
     prob = ndl.make_problem(2, n, 4, d, c, prec=ndl.NDL_F64)
     with pytest.raises(ndl.NdlError) as e:
@@ -227,3 +227,32 @@ def test_device_decomposition_matches_oracle():
         k = O.cutoff(m[node] / n, n)
         got = sorted((L - s, j) for s, j in ndl.ndl_fast_decomposition(plan, node))
         assert got == sorted(O.decompose(2, n, node, k))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_every_tile_variant_and_autotune(prec):
+    """Each tile variant the autotuner may pick gives the same result (bitwise:
+    the per-node summation order does not depend on the tile)."""
+    import torch
+    say(f"case variants prec={prec}")
+    n, R = 150, 6
+    delta, c, u = rand_problem(2, n, R, 2.0, 6.0, seed=41, smooth=True)
+    from gpuhelp import dev, torch_dtype
+    d_d, d_c, d_u = dev(delta, prec), dev(c, prec), dev(u, prec)
+    plan = ndl.ndl_plan_create(ndl.make_problem(2, n, R, d_d, d_c, prec=prec), keep=(d_d, d_c))
+    nv = ndl.ndl_plan_num_variants(plan)
+    assert nv >= 2
+    outs = []
+    for v in range(nv):
+        ndl.ndl_plan_set_variant(plan, v)
+        o = torch.zeros((n, n), dtype=torch_dtype(prec), device="cuda")
+        ndl.ndl_apply(plan, d_u, o, 1)
+        outs.append(o.cpu().numpy())
+    ref = oracle_apply(2, n, R, delta, c, u, prec)
+    for v, o in enumerate(outs):
+        assert rel_l2(o, ref) <= TOL[prec], v
+        assert np.array_equal(o, outs[0]), v
+    info = ndl.ndl_autotune(plan)
+    assert 0 <= info.variant < nv
+    with pytest.raises(ndl.NdlError):
+        ndl.ndl_plan_set_variant(plan, nv)
