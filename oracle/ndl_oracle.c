@@ -116,6 +116,44 @@ static double radial_moment(const or_problem* p)
  *                      operator reproduces 2d (diffusion) on |x|^2 exactly;
  * norm 1 (continuous): A * int_{B_delta} g(|y|/delta) |y|^2 dy = M;
  * norm 2 (none):       A = delta^-(d+2), the literal constant of eq. "kernel". */
+/* Exponent e of a power profile g(r) = r^e (kernels 0, 1, 2). */
+static double power_exponent(const or_problem* p)
+{
+    if (p->kernel == 0) return 0.0;
+    if (p->kernel == 1) return -1.0;
+    return -((double)p->dim + 2.0 * p->s);
+}
+
+/* Memo of the lattice moment sums T_e[k] = sum_{0<|z|^2<=k} |z|^(e+2) for the
+ * power profiles, where g(|z|/m) |z|^2 = m^-e |z|^(e+2) factors the
+ * m-dependence out of the discrete normalisation sum.  Filled by enumeration. */
+typedef struct {
+    int64_t kmax;
+    double* T;
+} moment_memo;
+
+static void memo_build(const or_problem* p, int64_t kmax, moment_memo* mm)
+{
+    int d = p->dim;
+    double e = power_exponent(p);
+    mm->kmax = kmax;
+    mm->T = (double*)calloc((size_t)(kmax + 1), sizeof(double));
+    int64_t J = isqrt_floor(kmax);
+    int64_t z[3] = {0, 0, 0};
+    int64_t lo1 = d >= 2 ? -J : 0, hi1 = d >= 2 ? J : 0;
+    int64_t lo2 = d >= 3 ? -J : 0, hi2 = d >= 3 ? J : 0;
+    for (z[0] = -J; z[0] <= J; z[0]++)
+        for (z[1] = lo1; z[1] <= hi1; z[1]++)
+            for (z[2] = lo2; z[2] <= hi2; z[2]++) {
+                int64_t q = z[0] * z[0] + z[1] * z[1] + z[2] * z[2];
+                if (q == 0 || q > kmax) continue;
+                mm->T[q] += pow(sqrt((double)q), e + 2.0);
+            }
+    for (int64_t k = 1; k <= kmax; k++) mm->T[k] += mm->T[k - 1];
+}
+
+static const moment_memo* g_memo = NULL; /* set for the duration of one apply */
+
 double or_norm(const or_problem* p, int64_t k, double m, double delta)
 {
     int d = p->dim;
@@ -123,6 +161,11 @@ double or_norm(const or_problem* p, int64_t k, double m, double delta)
     if (p->norm == 2) return 1.0 / pow(delta, d + 2.0);
     if (p->norm == 1)
         return p->m2 / (sphere_area(d) * pow(delta, d + 2.0) * radial_moment(p));
+    if (g_memo && p->kernel != 3 && k <= g_memo->kmax) {
+        double e = power_exponent(p);
+        double T = g_memo->T[k];
+        return T > 0.0 ? p->m2 * pow(m, e) / (pow(h, (double)d + 2.0) * T) : INFINITY;
+    }
     double hd = pow(h, (double)d);
     int64_t J = isqrt_floor(k);
     double sum = 0.0;
@@ -259,6 +302,16 @@ static int64_t div_reach(const or_problem* p, const double* delta)
     return isqrt_floor(or_cutoff(dmax, p->n));
 }
 
+static int64_t max_cutoff(const or_problem* p, const double* delta)
+{
+    int64_t N = npoints(p), km = 0;
+    for (int64_t i = 0; i < N; i++) {
+        int64_t k = or_cutoff(delta[i], p->n);
+        if (k > km) km = k;
+    }
+    return km;
+}
+
 int or_apply_div(const or_problem* p, const double* delta, const double* coef,
                  const double* u, double* out)
 {
@@ -267,6 +320,8 @@ int or_apply_div(const or_problem* p, const double* delta, const double* coef,
     double hd = pow(1.0 / (double)p->n, (double)d);
     int64_t J = div_reach(p, delta);
     if (J > p->R) return -1;
+    moment_memo mm = {0, NULL};
+    if (p->norm == 0 && p->kernel != 3) { memo_build(p, max_cutoff(p, delta), &mm); g_memo = &mm; }
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; i++) {
         int64_t x[3], y[3], z[3] = {0, 0, 0}, kij;
@@ -287,6 +342,8 @@ int or_apply_div(const or_problem* p, const double* delta, const double* coef,
                 }
         out[i] = acc;
     }
+    g_memo = NULL;
+    free(mm.T);
     return 0;
 }
 
@@ -297,6 +354,8 @@ int or_div_diag(const or_problem* p, const double* delta, const double* coef, do
     int64_t N = npoints(p);
     double hd = pow(1.0 / (double)p->n, (double)d);
     int64_t J = div_reach(p, delta);
+    moment_memo mm = {0, NULL};
+    if (p->norm == 0 && p->kernel != 3) { memo_build(p, max_cutoff(p, delta), &mm); g_memo = &mm; }
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; i++) {
         int64_t x[3], y[3], z[3] = {0, 0, 0}, kij;
@@ -316,6 +375,8 @@ int or_div_diag(const or_problem* p, const double* delta, const double* coef, do
                 }
         diag[i] = acc;
     }
+    g_memo = NULL;
+    free(mm.T);
     return 0;
 }
 

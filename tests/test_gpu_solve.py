@@ -1,0 +1,105 @@
+"""Batched CG (ndl_cg_solve) against the FP64 oracle: -L_div x = b to a relative
+FP64 true residual of 1e-8, several uneven problems in one call."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1905_08375_amd import fields as F
+from paper_1905_08375_amd import ndl
+from gpuhelp import dev, say
+
+pytestmark = pytest.mark.gpu
+
+
+def problems(sizes, dim=2, seed=0, mlo=2.0, mhi=8.0):
+    out = []
+    for i, n in enumerate(sizes):
+        g = np.random.default_rng(seed + i)
+        X = F.mesh(n, dim)
+        ph = g.uniform(0, 1, size=2)
+        m = (mlo + mhi) / 2 + (mhi - mlo) / 2 * np.sin(2 * np.pi * (X[0] + ph[0])) * np.cos(2 * np.pi * (X[-1] + ph[1]))
+        c = np.exp(F.grf(n, dim, 0.5, 0.1, 4, 2000 + seed + i))
+        b = g.standard_normal((n,) * dim)
+        out.append((n, m / n, c, b))
+    return out
+
+
+def run(probs, prec, dim=2, R=8, **kw):
+    import torch
+    plans, bs, xs, keep = [], [], [], []
+    for n, delta, c, b in probs:
+        d_d, d_c = dev(delta, prec), dev(c, prec)
+        plans.append(ndl.ndl_plan_create(ndl.make_problem(dim, n, R, d_d, d_c, form=ndl.NDL_DIV, prec=prec),
+                                         keep=(d_d, d_c)))
+        bs.append(torch.from_numpy(b.astype(np.float64)).cuda())
+        xs.append(torch.zeros((n,) * dim, dtype=torch.float64, device="cuda"))
+    rc, reps = ndl.ndl_cg_solve(plans, bs, xs, **kw)
+    torch.cuda.synchronize()
+    return rc, reps, [x.cpu().numpy() for x in xs]
+
+
+def oracle_relres(n, delta, c, b, x, prec, dim=2, R=8):
+    P = O.Problem(dim=dim, n=n, R=R, form="div", kernel="frac")
+    npt = np.float64 if prec == ndl.NDL_F64 else np.float32
+    d64 = delta.astype(npt).astype(np.float64)
+    c64 = c.astype(npt).astype(np.float64)
+    Ax = -O.apply(P, d64, c64, F.pad(x, R))
+    return np.linalg.norm(b - Ax) / np.linalg.norm(b), d64, c64
+
+
+@pytest.mark.parametrize("prec", [ndl.NDL_F64, ndl.NDL_F32C])
+def test_batched_cg_reaches_1e8(prec):
+    say(f"case cg prec={prec}")
+    probs = problems([40, 56, 64, 33])
+    rc, reps, xs = run(probs, prec, rtol=1e-8)
+    assert rc == ndl.NDL_OK, ndl.ndl_last_error()
+    for (n, delta, c, b), rep, x in zip(probs, reps, xs):
+        rr, d64, c64 = oracle_relres(n, delta, c, b, x, prec)
+        say(f"  n={n} iters={rep.iters} outer={rep.outer} gpu_res={rep.rel_res_fp64:.2e} oracle_res={rr:.2e}")
+        assert rep.converged == 1
+        assert rep.rel_res_fp64 <= 1e-8
+        assert rr <= 1.05e-8
+        # the oracle's own solve: x agrees within the residual-implied bound
+        P = O.Problem(dim=2, n=n, R=8, form="div", kernel="frac")
+        xo, it, rro, ok = O.cg_div(P, d64, c64, b, rtol=1e-10)
+        assert ok
+        assert np.linalg.norm(x - xo) <= 1e-5 * np.linalg.norm(xo)
+        if prec == ndl.NDL_F64:
+            _, it8, _, _ = O.cg_div(P, d64, c64, b, rtol=1e-8)
+            assert abs(rep.iters - it8) <= 3, (rep.iters, it8)
+
+
+def test_cg_3d():
+    say("case cg 3d")
+    probs = []
+    for i, n in enumerate([12, 16]):
+        g = np.random.default_rng(50 + i)
+        m = g.uniform(2.0, 4.0, (n, n, n))
+        c = np.exp(g.normal(0, 0.5, (n, n, n)))
+        b = g.standard_normal((n, n, n))
+        probs.append((n, m / n, c, b))
+    rc, reps, xs = run(probs, ndl.NDL_F32C, dim=3, R=4, rtol=1e-8)
+    assert rc == ndl.NDL_OK
+    for (n, delta, c, b), rep, x in zip(probs, reps, xs):
+        rr, _, _ = oracle_relres(n, delta, c, b, x, ndl.NDL_F32C, dim=3, R=4)
+        assert rr <= 1.05e-8, rr
+
+
+def test_cg_rejects_case_a():
+    import torch
+    n = 16
+    d = torch.full((n, n), 3.0 / n, device="cuda")
+    c = torch.ones((n, n), device="cuda")
+    plan = ndl.ndl_plan_create(ndl.make_problem(2, n, 4, d, c, prec=ndl.NDL_F32C), keep=(d, c))
+    b = torch.ones((n, n), dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    with pytest.raises(ndl.NdlError) as e:
+        ndl.ndl_cg_solve([plan], [b], [x])
+    assert e.value.code == ndl.NDL_ENOTSPD
+
+
+def test_cg_iteration_cap_reports_noconv():
+    probs = problems([48])
+    rc, reps, xs = run(probs, ndl.NDL_F64, rtol=1e-8, max_iter=5)
+    assert rc == ndl.NDL_ENOCONV
+    assert reps[0].converged == 0 and reps[0].iters <= 5 + 25
