@@ -103,6 +103,69 @@ def bench_apply(prec, fast, steps, warmup):
     return dict(seconds=secs, wall=wall, n_points=n * n, info=info, out=out)
 
 
+def bench_solve(count=64, rtol=1e-8, prec=None):
+    """64 batched case (b) solves on uneven grids {256..1024}^2, m in [2, 8]."""
+    import torch
+    from paper_1905_08375_amd import fields as F
+    from paper_1905_08375_amd import ndl
+    prec = ndl.NDL_F32C if prec is None else prec
+    npt = np.float64 if prec == ndl.NDL_F64 else np.float32
+    sizes = F.solve_sizes(count)
+    plans, bs, xs = [], [], []
+    R = 8
+    for i, n in enumerate(sizes):
+        w = F.solve_instance_2d(n, i)
+        d = torch.from_numpy(w["delta"].astype(npt)).cuda()
+        c = torch.from_numpy(w["coef"].astype(npt)).cuda()
+        plans.append(ndl.ndl_plan_create(ndl.make_problem(2, n, R, d, c, form=ndl.NDL_DIV, prec=prec), keep=(d, c)))
+        bs.append(torch.from_numpy(w["b"]).cuda())
+        xs.append(torch.zeros((n, n), dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, reps = ndl.ndl_cg_solve(plans, bs, xs, rtol=rtol)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    pts = sum(n * n for n in sizes)
+    return {"seconds_to_1e-8": el, "problems": count, "points": pts, "rc": rc,
+            "max_rel_res_fp64": max(r.rel_res_fp64 for r in reps), "all_converged": all(r.converged for r in reps),
+            "max_iters": max(r.iters for r in reps), "outer_steps": max(r.outer for r in reps),
+            "precision": "fp32 inner (compensated apply), fp64 reductions and refinement"}
+
+
+def bench_pd(steps=5, batch=8, n=2048):
+    import torch
+    from paper_1905_08375_amd import fields as F
+    from paper_1905_08375_amd import ndl
+    R = 12
+    w = F.peridynamic_2d(n=n, batch=batch, R=R)
+    d = torch.from_numpy(w["delta"].astype(np.float32)).cuda()
+    c = torch.from_numpy(w["coef"].astype(np.float32)).cuda()
+    u = torch.from_numpy(w["u"].astype(np.float32)).cuda()
+    plan = ndl.ndl_plan_create(ndl.make_problem(2, n, R, d, c, model=ndl.NDL_PERIDYNAMIC, kernel=ndl.NDL_G_INV_R,
+                                                prec=ndl.NDL_F32K), keep=(d, c))
+    out = torch.empty((batch, 2, n, n), dtype=torch.float32, device="cuda")
+    secs, _ = timed(lambda: ndl.ndl_apply(plan, u, out, batch), steps, 1)
+    per = secs / steps
+    return {"ms_per_batch_apply": per * 1e3, "gpoint_fields_per_s": batch * n * n / per / 1e9,
+            "pairs_per_point": plan.info().pairs_per_point}
+
+
+def bench_1d(steps=200):
+    import torch
+    from paper_1905_08375_amd import fields as F
+    from paper_1905_08375_amd import ndl
+    d1 = F.diffusion_1d()
+    n, R = 4096, 41
+    dd = torch.from_numpy(d1["delta"]).cuda()
+    cc = torch.from_numpy(d1["coef"]).cuda()
+    u = torch.from_numpy(F.pad(d1["u"], R)).cuda()
+    plan = ndl.ndl_plan_create(ndl.make_problem(1, n, R, dd, cc, kernel=ndl.NDL_G_CONST,
+                                                norm=ndl.NDL_NORM_CONTINUOUS, prec=ndl.NDL_F64), keep=(dd, cc))
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    secs, _ = timed(lambda: ndl.ndl_apply(plan, u, out, 1), steps, 10)
+    return {"us_per_apply": secs / steps * 1e6, "note": "4096 nodes: launch-latency bound"}
+
+
 def cpu_baseline(budget_s=12.0):
     """The FP64 oracle on the same workload (FP32-rounded inputs), on the host cores."""
     import oracle as O
@@ -170,6 +233,12 @@ def main():
             log("row:", nm)
             r = bench_apply(prec, True, k, 20)
             rows[nm] = {"gpoint_per_s": N * k / r["seconds"] / 1e9, "us_per_apply": r["seconds"] / k * 1e6}
+        log("row: 1D 4096 direct FP64")
+        rows["direct_1d_4096_f64"] = bench_1d()
+        log("row: peridynamics 2048^2 x 8 fields")
+        rows["pd_2048x8_f32k"] = bench_pd()
+        log("row: 64 batched solves to 1e-8")
+        rows["cg_64_uneven_to_1e-8"] = bench_solve()
     cpu = None if args.no_cpu else cpu_baseline()
     line = {
         "metric": "Gpoint-applies/s of L_delta (2D var. horizon); PCG time to 1e-8: learned vs plain",
