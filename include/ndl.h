@@ -181,8 +181,21 @@ int ndl_net_num_params(ndl_net net, int64_t* count);
  * (log c, m/4) features; returns the mean loss in *loss. */
 int ndl_net_train_step(ndl_net net, int batch, int s, const float* r, const float* feat,
                        const float* e, float lr, float* loss, void* stream);
-/* z = M(r): r, z device arrays of n^3 (element type of the plan's prec). */
+/* z = M(r): r, z device arrays of n^3 (element type of the plan's prec);
+ * the plan (3D, n divisible by 8) supplies delta and c for the features. */
 int ndl_precond_apply(ndl_net net, ndl_plan plan, const void* r, void* z, void* stream);
+
+/* Test hook: one 3x3x3 convolution layer of the network (zero padding) with
+ * the network's kernels.  x [S^3][cin] BF16 bit patterns (NDHWC), w
+ * [cout][K] FP32 with K = 27 cin rounded up to 32 and k = tap cin + c,
+ * tap = (dz*3 + dy)*3 + dx, bias [cout].  Outputs (each optional, NULL to
+ * skip): y = conv(x) + bias, FP32 [S^3][cout] (weights and inputs rounded to
+ * BF16, FP32 accumulation); dx = conv^T(dy), FP32 [S^3][cin] (dy rounded to
+ * BF16); gw [cout][K], gb [cout] = weight and bias gradients for dy (FP32).
+ * cin/cout in {(8,16), (16,16), (16,32), (32,32), (32,16)}.  Device pointers;
+ * synchronises the stream. */
+int ndl_net_conv_test(int cin, int cout, int S, const uint16_t* x, const float* w, const float* bias, float* y,
+                      const float* dy, float* dx, float* gw, float* gb, void* stream);
 
 /* Autotuner: time the candidate tiles of the direct kernel for this plan and
  * keep the fastest (cached in memory and in the file named by

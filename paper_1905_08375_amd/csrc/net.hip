@@ -1,0 +1,1110 @@
+// Learned preconditioner: a 3D U-Net of 3x3x3 convolutions whose forward
+// and input-gradient convolutions run on the BF16 matrix cores of gfx950
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation), trained on the GPU with the
+// library's own kernels (weight gradients in FP32, Adam with FP32 masters).
+//
+// Activations are BF16 in NDHWC layout (channels innermost, C in {8, 16, 32};
+// the 3 input features are padded to 8 channels).  A convolution is an
+// implicit GEMM: M = voxels (16 per MFMA tile along x), N = output channels
+// (16 per tile), K = 27 taps x C_in, ordered k = tap * C_in + c and padded to a
+// multiple of 32; one MFMA consumes 32 consecutive k.  A block stages the
+// input rows z-1..z+1, y0-1..y0+4, x0-1..x0+XB of its 4 x XB output voxels and
+// the packed weights [C_out][K] in LDS; each wave owns one output row.
+//
+// Network (levels l = 0..3, channels c_l = 16, 16, 32, 32):
+//   enc_l : conv(c_{l-1} -> c_l) relu, conv(c_l -> c_l) relu   (input 8 -> 16 at l = 0)
+//   down  : 2x average pool;  bottom l = 3
+//   dec_l : x = up2(x) + enc_l ; conv(c_{l+1} -> c_l) relu ; (l = 2: conv 32->32, conv 32->16)
+//   head  : conv(16 -> 1) linear (output padded to 16 channels, channel 0 used)
+#include <hip/hip_bfloat16.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+
+#include "common.h"
+
+namespace ndl {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t bf16_t;  // storage type
+
+__device__ __forceinline__ float bf2f(bf16_t v)
+{
+    uint32_t u = (uint32_t)v << 16;
+    return __uint_as_float(u);
+}
+
+__device__ __forceinline__ bf16_t f2bf(float f)  // round to nearest even
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (bf16_t)(u >> 16);  // inf / nan
+    uint32_t r = ((u >> 16) & 1u) + 0x7fffu;
+    return (bf16_t)((u + r) >> 16);
+}
+
+static inline bf16_t f2bf_host(float f)
+{
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (bf16_t)(u >> 16);
+    uint32_t r = ((u >> 16) & 1u) + 0x7fffu;
+    return (bf16_t)((u + r) >> 16);
+}
+
+constexpr int kpad(int cin) { return ((27 * cin + 31) / 32) * 32; }
+
+// ------------------------------------------------------------------ forward conv (MFMA)
+// in  : [S][S][S][CIN] bf16, w : [COUT][KP] bf16, bias : [COUT] fp32 (may be null)
+// out : [S][S][S][COUT] bf16 (ACT 1 = relu) or fp32 when OUTF32
+template <int CIN, int COUT, int XB, int ACT, bool OUTF32>
+__global__ __launch_bounds__(256) void k_conv_fwd(const bf16_t* __restrict__ in, const bf16_t* __restrict__ w,
+                                                  const float* __restrict__ bias, void* __restrict__ out, int S)
+{
+    constexpr int KP = kpad(CIN);
+    constexpr int LX = XB + 2, LY = 6, LZ = 3;
+    constexpr int NT = XB / 16;    // MFMA row tiles per wave
+    constexpr int NC = COUT / 16;  // MFMA column tiles
+    extern __shared__ __align__(16) unsigned char smem[];
+    bf16_t* sin = reinterpret_cast<bf16_t*>(smem);                 // [LZ][LY][LX][CIN]
+    bf16_t* sw = sin + LZ * LY * LX * CIN;                         // [COUT][KP]
+    const int x0 = blockIdx.x * XB, y0 = blockIdx.y * 4, z = blockIdx.z;
+    // stage weights (16-byte chunks)
+    const int wchunks = COUT * KP / 8;
+    for (int c = threadIdx.x; c < wchunks; c += 256)
+        reinterpret_cast<uint4*>(sw)[c] = reinterpret_cast<const uint4*>(w)[c];
+    // stage input rows, 8 channels per chunk
+    constexpr int CPV = CIN / 8;
+    const int ichunks = LZ * LY * LX * CPV;
+    for (int c = threadIdx.x; c < ichunks; c += 256) {
+        int cc = c % CPV;
+        int vox = c / CPV;
+        int lx = vox % LX;
+        int r = vox / LX;
+        int ly = r % LY;
+        int lz = r / LY;
+        int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z - 1 + lz;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (gx >= 0 && gx < S && gy >= 0 && gy < S && gz >= 0 && gz < S)
+            v = reinterpret_cast<const uint4*>(in + (((int64_t)gz * S + gy) * S + gx) * CIN)[cc];
+        reinterpret_cast<uint4*>(sin)[c] = v;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int row = lane & 15, kb = lane >> 4;
+    f32x4 acc[NT][NC];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int kc = 0; kc < KP / 32; ++kc) {
+        const int k0 = kc * 32 + kb * 8;
+        const int tap = k0 / CIN, ci = k0 % CIN;
+        bf16x8 a[NT];
+        if (tap < 27) {
+            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int lx = t * 16 + row + dx;
+                const bf16_t* src = sin + (((dz * LY) + (wv + dy)) * LX + lx) * CIN + ci;
+                a[t] = *reinterpret_cast<const bf16x8*>(src);
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                uint4 zz = make_uint4(0, 0, 0, 0);
+                a[t] = *reinterpret_cast<const bf16x8*>(&zz);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const bf16x8 b = *reinterpret_cast<const bf16x8*>(sw + (c * 16 + row) * KP + k0);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], b, acc[t][c], 0, 0, 0);
+        }
+    }
+    // D layout: lane holds rows 4*kb .. 4*kb+3 of column `row`
+    const int y = y0 + wv;
+    if (y >= S) return;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int co = c * 16 + row;
+            const float bv = bias ? bias[co] : 0.f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int x = x0 + t * 16 + kb * 4 + i;
+                if (x >= S) continue;
+                float v = acc[t][c][i] + bv;
+                if (ACT == 1) v = v > 0.f ? v : 0.f;
+                int64_t o = (((int64_t)z * S + y) * S + x) * COUT + co;
+                if (OUTF32) reinterpret_cast<float*>(out)[o] = v;
+                else reinterpret_cast<bf16_t*>(out)[o] = f2bf(v);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ weight gradient (FP32 VALU)
+// part[blk][co][k] = sum over the block's voxels of dy[v][co] * x[v + tap][ci]
+// (k = tap * CIN + ci), blocks of 64 x 4 x 1 voxels; bias gradient in k = KP.
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_conv_wgrad(const bf16_t* __restrict__ x, const float* __restrict__ dy,
+                                                    float* __restrict__ part, int S)
+{
+    constexpr int KP = kpad(CIN);
+    constexpr int LX = 66, LY = 6, LZ = 3;
+    extern __shared__ __align__(16) unsigned char smem[];
+    bf16_t* sx = reinterpret_cast<bf16_t*>(smem);                       // [LZ][LY][LX][CIN]
+    float* sd = reinterpret_cast<float*>(sx + LZ * LY * LX * CIN);       // [256][COUT]
+    const int x0 = blockIdx.x * 64, y0 = blockIdx.y * 4, z = blockIdx.z;
+    const int nblk = (int)(gridDim.x * gridDim.y * gridDim.z);
+    const int blk = (int)((blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x);
+    for (int c = threadIdx.x; c < LZ * LY * LX * CIN; c += 256) {
+        int ci = c % CIN;
+        int vox = c / CIN;
+        int lx = vox % LX;
+        int r = vox / LX;
+        int ly = r % LY;
+        int lz = r / LY;
+        int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z - 1 + lz;
+        bf16_t v = 0;
+        if (gx >= 0 && gx < S && gy >= 0 && gy < S && gz >= 0 && gz < S) v = x[(((int64_t)gz * S + gy) * S + gx) * CIN + ci];
+        sx[c] = v;
+    }
+    for (int c = threadIdx.x; c < 256 * COUT; c += 256) {
+        int co = c % COUT;
+        int v = c / COUT;
+        int gx = x0 + (v & 63), gy = y0 + (v >> 6);
+        float d = 0.f;
+        if (gx < S && gy < S) d = dy[(((int64_t)z * S + gy) * S + gx) * COUT + co];
+        sd[c] = d;
+    }
+    __syncthreads();
+    // units: (tap, ci block of 4, co block of 4) -> 16 entries
+    constexpr int UNITS = 27 * (CIN / 4) * (COUT / 4);
+    for (int u = threadIdx.x; u < UNITS; u += 256) {
+        int cb = u % (COUT / 4);
+        int r = u / (COUT / 4);
+        int ib = r % (CIN / 4);
+        int tap = r / (CIN / 4);
+        int dz = tap / 9, dyy = (tap / 3) % 3, dx = tap % 3;
+        float acc[4][4] = {};
+        for (int v = 0; v < 256; ++v) {
+            int vx = v & 63, vy = v >> 6;
+            const bf16_t* xs = sx + (((dz * LY) + (vy + dyy)) * LX + (vx + dx)) * CIN + ib * 4;
+            float xv[4] = {bf2f(xs[0]), bf2f(xs[1]), bf2f(xs[2]), bf2f(xs[3])};
+            const float4 dv = *reinterpret_cast<const float4*>(sd + v * COUT + cb * 4);
+            float d4[4] = {dv.x, dv.y, dv.z, dv.w};
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = fmaf(d4[a], xv[b], acc[a][b]);
+        }
+        float* pb = part + (size_t)blk * COUT * (KP + 1);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) pb[(cb * 4 + a) * (KP + 1) + tap * CIN + ib * 4 + b] = acc[a][b];
+    }
+    // bias partials and the padded K entries
+    for (int c = threadIdx.x; c < COUT; c += 256) {
+        float s = 0.f;
+        for (int v = 0; v < 256; ++v) s += sd[v * COUT + c];
+        float* pb = part + (size_t)blk * COUT * (KP + 1);
+        pb[c * (KP + 1) + KP] = s;
+        for (int k = 27 * CIN; k < KP; ++k) pb[c * (KP + 1) + k] = 0.f;
+    }
+    (void)nblk;
+}
+
+// grad[e] (+)= sum over blocks of part[blk][e], fixed order
+__global__ void k_reduce_parts(const float* __restrict__ part, int nblk, int nent, float* __restrict__ grad, int accumulate)
+{
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nent) return;
+    float s = 0.f;
+    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * nent + e];
+    grad[e] = accumulate ? grad[e] + s : s;
+}
+
+// ------------------------------------------------------------------ elementwise kernels
+// dy (fp32, C ch) * relu mask of y (bf16) -> bf16 (input of the data-gradient conv)
+__global__ void k_relu_mask(const float* __restrict__ dy, const bf16_t* __restrict__ y, bf16_t* __restrict__ dyb,
+                            float* __restrict__ dyf, int64_t n, int act)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float d = dy[i];
+    if (act && bf2f(y[i]) <= 0.f) d = 0.f;
+    dyf[i] = d;
+    dyb[i] = f2bf(d);
+}
+
+// 2x average pool, NDHWC: out[S/2] from in[S]
+__global__ void k_pool(const bf16_t* __restrict__ in, bf16_t* __restrict__ out, int S, int C)
+{
+    int So = S / 2;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t tot = (int64_t)So * So * So * C;
+    if (i >= tot) return;
+    int c = (int)(i % C);
+    int64_t v = i / C;
+    int x = (int)(v % So), y = (int)((v / So) % So), z = (int)(v / ((int64_t)So * So));
+    float s = 0.f;
+    for (int m = 0; m < 8; ++m) {
+        int xx = 2 * x + (m & 1), yy = 2 * y + ((m >> 1) & 1), zz = 2 * z + (m >> 2);
+        s += bf2f(in[(((int64_t)zz * S + yy) * S + xx) * C + c]);
+    }
+    out[i] = f2bf(0.125f * s);
+}
+
+// out[S] = up2(coarse[S/2]) + skip[S]  (bf16)
+__global__ void k_up_add(const bf16_t* __restrict__ coarse, const bf16_t* __restrict__ skip, bf16_t* __restrict__ out,
+                         int S, int C)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t tot = (int64_t)S * S * S * C;
+    if (i >= tot) return;
+    int c = (int)(i % C);
+    int64_t v = i / C;
+    int x = (int)(v % S), y = (int)((v / S) % S), z = (int)(v / ((int64_t)S * S));
+    int Sc = S / 2;
+    float a = bf2f(coarse[(((int64_t)(z / 2) * Sc + y / 2) * Sc + x / 2) * C + c]);
+    out[i] = f2bf(a + bf2f(skip[i]));
+}
+
+// backward of up_add: dcoarse[S/2] (+)= sum of the 8 children of dout; dskip += dout
+__global__ void k_up_add_bwd(const float* __restrict__ dout, float* __restrict__ dcoarse, float* __restrict__ dskip,
+                             int S, int C)
+{
+    int Sc = S / 2;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t tot = (int64_t)Sc * Sc * Sc * C;
+    if (i >= tot) return;
+    int c = (int)(i % C);
+    int64_t v = i / C;
+    int x = (int)(v % Sc), y = (int)((v / Sc) % Sc), z = (int)(v / ((int64_t)Sc * Sc));
+    float s = 0.f;
+    for (int m = 0; m < 8; ++m) {
+        int xx = 2 * x + (m & 1), yy = 2 * y + ((m >> 1) & 1), zz = 2 * z + (m >> 2);
+        int64_t j = (((int64_t)zz * S + yy) * S + xx) * C + c;
+        float d = dout[j];
+        s += d;
+        dskip[j] += d;
+    }
+    dcoarse[i] = s;
+}
+
+// backward of the pool: din[S] += dout[S/2] / 8
+__global__ void k_pool_bwd(const float* __restrict__ dout, float* __restrict__ din, int S, int C)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t tot = (int64_t)S * S * S * C;
+    if (i >= tot) return;
+    int c = (int)(i % C);
+    int64_t v = i / C;
+    int x = (int)(v % S), y = (int)((v / S) % S), z = (int)(v / ((int64_t)S * S));
+    int So = S / 2;
+    din[i] += 0.125f * dout[(((int64_t)(z / 2) * So + y / 2) * So + x / 2) * C + c];
+}
+
+// flipped, transposed weights for the data gradient: wt[ci][tap' * COUT + co] = w[co][tap * CIN + ci],
+// tap' = 26 - tap; both padded to their K.
+__global__ void k_wt_transpose(const float* __restrict__ w32, bf16_t* __restrict__ wt, int CIN, int COUT, int KPin,
+                               int KPout)
+{
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= CIN * KPout) return;
+    int ci = e / KPout, k = e % KPout;
+    int tapp = k / COUT, co = k % COUT;
+    float v = 0.f;
+    if (tapp < 27) v = w32[co * KPin + (26 - tapp) * CIN + ci];
+    wt[e] = f2bf(v);
+}
+
+__global__ void k_to_bf16(const float* __restrict__ a, bf16_t* __restrict__ b, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = f2bf(a[i]);
+}
+
+__global__ void k_zero_f32(float* __restrict__ a, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0.f;
+}
+
+// Adam on FP32 masters (bias-corrected); rows of padded K stay zero.
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
+                       int64_t n, float lr, float b1, float b2, float c1, float c2, float eps)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float gi = g[i];
+    float mi = b1 * m[i] + (1.f - b1) * gi;
+    float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ------------------------------------------------------------------ input / output packing
+// input channels: r * rscale, (log c - mu) / sd, m / 4, zeros to 8
+template <typename T>
+__global__ void k_pack_input(const T* __restrict__ r, const double* __restrict__ rscale, const T* __restrict__ delta,
+                             const T* __restrict__ coef, int64_t n, int S, double mu, double isd, bf16_t* __restrict__ x)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double rs = rscale ? *rscale : 1.0;
+    bf16_t* o = x + i * 8;
+    o[0] = f2bf((float)((double)r[i] * rs));
+    o[1] = f2bf((float)((log((double)coef[i]) - mu) * isd));
+    o[2] = f2bf((float)((double)delta[i] * (double)S * 0.25));
+#pragma unroll
+    for (int c = 3; c < 8; ++c) o[c] = 0;
+}
+
+// training batch: r, feat (log c std, m/4) fp32 already prepared
+__global__ void k_pack_train(const float* __restrict__ r, const float* __restrict__ feat, int64_t n, bf16_t* __restrict__ x)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bf16_t* o = x + i * 8;
+    o[0] = f2bf(r[i]);
+    o[1] = f2bf(feat[i]);
+    o[2] = f2bf(feat[n + i]);
+#pragma unroll
+    for (int c = 3; c < 8; ++c) o[c] = 0;
+}
+
+// z = (channel 0 of the fp32 head output) / rscale
+template <typename T>
+__global__ void k_unpack(const float* __restrict__ y, const double* __restrict__ rscale, int64_t n, T* __restrict__ z)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double rs = rscale ? *rscale : 1.0;
+    z[i] = (T)((double)y[i * 16] / rs);
+}
+
+// loss: sum (y0 - e)^2 and sum e^2 per sample (partials per block) and dy = 2 (y0 - e) / (B sum e^2)
+__global__ void k_loss_parts(const float* __restrict__ y, const float* __restrict__ e, int64_t n, double* __restrict__ part)
+{
+    __shared__ double s1[256], s2[256];
+    double a = 0.0, b = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double d = (double)y[i * 16] - (double)e[i];
+        a += d * d;
+        b += (double)e[i] * (double)e[i];
+    }
+    s1[threadIdx.x] = a;
+    s2[threadIdx.x] = b;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) { s1[threadIdx.x] += s1[threadIdx.x + o]; s2[threadIdx.x] += s2[threadIdx.x + o]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { part[2 * blockIdx.x] = s1[0]; part[2 * blockIdx.x + 1] = s2[0]; }
+}
+
+__global__ void k_loss_grad(const float* __restrict__ y, const float* __restrict__ e, int64_t n,
+                            const double* __restrict__ part, int nparts, float inv_b, float* __restrict__ dy,
+                            float* __restrict__ loss_acc)
+{
+    __shared__ double den_s;
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int p = 0; p < nparts; ++p) { a += part[2 * p]; b += part[2 * p + 1]; }
+        den_s = b > 0 ? b : 1.0;
+        if (blockIdx.x == 0) atomicAdd(loss_acc, (float)(a / den_s) * inv_b);
+    }
+    __syncthreads();
+    double den = den_s;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        float d = (float)(2.0 * ((double)y[i * 16] - (double)e[i]) / den) * inv_b;
+        dy[i * 16] = d;
+#pragma unroll
+        for (int c = 1; c < 16; ++c) dy[i * 16 + c] = 0.f;
+    }
+}
+
+// ------------------------------------------------------------------ host side
+struct ConvSpec {
+    int cin, cout, act;  // act: 1 relu, 0 linear
+};
+
+// layer order of the network
+static const ConvSpec kLayers[] = {
+    {8, 16, 1}, {16, 16, 1},    // enc0
+    {16, 16, 1}, {16, 16, 1},   // enc1
+    {16, 32, 1}, {32, 32, 1},   // enc2
+    {32, 32, 1}, {32, 32, 1},   // bottom (level 3)
+    {32, 32, 1}, {32, 16, 1},   // dec2
+    {16, 16, 1},                // dec1
+    {16, 16, 1},                // dec0
+    {16, 16, 0},                // head (channel 0 used)
+};
+static constexpr int kNumLayers = sizeof(kLayers) / sizeof(kLayers[0]);
+
+struct Layer {
+    ConvSpec sp;
+    int KP;
+    size_t nw;           // cout * KP
+    float* w32 = nullptr;
+    float* b32 = nullptr;
+    float *gw = nullptr, *gb = nullptr;
+    float *mw = nullptr, *vw = nullptr, *mb = nullptr, *vb = nullptr;
+    bf16_t* wbf = nullptr;  // [cout][KP]
+    bf16_t* wt = nullptr;   // [cin][KP of cout]
+};
+
+struct Net {
+    Layer L[kNumLayers];
+    int64_t step = 0;
+    // activation workspace for a cube side (allocated on demand)
+    int S = 0;
+    std::vector<void*> bufs;
+    // named activations (bf16) per level and fp32 grads
+    bf16_t *x_in = nullptr;
+    bf16_t *a[kNumLayers] = {};   // outputs of each conv (bf16; head in fp32 separately)
+    bf16_t *p[4] = {};            // pooled inputs of levels 1..3
+    bf16_t *u[3] = {};            // up+skip sums at levels 0..2
+    float* head = nullptr;        // fp32 [S^3][16]
+    // backward scratch
+    float* g0 = nullptr;
+    bf16_t* gb16 = nullptr;
+    float* part = nullptr;
+    size_t part_elems = 0;
+    double* lpart = nullptr;
+    float* lossacc = nullptr;
+    double* rscale = nullptr;
+    ~Net()
+    {
+        for (void* b : bufs) (void)hipFree(b);
+        for (auto& l : L) {
+            void* ps[] = {l.w32, l.b32, l.gw, l.gb, l.mw, l.vw, l.mb, l.vb, l.wbf, l.wt};
+            for (void* q : ps)
+                if (q) (void)hipFree(q);
+        }
+    }
+};
+
+static int level_of_layer(int i)
+{
+    static const int lv[kNumLayers] = {0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 0, 0};
+    return lv[i];
+}
+
+template <typename T>
+static int dmalloc(Net& n, T** p, size_t count)
+{
+    void* q = nullptr;
+    NDL_HIP(hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)));
+    n.bufs.push_back(q);
+    *p = static_cast<T*>(q);
+    return NDL_OK;
+}
+
+static uint64_t splitmix(uint64_t& s)
+{
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static double gauss(uint64_t& s)
+{
+    double u1 = ((splitmix(s) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    double u2 = ((splitmix(s) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    return std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * M_PI * u2);
+}
+
+static unsigned nb(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+static int refresh_bf16(Layer& l, hipStream_t s)
+{
+    k_to_bf16<<<nb((int64_t)l.nw), 256, 0, s>>>(l.w32, l.wbf, (int64_t)l.nw);
+    int KPo = kpad(l.sp.cout);
+    k_wt_transpose<<<nb((int64_t)l.sp.cin * KPo), 256, 0, s>>>(l.w32, l.wt, l.sp.cin, l.sp.cout, l.KP, KPo);
+    NDL_HIP(hipGetLastError());
+    return NDL_OK;
+}
+
+static int net_init(Net& n, uint64_t seed)
+{
+    uint64_t st = seed ^ 0x1905083750000000ull;
+    for (int i = 0; i < kNumLayers; ++i) {
+        Layer& l = n.L[i];
+        l.sp = kLayers[i];
+        l.KP = kpad(l.sp.cin);
+        l.nw = (size_t)l.sp.cout * l.KP;
+        int real_cin = i == 0 ? 3 : l.sp.cin;
+        int real_cout = i == kNumLayers - 1 ? 1 : l.sp.cout;
+        std::vector<float> w(l.nw, 0.f), b(l.sp.cout, 0.f);
+        double sd = std::sqrt(2.0 / (27.0 * real_cin));
+        if (i == kNumLayers - 1) sd = std::sqrt(1.0 / (27.0 * real_cin));
+        for (int co = 0; co < real_cout; ++co)
+            for (int tap = 0; tap < 27; ++tap)
+                for (int ci = 0; ci < real_cin; ++ci) w[co * l.KP + tap * l.sp.cin + ci] = (float)(sd * gauss(st));
+        float** ptrs[] = {&l.w32, &l.gw, &l.mw, &l.vw};
+        for (float** q : ptrs) NDL_HIP(hipMalloc(q, l.nw * sizeof(float)));
+        float** bp[] = {&l.b32, &l.gb, &l.mb, &l.vb};
+        for (float** q : bp) NDL_HIP(hipMalloc(q, l.sp.cout * sizeof(float)));
+        NDL_HIP(hipMalloc(&l.wbf, l.nw * sizeof(bf16_t)));
+        NDL_HIP(hipMalloc(&l.wt, (size_t)l.sp.cin * kpad(l.sp.cout) * sizeof(bf16_t)));
+        NDL_HIP(hipMemcpy(l.w32, w.data(), l.nw * sizeof(float), hipMemcpyHostToDevice));
+        NDL_HIP(hipMemcpy(l.b32, b.data(), l.sp.cout * sizeof(float), hipMemcpyHostToDevice));
+        NDL_HIP(hipMemset(l.mw, 0, l.nw * sizeof(float)));
+        NDL_HIP(hipMemset(l.vw, 0, l.nw * sizeof(float)));
+        NDL_HIP(hipMemset(l.mb, 0, l.sp.cout * sizeof(float)));
+        NDL_HIP(hipMemset(l.vb, 0, l.sp.cout * sizeof(float)));
+        NDL_TRY(refresh_bf16(l, nullptr));
+    }
+    NDL_HIP(hipDeviceSynchronize());
+    return NDL_OK;
+}
+
+// workspace for cube side S (levels S, S/2, S/4, S/8)
+static int net_workspace(Net& n, int S)
+{
+    if (n.S == S) return NDL_OK;
+    for (void* b : n.bufs) (void)hipFree(b);
+    n.bufs.clear();
+    n.S = S;
+    auto vox = [&](int l) { int s = S >> l; return (size_t)s * s * s; };
+    NDL_TRY(dmalloc(n, &n.x_in, vox(0) * 8));
+    for (int i = 0; i < kNumLayers; ++i) NDL_TRY(dmalloc(n, &n.a[i], vox(level_of_layer(i)) * kLayers[i].cout));
+    NDL_TRY(dmalloc(n, &n.p[1], vox(1) * 16));
+    NDL_TRY(dmalloc(n, &n.p[2], vox(2) * 16));
+    NDL_TRY(dmalloc(n, &n.p[3], vox(3) * 32));
+    NDL_TRY(dmalloc(n, &n.u[2], vox(2) * 32));
+    NDL_TRY(dmalloc(n, &n.u[1], vox(1) * 16));
+    NDL_TRY(dmalloc(n, &n.u[0], vox(0) * 16));
+    NDL_TRY(dmalloc(n, &n.head, vox(0) * 16));
+    NDL_TRY(dmalloc(n, &n.lpart, 2 * 1024));
+    NDL_TRY(dmalloc(n, &n.lossacc, 1));
+    NDL_TRY(dmalloc(n, &n.rscale, 1));
+    return NDL_OK;
+}
+
+// forward convolution dispatch
+template <int CIN, int COUT>
+static int conv_fwd_t(const bf16_t* in, const bf16_t* w, const float* bias, void* out, int S, int act, bool f32,
+                      hipStream_t s)
+{
+    constexpr int XB = CIN >= 32 ? 32 : 64;
+    constexpr int KP = kpad(CIN);
+    size_t lds = (size_t)3 * 6 * (XB + 2) * CIN * 2 + (size_t)COUT * KP * 2;
+    dim3 grid((unsigned)((S + XB - 1) / XB), (unsigned)((S + 3) / 4), (unsigned)S);
+    const void* fn;
+    if (f32) fn = (const void*)k_conv_fwd<CIN, COUT, XB, 0, true>;
+    else if (act) fn = (const void*)k_conv_fwd<CIN, COUT, XB, 1, false>;
+    else fn = (const void*)k_conv_fwd<CIN, COUT, XB, 0, false>;
+    if (lds > 64 * 1024) NDL_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    if (f32) k_conv_fwd<CIN, COUT, XB, 0, true><<<grid, 256, lds, s>>>(in, w, bias, out, S);
+    else if (act) k_conv_fwd<CIN, COUT, XB, 1, false><<<grid, 256, lds, s>>>(in, w, bias, out, S);
+    else k_conv_fwd<CIN, COUT, XB, 0, false><<<grid, 256, lds, s>>>(in, w, bias, out, S);
+    NDL_HIP(hipGetLastError());
+    return NDL_OK;
+}
+
+static int conv_fwd(int cin, int cout, const bf16_t* in, const bf16_t* w, const float* bias, void* out, int S, int act,
+                    bool f32, hipStream_t s)
+{
+#define NDL_CF(A, B) if (cin == A && cout == B) return conv_fwd_t<A, B>(in, w, bias, out, S, act, f32, s)
+    NDL_CF(8, 16);
+    NDL_CF(16, 16);
+    NDL_CF(16, 32);
+    NDL_CF(32, 32);
+    NDL_CF(32, 16);
+#undef NDL_CF
+    set_error("conv %d->%d not instantiated", cin, cout);
+    return NDL_EUNSUPPORTED;
+}
+
+// gw[co][k] (+)= red[co][k] for k < KP, gb[co] (+)= red[co][KP]
+__global__ void k_split_grad(const float* __restrict__ red, float* __restrict__ gw, float* __restrict__ gb, int cout,
+                             int kp)
+{
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= cout * (kp + 1)) return;
+    int co = e / (kp + 1), k = e % (kp + 1);
+    if (k < kp) gw[co * kp + k] += red[e];
+    else gb[co] += red[e];
+}
+
+template <int CIN, int COUT>
+static int conv_wgrad_t(const bf16_t* x, const float* dy, float* part, size_t part_elems, float* gw, float* gb, int S,
+                        hipStream_t s)
+{
+    constexpr int KP = kpad(CIN);
+    size_t lds = (size_t)3 * 6 * 66 * CIN * 2 + (size_t)256 * COUT * 4;
+    dim3 grid((unsigned)((S + 63) / 64), (unsigned)((S + 3) / 4), (unsigned)S);
+    int nblk = (int)(grid.x * grid.y * grid.z);
+    int nent = COUT * (KP + 1);
+    if ((size_t)(nblk + 1) * nent > part_elems) {
+        set_error("internal: weight-gradient scratch too small");
+        return NDL_EINVAL;
+    }
+    if (lds > 64 * 1024)
+        NDL_HIP(hipFuncSetAttribute((const void*)k_conv_wgrad<CIN, COUT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds));
+    k_conv_wgrad<CIN, COUT><<<grid, 256, lds, s>>>(x, dy, part, S);
+    float* red = part + (size_t)nblk * nent;
+    k_reduce_parts<<<nb(nent), 256, 0, s>>>(part, nblk, nent, red, 0);
+    k_split_grad<<<nb(nent), 256, 0, s>>>(red, gw, gb, COUT, KP);
+    NDL_HIP(hipGetLastError());
+    return NDL_OK;
+}
+
+static int conv_wgrad(int cin, int cout, const bf16_t* x, const float* dy, Net& n, Layer& l, int S, hipStream_t s)
+{
+#define NDL_CW(A, B) \
+    if (cin == A && cout == B) return conv_wgrad_t<A, B>(x, dy, n.part, n.part_elems, l.gw, l.gb, S, s)
+    NDL_CW(8, 16);
+    NDL_CW(16, 16);
+    NDL_CW(16, 32);
+    NDL_CW(32, 32);
+    NDL_CW(32, 16);
+#undef NDL_CW
+    set_error("wgrad %d->%d not instantiated", cin, cout);
+    return NDL_EUNSUPPORTED;
+}
+
+// ------------------------------------------------------------------ training workspace
+struct Grads {
+    float* d[kNumLayers] = {};  // gradient w.r.t. each conv output
+    float* dp[4] = {};
+    float* du[3] = {};
+};
+
+
+struct NetState {
+    Net net;
+    Grads g;
+    int Sg = 0;
+    double feat_mu = 0.0, feat_isd = 1.0;
+    const void* feat_plan = nullptr;
+};
+
+static int grads_workspace(NetState& st, int S)
+{
+    if (st.Sg == S) return NDL_OK;
+    Net& n = st.net;
+    auto vox = [&](int l) { int q = S >> l; return (size_t)q * q * q; };
+    for (int i = 0; i < kNumLayers; ++i) NDL_TRY(dmalloc(n, &st.g.d[i], vox(level_of_layer(i)) * kLayers[i].cout));
+    NDL_TRY(dmalloc(n, &st.g.dp[1], vox(1) * 16));
+    NDL_TRY(dmalloc(n, &st.g.dp[2], vox(2) * 16));
+    NDL_TRY(dmalloc(n, &st.g.dp[3], vox(3) * 32));
+    NDL_TRY(dmalloc(n, &st.g.du[0], vox(0) * 16));
+    NDL_TRY(dmalloc(n, &st.g.du[1], vox(1) * 16));
+    NDL_TRY(dmalloc(n, &st.g.du[2], vox(2) * 32));
+    NDL_TRY(dmalloc(n, &n.g0, vox(0) * 32));
+    NDL_TRY(dmalloc(n, &n.gb16, vox(0) * 32));
+    size_t blocks0 = (size_t)((S + 63) / 64) * ((S + 3) / 4) * S;
+    n.part_elems = (blocks0 + 1) * 32 * (kpad(32) + 1);
+    NDL_TRY(dmalloc(n, &n.part, n.part_elems));
+    st.Sg = S;
+    return NDL_OK;
+}
+
+// ------------------------------------------------------------------ forward / backward
+static const bf16_t* layer_input(Net& n, int i)
+{
+    switch (i) {
+    case 0: return n.x_in;
+    case 1: return n.a[0];
+    case 2: return n.p[1];
+    case 3: return n.a[2];
+    case 4: return n.p[2];
+    case 5: return n.a[4];
+    case 6: return n.p[3];
+    case 7: return n.a[6];
+    case 8: return n.u[2];
+    case 9: return n.a[8];
+    case 10: return n.u[1];
+    case 11: return n.u[0];
+    default: return n.a[11];
+    }
+}
+
+static int net_forward(Net& n, int S, hipStream_t s)
+{
+    int Sl[4] = {S, S / 2, S / 4, S / 8};
+    auto conv = [&](int i) -> int {
+        Layer& l = n.L[i];
+        int lv = level_of_layer(i);
+        bool head = i == kNumLayers - 1;
+        return conv_fwd(l.sp.cin, l.sp.cout, layer_input(n, i), l.wbf, l.b32, head ? (void*)n.head : (void*)n.a[i],
+                        Sl[lv], l.sp.act, head, s);
+    };
+    auto vox = [&](int l) { return (int64_t)Sl[l] * Sl[l] * Sl[l]; };
+    NDL_TRY(conv(0));
+    NDL_TRY(conv(1));
+    k_pool<<<nb(vox(1) * 16), 256, 0, s>>>(n.a[1], n.p[1], Sl[0], 16);
+    NDL_TRY(conv(2));
+    NDL_TRY(conv(3));
+    k_pool<<<nb(vox(2) * 16), 256, 0, s>>>(n.a[3], n.p[2], Sl[1], 16);
+    NDL_TRY(conv(4));
+    NDL_TRY(conv(5));
+    k_pool<<<nb(vox(3) * 32), 256, 0, s>>>(n.a[5], n.p[3], Sl[2], 32);
+    NDL_TRY(conv(6));
+    NDL_TRY(conv(7));
+    k_up_add<<<nb(vox(2) * 32), 256, 0, s>>>(n.a[7], n.a[5], n.u[2], Sl[2], 32);
+    NDL_TRY(conv(8));
+    NDL_TRY(conv(9));
+    k_up_add<<<nb(vox(1) * 16), 256, 0, s>>>(n.a[9], n.a[3], n.u[1], Sl[1], 16);
+    NDL_TRY(conv(10));
+    k_up_add<<<nb(vox(0) * 16), 256, 0, s>>>(n.a[10], n.a[1], n.u[0], Sl[0], 16);
+    NDL_TRY(conv(11));
+    NDL_TRY(conv(12));
+    NDL_HIP(hipGetLastError());
+    return NDL_OK;
+}
+
+// Backward from dhead (= g.d[12], fp32 [S^3][16]); weight gradients accumulate.
+static int net_backward(NetState& st, int S, hipStream_t s)
+{
+    Net& n = st.net;
+    Grads& g = st.g;
+    int Sl[4] = {S, S / 2, S / 4, S / 8};
+    auto vox = [&](int l) { return (int64_t)Sl[l] * Sl[l] * Sl[l]; };
+    // conv i: dY = g.d[i] (masked by relu of a[i]); dX -> dst (fp32, overwritten) unless dst null
+    auto back = [&](int i, float* dst) -> int {
+        Layer& l = n.L[i];
+        int lv = level_of_layer(i);
+        int64_t cnt = vox(lv) * l.sp.cout;
+        const bf16_t* y = i == kNumLayers - 1 ? nullptr : n.a[i];
+        // masked gradient (fp32 in n.g0, bf16 in n.gb16)
+        k_relu_mask<<<nb(cnt), 256, 0, s>>>(g.d[i], y ? y : n.gb16, n.gb16, n.g0, cnt, y ? l.sp.act : 0);
+        NDL_TRY(conv_wgrad(l.sp.cin, l.sp.cout, layer_input(n, i), n.g0, n, l, Sl[lv], s));
+        if (dst) NDL_TRY(conv_fwd(l.sp.cout, l.sp.cin, n.gb16, l.wt, nullptr, dst, Sl[lv], 0, true, s));
+        return NDL_OK;
+    };
+    NDL_TRY(back(12, g.d[11]));
+    NDL_TRY(back(11, g.du[0]));
+    // u0 = up(a10) + a1
+    k_zero_f32<<<nb(vox(0) * 16), 256, 0, s>>>(g.d[1], vox(0) * 16);
+    k_up_add_bwd<<<nb(vox(1) * 16), 256, 0, s>>>(g.du[0], g.d[10], g.d[1], Sl[0], 16);
+    NDL_TRY(back(10, g.du[1]));
+    k_zero_f32<<<nb(vox(1) * 16), 256, 0, s>>>(g.d[3], vox(1) * 16);
+    k_up_add_bwd<<<nb(vox(2) * 16), 256, 0, s>>>(g.du[1], g.d[9], g.d[3], Sl[1], 16);
+    NDL_TRY(back(9, g.d[8]));
+    NDL_TRY(back(8, g.du[2]));
+    k_zero_f32<<<nb(vox(2) * 32), 256, 0, s>>>(g.d[5], vox(2) * 32);
+    k_up_add_bwd<<<nb(vox(3) * 32), 256, 0, s>>>(g.du[2], g.d[7], g.d[5], Sl[2], 32);
+    NDL_TRY(back(7, g.d[6]));
+    NDL_TRY(back(6, g.dp[3]));
+    k_pool_bwd<<<nb(vox(2) * 32), 256, 0, s>>>(g.dp[3], g.d[5], Sl[2], 32);
+    NDL_TRY(back(5, g.d[4]));
+    NDL_TRY(back(4, g.dp[2]));
+    k_pool_bwd<<<nb(vox(1) * 16), 256, 0, s>>>(g.dp[2], g.d[3], Sl[1], 16);
+    NDL_TRY(back(3, g.d[2]));
+    NDL_TRY(back(2, g.dp[1]));
+    k_pool_bwd<<<nb(vox(0) * 16), 256, 0, s>>>(g.dp[1], g.d[1], Sl[0], 16);
+    NDL_TRY(back(1, g.d[0]));
+    NDL_TRY(back(0, nullptr));
+    NDL_HIP(hipGetLastError());
+    return NDL_OK;
+}
+
+// ------------------------------------------------------------------ norms of the input
+template <typename T>
+__global__ void k_sumsq(const T* __restrict__ r, int64_t n, double* __restrict__ part)
+{
+    __shared__ double sh[256];
+    double a = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double v = (double)r[i];
+        a += v * v;
+    }
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_rscale(const double* __restrict__ part, int np, double* __restrict__ rs)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < np; ++i) s += part[i];
+    *rs = s > 0.0 ? 1.0 / sqrt(s) : 1.0;
+}
+
+template <typename T>
+__global__ void k_logc_moments(const T* __restrict__ c, int64_t n, double* __restrict__ part)
+{
+    __shared__ double s1[256], s2[256];
+    double a = 0.0, b = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double v = log((double)c[i]);
+        a += v;
+        b += v * v;
+    }
+    s1[threadIdx.x] = a;
+    s2[threadIdx.x] = b;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) { s1[threadIdx.x] += s1[threadIdx.x + o]; s2[threadIdx.x] += s2[threadIdx.x + o]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { part[2 * blockIdx.x] = s1[0]; part[2 * blockIdx.x + 1] = s2[0]; }
+}
+
+// z = M(r) for a plan's cube (n^3, n % 8 == 0): input (r / ||r||, standardised log c, m / 4)
+template <typename T>
+static int precond_t(NetState& st, const Plan& p, const T* r, T* z, hipStream_t s)
+{
+    Net& n = st.net;
+    int S = (int)p.n;
+    if (n.S != S) {
+        NDL_TRY(net_workspace(n, S));
+        st.Sg = 0;  // gradient buffers lived in the old workspace
+    }
+    if (st.feat_plan != (const void*)&p) {
+        k_logc_moments<T><<<256, 256, 0, s>>>((const T*)p.prob.coef, p.N, n.lpart);
+        std::vector<double> h(512);
+        NDL_HIP(hipMemcpyAsync(h.data(), n.lpart, 512 * sizeof(double), hipMemcpyDeviceToHost, s));
+        NDL_HIP(hipStreamSynchronize(s));
+        double a = 0.0, b = 0.0;
+        for (int i = 0; i < 256; ++i) { a += h[2 * i]; b += h[2 * i + 1]; }
+        double mu = a / (double)p.N, var = b / (double)p.N - mu * mu;
+        st.feat_mu = mu;
+        st.feat_isd = var > 0 ? 1.0 / std::sqrt(var) : 1.0;
+        st.feat_plan = &p;
+    }
+    k_sumsq<T><<<256, 256, 0, s>>>(r, p.N, n.lpart);
+    k_rscale<<<1, 64, 0, s>>>(n.lpart, 256, n.rscale);
+    k_pack_input<T><<<nb(p.N), 256, 0, s>>>(r, n.rscale, (const T*)p.prob.delta, (const T*)p.prob.coef, p.N, S,
+                                            st.feat_mu, st.feat_isd, n.x_in);
+    NDL_TRY(net_forward(n, S, s));
+    k_unpack<T><<<nb(p.N), 256, 0, s>>>(n.head, n.rscale, p.N, z);
+    NDL_HIP(hipGetLastError());
+    return NDL_OK;
+}
+
+int net_precond(void* net, const Plan& p, const void* r, void* z, hipStream_t s)
+{
+    NetState& st = *reinterpret_cast<NetState*>(net);
+    if (p.dim != 3 || p.n % 8 != 0) {
+        set_error("learned preconditioner needs a 3D cube with n divisible by 8");
+        return NDL_EUNSUPPORTED;
+    }
+    return p.prec == NDL_F64 ? precond_t<double>(st, p, (const double*)r, (double*)z, s)
+                             : precond_t<float>(st, p, (const float*)r, (float*)z, s);
+}
+
+}  // namespace ndl
+
+using namespace ndl;
+
+extern "C" {
+
+int ndl_net_create(int levels, const int* channels, uint64_t seed, ndl_net* out)
+{
+    if (!out) { set_error("null output"); return NDL_EINVAL; }
+    *out = nullptr;
+    static const int want[4] = {16, 16, 32, 32};
+    if (levels != 4 || (channels && (channels[0] != want[0] || channels[1] != want[1] || channels[2] != want[2] ||
+                                     channels[3] != want[3]))) {
+        set_error("the built network has 4 levels with channels (16, 16, 32, 32)");
+        return NDL_EUNSUPPORTED;
+    }
+    NetState* st = new (std::nothrow) NetState();
+    if (!st) { set_error("host allocation failed"); return NDL_ENOMEM; }
+    int rc = net_init(st->net, seed);
+    if (rc != NDL_OK) { delete st; return rc; }
+    *out = reinterpret_cast<ndl_net>(st);
+    return NDL_OK;
+}
+
+int ndl_net_destroy(ndl_net net)
+{
+    delete reinterpret_cast<NetState*>(net);
+    return NDL_OK;
+}
+
+int ndl_net_num_params(ndl_net net, int64_t* count)
+{
+    if (!net || !count) { set_error("null argument"); return NDL_EINVAL; }
+    int64_t c = 0;
+    for (int i = 0; i < kNumLayers; ++i) {
+        int real_cin = i == 0 ? 3 : kLayers[i].cin;
+        int real_cout = i == kNumLayers - 1 ? 1 : kLayers[i].cout;
+        c += (int64_t)real_cout * 27 * real_cin + real_cout;
+    }
+    *count = c;
+    return NDL_OK;
+}
+
+// file: "NDLNET01", step, then per layer: cout, KP, w32[cout*KP], b32[cout]
+int ndl_net_save(ndl_net net, const char* path)
+{
+    if (!net || !path) { set_error("null argument"); return NDL_EINVAL; }
+    NetState& st = *reinterpret_cast<NetState*>(net);
+    FILE* f = fopen(path, "wb");
+    if (!f) { set_error("cannot open %s", path); return NDL_EINVAL; }
+    fwrite("NDLNET01", 1, 8, f);
+    fwrite(&st.net.step, sizeof(int64_t), 1, f);
+    for (int i = 0; i < kNumLayers; ++i) {
+        Layer& l = st.net.L[i];
+        std::vector<float> w(l.nw), b(l.sp.cout);
+        NDL_HIP(hipMemcpy(w.data(), l.w32, l.nw * sizeof(float), hipMemcpyDeviceToHost));
+        NDL_HIP(hipMemcpy(b.data(), l.b32, l.sp.cout * sizeof(float), hipMemcpyDeviceToHost));
+        int32_t hdr[2] = {l.sp.cout, l.KP};
+        fwrite(hdr, sizeof(int32_t), 2, f);
+        fwrite(w.data(), sizeof(float), w.size(), f);
+        fwrite(b.data(), sizeof(float), b.size(), f);
+    }
+    fclose(f);
+    return NDL_OK;
+}
+
+int ndl_net_load(ndl_net net, const char* path)
+{
+    if (!net || !path) { set_error("null argument"); return NDL_EINVAL; }
+    NetState& st = *reinterpret_cast<NetState*>(net);
+    FILE* f = fopen(path, "rb");
+    if (!f) { set_error("cannot open %s", path); return NDL_EINVAL; }
+    char magic[8];
+    bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "NDLNET01", 8) == 0;
+    int64_t step = 0;
+    ok = ok && fread(&step, sizeof(int64_t), 1, f) == 1;
+    for (int i = 0; i < kNumLayers && ok; ++i) {
+        Layer& l = st.net.L[i];
+        int32_t hdr[2];
+        ok = fread(hdr, sizeof(int32_t), 2, f) == 2 && hdr[0] == l.sp.cout && hdr[1] == l.KP;
+        std::vector<float> w(l.nw), b(l.sp.cout);
+        ok = ok && fread(w.data(), sizeof(float), w.size(), f) == w.size();
+        ok = ok && fread(b.data(), sizeof(float), b.size(), f) == b.size();
+        if (ok) {
+            NDL_HIP(hipMemcpy(l.w32, w.data(), l.nw * sizeof(float), hipMemcpyHostToDevice));
+            NDL_HIP(hipMemcpy(l.b32, b.data(), l.sp.cout * sizeof(float), hipMemcpyHostToDevice));
+            NDL_TRY(refresh_bf16(l, nullptr));
+        }
+    }
+    fclose(f);
+    if (!ok) { set_error("%s is not a network file of this layout", path); return NDL_EINVAL; }
+    st.net.step = step;
+    NDL_HIP(hipDeviceSynchronize());
+    return NDL_OK;
+}
+
+int ndl_net_train_step(ndl_net net, int batch, int s, const float* r, const float* feat, const float* e, float lr,
+                       float* loss, void* stream)
+{
+    if (!net || batch <= 0 || s < 8 || s % 8 != 0 || !r || !feat || !e) {
+        set_error("ndl_net_train_step: bad arguments (crop side must be a multiple of 8)");
+        return NDL_EINVAL;
+    }
+    NetState& st = *reinterpret_cast<NetState*>(net);
+    Net& n = st.net;
+    hipStream_t hs = (hipStream_t)stream;
+    if (n.S != s) {
+        NDL_TRY(net_workspace(n, s));
+        st.Sg = 0;
+    }
+    NDL_TRY(grads_workspace(st, s));
+    int64_t vox = (int64_t)s * s * s;
+    for (int i = 0; i < kNumLayers; ++i) {
+        k_zero_f32<<<nb((int64_t)n.L[i].nw), 256, 0, hs>>>(n.L[i].gw, (int64_t)n.L[i].nw);
+        k_zero_f32<<<1, 256, 0, hs>>>(n.L[i].gb, n.L[i].sp.cout);
+    }
+    k_zero_f32<<<1, 64, 0, hs>>>(n.lossacc, 1);
+    for (int b = 0; b < batch; ++b) {
+        const float* rb = r + (size_t)b * vox;
+        const float* fb = feat + (size_t)b * 2 * vox;
+        const float* eb = e + (size_t)b * vox;
+        k_pack_train<<<nb(vox), 256, 0, hs>>>(rb, fb, vox, n.x_in);
+        NDL_TRY(net_forward(n, s, hs));
+        k_loss_parts<<<256, 256, 0, hs>>>(n.head, eb, vox, n.lpart);
+        k_loss_grad<<<256, 256, 0, hs>>>(n.head, eb, vox, n.lpart, 256, 1.0f / batch, st.g.d[kNumLayers - 1],
+                                         n.lossacc);
+        NDL_TRY(net_backward(st, s, hs));
+    }
+    n.step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    float c1 = 1.f - std::pow(b1, (float)n.step), c2 = 1.f - std::pow(b2, (float)n.step);
+    for (int i = 0; i < kNumLayers; ++i) {
+        Layer& l = n.L[i];
+        k_adam<<<nb((int64_t)l.nw), 256, 0, hs>>>(l.w32, l.gw, l.mw, l.vw, (int64_t)l.nw, lr, b1, b2, c1, c2, 1e-8f);
+        k_adam<<<1, 256, 0, hs>>>(l.b32, l.gb, l.mb, l.vb, l.sp.cout, lr, b1, b2, c1, c2, 1e-8f);
+        NDL_TRY(refresh_bf16(l, hs));
+    }
+    NDL_HIP(hipGetLastError());
+    float h = 0.f;
+    NDL_HIP(hipMemcpyAsync(&h, n.lossacc, sizeof(float), hipMemcpyDeviceToHost, hs));
+    NDL_HIP(hipStreamSynchronize(hs));
+    if (loss) *loss = h;
+    return std::isfinite(h) ? NDL_OK : NDL_EBREAKDOWN;
+}
+
+int ndl_precond_apply(ndl_net net, ndl_plan plan, const void* r, void* z, void* stream)
+{
+    if (!net || !plan || !r || !z) { set_error("null argument"); return NDL_EINVAL; }
+    return net_precond(net, *reinterpret_cast<Plan*>(plan), r, z, (hipStream_t)stream);
+}
+
+// Test hook: one convolution layer of the network, forward and backward.
+// x [S^3][cin] bf16 bits, w [cout][K] fp32 (K = 27 cin padded to 32), bias [cout];
+// y [S^3][cout] fp32 (linear).  dgrad: dx = conv^T(dy) [S^3][cin] fp32;
+// wgrad: gw [cout][K], gb [cout] (overwritten).  All device pointers.
+int ndl_net_conv_test(int cin, int cout, int S, const uint16_t* x, const float* w, const float* bias, float* y,
+                      const float* dy, float* dx, float* gw, float* gb, void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    Net tmp;
+    Layer l;
+    l.sp = ConvSpec{cin, cout, 0};
+    l.KP = kpad(cin);
+    l.nw = (size_t)cout * l.KP;
+    NDL_HIP(hipMalloc(&l.wbf, l.nw * sizeof(bf16_t)));
+    NDL_HIP(hipMalloc(&l.wt, (size_t)cin * kpad(cout) * sizeof(bf16_t)));
+    l.w32 = const_cast<float*>(w);
+    NDL_TRY(refresh_bf16(l, s));
+    int rc = NDL_OK;
+    float* yb = nullptr;
+    int64_t vox = (int64_t)S * S * S;
+    if (y) rc = conv_fwd(cin, cout, x, l.wbf, bias, y, S, 0, true, s);
+    if (rc == NDL_OK && dy) {
+        bf16_t* dyb = nullptr;
+        NDL_HIP(hipMalloc(&dyb, vox * cout * sizeof(bf16_t)));
+        k_to_bf16<<<nb(vox * cout), 256, 0, s>>>(dy, dyb, vox * cout);
+        if (dx) rc = conv_fwd(cout, cin, dyb, l.wt, nullptr, dx, S, 0, true, s);
+        if (rc == NDL_OK && gw) {
+            size_t blocks = (size_t)((S + 63) / 64) * ((S + 3) / 4) * S;
+            tmp.part_elems = (blocks + 1) * cout * (l.KP + 1);
+            NDL_HIP(hipMalloc(&tmp.part, tmp.part_elems * sizeof(float)));
+            tmp.bufs.push_back(tmp.part);
+            l.gw = gw;
+            l.gb = gb;
+            k_zero_f32<<<nb((int64_t)l.nw), 256, 0, s>>>(gw, (int64_t)l.nw);
+            k_zero_f32<<<1, 256, 0, s>>>(gb, cout);
+            // wgrad reads the fp32 gradient directly
+            rc = conv_wgrad(cin, cout, x, dy, tmp, l, S, s);
+        }
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(dyb);
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(l.wbf);
+    (void)hipFree(l.wt);
+    l.wbf = nullptr;
+    l.wt = nullptr;
+    l.w32 = nullptr;
+    l.gw = l.gb = nullptr;
+    return rc;
+}
+
+}  // extern "C"

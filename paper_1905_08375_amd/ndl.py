@@ -27,6 +27,7 @@ EXPORTS = [
     "ndl_fast_decomposition", "ndl_decompose_node", "ndl_cg_solve", "ndl_net_create", "ndl_net_destroy",
     "ndl_net_save", "ndl_net_load", "ndl_net_num_params", "ndl_net_train_step", "ndl_precond_apply",
     "ndl_autotune", "ndl_last_error", "ndl_version", "ndl_plan_set_variant", "ndl_plan_num_variants",
+    "ndl_net_conv_test",
 ]
 
 
@@ -90,6 +91,7 @@ def lib():
             "ndl_autotune": [vp, vp],
             "ndl_plan_set_variant": [vp, C.c_int],
             "ndl_plan_num_variants": [vp, C.POINTER(C.c_int)],
+            "ndl_net_conv_test": [C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp, vp, vp],
         }
         for name, args in sig.items():
             if hasattr(L, name):
@@ -232,3 +234,65 @@ def ndl_last_error() -> str:
 
 def ndl_version() -> str:
     return lib().ndl_version().decode()
+
+
+# ---------------------------------------------------------------- learned preconditioner
+class Net:
+    """Owns an ndl_net handle."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def close(self):
+        if self.handle:
+            lib().ndl_net_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ndl_net_create(levels: int = 4, channels=(16, 16, 32, 32), seed: int = 0) -> Net:
+    h = C.c_void_p()
+    ch = (C.c_int * len(channels))(*channels)
+    _check(lib().ndl_net_create(int(levels), ch, C.c_uint64(seed), C.byref(h)), "ndl_net_create")
+    return Net(h)
+
+
+def ndl_net_destroy(net: Net):
+    net.close()
+
+
+def ndl_net_num_params(net: Net) -> int:
+    c = C.c_int64()
+    _check(lib().ndl_net_num_params(net.handle, C.byref(c)), "ndl_net_num_params")
+    return c.value
+
+
+def ndl_net_save(net: Net, path: str):
+    _check(lib().ndl_net_save(net.handle, path.encode()), "ndl_net_save")
+
+
+def ndl_net_load(net: Net, path: str):
+    _check(lib().ndl_net_load(net.handle, path.encode()), "ndl_net_load")
+
+
+def ndl_net_train_step(net: Net, r, feat, e, lr: float, stream=None) -> float:
+    """r, e: [B][s,s,s] fp32; feat: [B][2][s,s,s] fp32 (device)."""
+    B, s = r.shape[0], r.shape[-1]
+    loss = C.c_float()
+    _check(lib().ndl_net_train_step(net.handle, int(B), int(s), _ptr(r), _ptr(feat), _ptr(e), C.c_float(lr),
+                                    C.byref(loss), _stream(stream)), "ndl_net_train_step")
+    return loss.value
+
+
+def ndl_precond_apply(net: Net, plan: Plan, r, z, stream=None):
+    _check(lib().ndl_precond_apply(net.handle, plan.handle, _ptr(r), _ptr(z), _stream(stream)), "ndl_precond_apply")
+
+
+def ndl_net_conv_test(cin, cout, S, x_bits, w, bias, y=None, dy=None, dx=None, gw=None, gb=None, stream=None):
+    _check(lib().ndl_net_conv_test(int(cin), int(cout), int(S), _ptr(x_bits), _ptr(w), _ptr(bias), _ptr(y), _ptr(dy),
+                                   _ptr(dx), _ptr(gw), _ptr(gb), _stream(stream)), "ndl_net_conv_test")
