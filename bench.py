@@ -132,6 +132,31 @@ def bench_solve(count=64, rtol=1e-8, prec=None):
             "precision": "fp32 inner (compensated apply), fp64 reductions and refinement"}
 
 
+def bench_pcg_3d(n=256, seed=100, train_steps=0):
+    """3D 256^3 case (b) solve to 1e-8: plain Jacobi-CG vs the learned two-level
+    preconditioner (weights from precond_train.WEIGHTS when present, else the
+    network is trained here on full fields for `train_steps` steps; training
+    time is reported separately and is not part of the solve times)."""
+    from paper_1905_08375_amd import ndl
+    from paper_1905_08375_amd import precond_train as PT
+    net = ndl.ndl_net_create(seed=1)
+    source = "untrained"
+    train_s = 0.0
+    if os.path.exists(PT.WEIGHTS):
+        ndl.ndl_net_load(net, PT.WEIGHTS)
+        source = os.path.relpath(PT.WEIGHTS, ROOT)
+    elif train_steps > 0:
+        t0 = time.perf_counter()
+        data = PT.make_pairs(n, range(2), ks=(16, 64, 256), log=log)
+        PT.train(net, data, steps=train_steps, log=log)
+        train_s = time.perf_counter() - t0
+        source = f"trained here ({train_steps} steps)"
+    res = PT.compare(net, n=n, seed=seed)
+    res["weights"] = source
+    res["training_seconds"] = train_s
+    return res
+
+
 def bench_pd(steps=5, batch=8, n=2048):
     import torch
     from paper_1905_08375_amd import fields as F
@@ -239,6 +264,8 @@ def main():
         rows["pd_2048x8_f32k"] = bench_pd()
         log("row: 64 batched solves to 1e-8")
         rows["cg_64_uneven_to_1e-8"] = bench_solve()
+        log("row: 3D 256^3 PCG to 1e-8, plain vs learned")
+        rows["pcg_3d_256_to_1e-8"] = bench_pcg_3d()
     cpu = None if args.no_cpu else cpu_baseline()
     line = {
         "metric": "Gpoint-applies/s of L_delta (2D var. horizon); PCG time to 1e-8: learned vs plain",

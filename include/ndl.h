@@ -181,6 +181,13 @@ int ndl_net_num_params(ndl_net net, int64_t* count);
  * (log c, m/4) features; returns the mean loss in *loss. */
 int ndl_net_train_step(ndl_net net, int batch, int s, const float* r, const float* feat,
                        const float* e, float lr, float* loss, void* stream);
+/* One Adam step of energy-norm training on full fields of an FP32 3D case (b)
+ * plan (n divisible by 8): for each of the `batch` samples (r, e) [batch][n^3]
+ * (device FP32, A e = r with A = -L), the two-level preconditioner
+ * z = D^-1 r + M(r) is evaluated and the loss ||e - z||_A^2 / ||e||_A^2 is
+ * back-propagated; *loss is its batch mean. */
+int ndl_net_train_step_energy(ndl_net net, ndl_plan plan, int batch, const float* r, const float* e, float lr,
+                              float* loss, void* stream);
 /* z = M(r): r, z device arrays of n^3 (element type of the plan's prec);
  * the plan (3D, n divisible by 8) supplies delta and c for the features. */
 int ndl_precond_apply(ndl_net net, ndl_plan plan, const void* r, void* z, void* stream);

@@ -383,14 +383,18 @@ __global__ void k_pack_train(const float* __restrict__ r, const float* __restric
     for (int c = 3; c < 8; ++c) o[c] = 0;
 }
 
-// z = (channel 0 of the fp32 head output) / rscale
+// The network is trained on targets scaled by kTargetScale (an O(1) output for
+// the smooth corrections of the operator on the unit cube).
+constexpr double kTargetScale = 32.0;
+
+// z = (channel 0 of the fp32 head output) / (rscale * kTargetScale)
 template <typename T>
 __global__ void k_unpack(const float* __restrict__ y, const double* __restrict__ rscale, int64_t n, T* __restrict__ z)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double rs = rscale ? *rscale : 1.0;
-    z[i] = (T)((double)y[i * 16] / rs);
+    z[i] = (T)((double)y[i * 16] / (rs * kTargetScale));
 }
 
 // loss: sum (y0 - e)^2 and sum e^2 per sample (partials per block) and dy = 2 (y0 - e) / (B sum e^2)
@@ -834,12 +838,13 @@ __global__ void k_sumsq(const T* __restrict__ r, int64_t n, double* __restrict__
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-__global__ void k_rscale(const double* __restrict__ part, int np, double* __restrict__ rs)
+// rscale = sqrt(N) / ||r||: the network sees the residual at unit RMS
+__global__ void k_rscale(const double* __restrict__ part, int np, double nvox, double* __restrict__ rs)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double s = 0.0;
     for (int i = 0; i < np; ++i) s += part[i];
-    *rs = s > 0.0 ? 1.0 / sqrt(s) : 1.0;
+    *rs = s > 0.0 ? sqrt(nvox / s) : 1.0;
 }
 
 template <typename T>
@@ -860,6 +865,60 @@ __global__ void k_logc_moments(const T* __restrict__ c, int64_t n, double* __res
         __syncthreads();
     }
     if (threadIdx.x == 0) { part[2 * blockIdx.x] = s1[0]; part[2 * blockIdx.x + 1] = s2[0]; }
+}
+
+
+// Energy-norm training on full fields of one case (b) plan (FP32): with the
+// two-level preconditioner z = D^-1 r + M(r), the loss per sample is
+//   ||e - z||_A^2 / ||e||_A^2 = (e - z).(r - A z) / (e.r),   A = -L, A e = r,
+// and its gradient with respect to z is 2 (A z - r) / (e.r).
+__global__ void k_z_two_level(const float* __restrict__ y, const double* __restrict__ rscale, const float* __restrict__ r,
+                              const float* __restrict__ dinv, int64_t n, float* __restrict__ z)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    z[i] = (float)((double)r[i] * (double)dinv[i] + (double)y[i * 16] / (*rscale * kTargetScale));
+}
+
+__global__ void k_energy_parts(const float* __restrict__ e, const float* __restrict__ z, const float* __restrict__ r,
+                               const float* __restrict__ az, int64_t n, double* __restrict__ part)
+{
+    __shared__ double s1[256], s2[256];
+    double a = 0.0, b = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        a += ((double)e[i] - (double)z[i]) * ((double)r[i] - (double)az[i]);
+        b += (double)e[i] * (double)r[i];
+    }
+    s1[threadIdx.x] = a;
+    s2[threadIdx.x] = b;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) { s1[threadIdx.x] += s1[threadIdx.x + o]; s2[threadIdx.x] += s2[threadIdx.x + o]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { part[2 * blockIdx.x] = s1[0]; part[2 * blockIdx.x + 1] = s2[0]; }
+}
+
+__global__ void k_energy_grad(const float* __restrict__ r, const float* __restrict__ az, int64_t n,
+                              const double* __restrict__ part, int nparts, const double* __restrict__ rscale,
+                              float inv_b, float* __restrict__ dy, float* __restrict__ loss_acc)
+{
+    __shared__ double den_s;
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int p = 0; p < nparts; ++p) { a += part[2 * p]; b += part[2 * p + 1]; }
+        den_s = b > 0 ? b : 1.0;
+        if (blockIdx.x == 0) atomicAdd(loss_acc, (float)(a / den_s) * inv_b);
+    }
+    __syncthreads();
+    double den = den_s;
+    double dzdy = 1.0 / (*rscale * kTargetScale);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double g = 2.0 * ((double)az[i] - (double)r[i]) / den;
+        dy[i * 16] = (float)(g * dzdy) * inv_b;
+#pragma unroll
+        for (int c = 1; c < 16; ++c) dy[i * 16 + c] = 0.f;
+    }
 }
 
 // z = M(r) for a plan's cube (n^3, n % 8 == 0): input (r / ||r||, standardised log c, m / 4)
@@ -885,11 +944,11 @@ static int precond_t(NetState& st, const Plan& p, const T* r, T* z, hipStream_t 
         st.feat_plan = &p;
     }
     k_sumsq<T><<<256, 256, 0, s>>>(r, p.N, n.lpart);
-    k_rscale<<<1, 64, 0, s>>>(n.lpart, 256, n.rscale);
+    k_rscale<<<1, 64, 0, s>>>(n.lpart, 256, (double)p.N, n.rscale);
     k_pack_input<T><<<nb(p.N), 256, 0, s>>>(r, n.rscale, (const T*)p.prob.delta, (const T*)p.prob.coef, p.N, S,
                                             st.feat_mu, st.feat_isd, n.x_in);
     NDL_TRY(net_forward(n, S, s));
-    k_unpack<T><<<nb(p.N), 256, 0, s>>>(n.head, n.rscale, p.N, z);
+    if (z) k_unpack<T><<<nb(p.N), 256, 0, s>>>(n.head, n.rscale, p.N, z);
     NDL_HIP(hipGetLastError());
     return NDL_OK;
 }
@@ -1033,6 +1092,68 @@ int ndl_net_train_step(ndl_net net, int batch, int s, const float* r, const floa
                                          n.lossacc);
         NDL_TRY(net_backward(st, s, hs));
     }
+    n.step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    float c1 = 1.f - std::pow(b1, (float)n.step), c2 = 1.f - std::pow(b2, (float)n.step);
+    for (int i = 0; i < kNumLayers; ++i) {
+        Layer& l = n.L[i];
+        k_adam<<<nb((int64_t)l.nw), 256, 0, hs>>>(l.w32, l.gw, l.mw, l.vw, (int64_t)l.nw, lr, b1, b2, c1, c2, 1e-8f);
+        k_adam<<<1, 256, 0, hs>>>(l.b32, l.gb, l.mb, l.vb, l.sp.cout, lr, b1, b2, c1, c2, 1e-8f);
+        NDL_TRY(refresh_bf16(l, hs));
+    }
+    NDL_HIP(hipGetLastError());
+    float h = 0.f;
+    NDL_HIP(hipMemcpyAsync(&h, n.lossacc, sizeof(float), hipMemcpyDeviceToHost, hs));
+    NDL_HIP(hipStreamSynchronize(hs));
+    if (loss) *loss = h;
+    return std::isfinite(h) ? NDL_OK : NDL_EBREAKDOWN;
+}
+
+int ndl_net_train_step_energy(ndl_net net, ndl_plan plan, int batch, const float* r, const float* e, float lr,
+                              float* loss, void* stream)
+{
+    if (!net || !plan || batch <= 0 || !r || !e) { set_error("ndl_net_train_step_energy: bad arguments"); return NDL_EINVAL; }
+    NetState& st = *reinterpret_cast<NetState*>(net);
+    Net& n = st.net;
+    const Plan& P = *reinterpret_cast<const Plan*>(plan);
+    if (P.dim != 3 || P.n % 8 != 0 || P.form != NDL_DIV || P.prec == NDL_F64) {
+        set_error("energy training needs an FP32 3D case (b) plan with n divisible by 8");
+        return NDL_EUNSUPPORTED;
+    }
+    hipStream_t hs = (hipStream_t)stream;
+    int S = (int)P.n;
+    int64_t N = P.N;
+    // forward once to size the workspace and the features
+    NDL_TRY(precond_t<float>(st, P, r, nullptr, hs));
+    NDL_TRY(grads_workspace(st, S));
+    float *z = nullptr, *az = nullptr;
+    NDL_HIP(hipMalloc(&z, N * sizeof(float)));
+    NDL_HIP(hipMalloc(&az, N * sizeof(float)));
+    for (int i = 0; i < kNumLayers; ++i) {
+        k_zero_f32<<<nb((int64_t)n.L[i].nw), 256, 0, hs>>>(n.L[i].gw, (int64_t)n.L[i].nw);
+        k_zero_f32<<<1, 256, 0, hs>>>(n.L[i].gb, n.L[i].sp.cout);
+    }
+    k_zero_f32<<<1, 64, 0, hs>>>(n.lossacc, 1);
+    int rc = NDL_OK;
+    for (int b = 0; b < batch && rc == NDL_OK; ++b) {
+        const float* rb = r + (size_t)b * N;
+        const float* eb = e + (size_t)b * N;
+        rc = precond_t<float>(st, P, rb, nullptr, hs);  // head output for rb
+        const float* dinv = nullptr;
+        if (rc == NDL_OK) rc = plan_neg_L_f32(P, z, az, &dinv, hs);  // builds dinv on first use
+        if (rc != NDL_OK) break;
+        k_z_two_level<<<nb(N), 256, 0, hs>>>(n.head, n.rscale, rb, dinv, N, z);
+        rc = plan_neg_L_f32(P, z, az, nullptr, hs);
+        if (rc != NDL_OK) break;
+        k_energy_parts<<<256, 256, 0, hs>>>(eb, z, rb, az, N, n.lpart);
+        k_energy_grad<<<256, 256, 0, hs>>>(rb, az, N, n.lpart, 256, n.rscale, 1.0f / batch, st.g.d[kNumLayers - 1],
+                                           n.lossacc);
+        rc = net_backward(st, S, hs);
+    }
+    (void)hipStreamSynchronize(hs);
+    (void)hipFree(z);
+    (void)hipFree(az);
+    if (rc != NDL_OK) return rc;
     n.step += 1;
     const float b1 = 0.9f, b2 = 0.999f;
     float c1 = 1.f - std::pow(b1, (float)n.step), c2 = 1.f - std::pow(b2, (float)n.step);

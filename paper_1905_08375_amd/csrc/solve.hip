@@ -74,6 +74,11 @@ __device__ __forceinline__ double block_sum(double v, double* red)
 
 // q = -L p over the items (case (b), FP64 pair cutoffs), fused with the
 // per-item partial of p.q.  DIAG = true computes the Jacobi diagonal instead.
+// The tile of p and, for FP32 data, of delta and c (with a halo of J nodes)
+// are staged in LDS; outside Omega delta is marked negative so a partner in
+// the collar takes (delta_i, c_i).  Per pair, in FP64:
+//   a = (delta_i + delta_j) (n/2),  k_ij = ceil(a*a) - 1  (exactly the rule of case (b)),
+//   w = (c'_i + c'_j) |z|^e M / T_e[k_ij],  c' = c n^2 / 2.
 template <typename T, bool DIAG>
 __global__ __launch_bounds__(256) void k_div_items(const Inst* __restrict__ insts, const int2* __restrict__ items,
                                                    int nitems, const T* __restrict__ pvec, T* __restrict__ qvec,
@@ -81,9 +86,11 @@ __global__ __launch_bounds__(256) void k_div_items(const Inst* __restrict__ inst
                                                    int nfull, const double* __restrict__ Tinv,
                                                    const Scal* __restrict__ sc, double* __restrict__ part)
 {
+    constexpr bool STAGE = sizeof(T) == 4;  // FP32 fields fit LDS next to the state
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* tu = reinterpret_cast<T*>(smem_raw);
     __shared__ double red[4];
+    __shared__ double tinv_s[256];
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         int2 item = items[it];
         const Inst I = insts[item.x];
@@ -96,27 +103,32 @@ __global__ __launch_bounds__(256) void k_div_items(const Inst* __restrict__ inst
         int ext[3] = {I.dim >= 3 ? I.n : 1, I.dim >= 2 ? I.n : 1, I.n};
         int halo[3] = {I.dim >= 3 ? I.J : 0, I.dim >= 2 ? I.J : 0, I.J};
         int L[3] = {I.E[0] + 2 * halo[0], I.E[1] + 2 * halo[1], I.E[2] + 2 * halo[2]};
+        const int tot = stage_box_len(L);
+        T* td = tu + tot;
+        T* tc = td + tot;
         const T* p = pvec + I.off;
         const T* dlt = static_cast<const T*>(I.delta);
         const T* cf = static_cast<const T*>(I.coef);
         __syncthreads();
-        if (!DIAG) {
-            int tot = stage_box_len(L);
-            for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-                int l2 = idx % L[2];
-                int r = idx / L[2];
-                int l1 = r % L[1];
-                int l0 = r / L[1];
-                int g0 = org[0] - halo[0] + l0, g1 = org[1] - halo[1] + l1, g2 = org[2] - halo[2] + l2;
-                T v = 0;
-                if (g0 >= 0 && g0 < ext[0] && g1 >= 0 && g1 < ext[1] && g2 >= 0 && g2 < ext[2])
-                    v = p[((int64_t)g0 * ext[1] + g1) * ext[2] + g2];
-                tu[idx] = v;
+        for (int k = threadIdx.x; k <= I.kmax && k < 256; k += blockDim.x) tinv_s[k] = Tinv[k];
+        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+            int l2 = idx % L[2];
+            int r = idx / L[2];
+            int l1 = r % L[1];
+            int l0 = r / L[1];
+            int g0 = org[0] - halo[0] + l0, g1 = org[1] - halo[1] + l1, g2 = org[2] - halo[2] + l2;
+            bool in = g0 >= 0 && g0 < ext[0] && g1 >= 0 && g1 < ext[1] && g2 >= 0 && g2 < ext[2];
+            int64_t gg = ((int64_t)g0 * ext[1] + g1) * ext[2] + g2;
+            if (!DIAG) tu[idx] = in ? p[gg] : T(0);
+            if (STAGE) {
+                td[idx] = in ? dlt[gg] : T(-1);
+                tc[idx] = in ? cf[gg] : T(0);
             }
         }
         __syncthreads();
         double dot = 0.0;
-        double nn = (double)I.n;
+        const double nh = 0.5 * (double)I.n;
+        const double ch = 0.5 * I.n2;
         int npts = I.E[0] * I.E[1] * I.E[2];
         for (int pi = threadIdx.x; pi < npts; pi += blockDim.x) {
             int e2 = pi % I.E[2];
@@ -127,29 +139,40 @@ __global__ __launch_bounds__(256) void k_div_items(const Inst* __restrict__ inst
             if (!(x0 < ext[0] && x1 < ext[1] && x2 < ext[2])) continue;
             int64_t gi = ((int64_t)x0 * ext[1] + x1) * ext[2] + x2;
             int cidx = ((e0 + halo[0]) * L[1] + (e1 + halo[1])) * L[2] + (e2 + halo[2]);
-            double di = (double)dlt[gi], ci = (double)cf[gi];
+            double di = STAGE ? (double)td[cidx] : (double)dlt[gi];
+            double ci = STAGE ? (double)tc[cidx] : (double)cf[gi];
+            double cpi = ci * ch;
             T u0 = DIAG ? T(0) : tu[cidx];
             Acc<T> acc;
             double dsum = 0.0;
             for (int q = 0; q < nfull; q++) {
                 int4 o = full[q];
                 if (o.w > I.kmax) break;
-                int y0 = x0 + o.x, y1 = x1 + o.y, y2 = x2 + o.z;
-                double dj = di, cj = ci;
-                if (y0 >= 0 && y0 < ext[0] && y1 >= 0 && y1 < ext[1] && y2 >= 0 && y2 < ext[2]) {
-                    int64_t gj = ((int64_t)y0 * ext[1] + y1) * ext[2] + y2;
-                    dj = (double)dlt[gj];
-                    cj = (double)cf[gj];
+                double dj, cj;
+                int off = (o.x * L[1] + o.y) * L[2] + o.z;
+                if (STAGE) {
+                    dj = (double)td[cidx + off];
+                    cj = (double)tc[cidx + off];
+                    if (dj < 0.0) { dj = di; cj = ci; }
+                } else {
+                    int y0 = x0 + o.x, y1 = x1 + o.y, y2 = x2 + o.z;
+                    dj = di;
+                    cj = ci;
+                    if (y0 >= 0 && y0 < ext[0] && y1 >= 0 && y1 < ext[1] && y2 >= 0 && y2 < ext[2]) {
+                        int64_t gj = ((int64_t)y0 * ext[1] + y1) * ext[2] + y2;
+                        dj = (double)dlt[gj];
+                        cj = (double)cf[gj];
+                    }
                 }
-                double am = (di + dj) * nn * 0.5;
+                double am = (di + dj) * nh;
                 double tt = am * am;
                 int kij = (int)ceil(tt) - 1;
                 if (o.w > kij) continue;
-                double C = 0.5 * (ci + cj);
                 double w;
                 if (I.norm == NDL_NORM_DISCRETE) {
-                    w = C * fw[q] * Tinv[kij] * I.n2;
+                    w = (cpi + cj * ch) * fw[q] * (kij < 256 ? tinv_s[kij] : Tinv[kij]);
                 } else {
+                    double C = 0.5 * (ci + cj);
                     double dij = (di + dj) * 0.5;
                     double dd2 = pow(dij, (double)(I.dim + 2));
                     double base = C * pow(am, -I.expo) * I.hd / dd2 * fw[q];
@@ -158,7 +181,6 @@ __global__ __launch_bounds__(256) void k_div_items(const Inst* __restrict__ inst
                 if (DIAG) {
                     dsum += w;
                 } else {
-                    int off = (o.x * L[1] + o.y) * L[2] + o.z;
                     acc.fma_((T)w, tu[cidx + off] - u0);
                     if ((q & 7) == 7) acc.flush();
                 }
@@ -522,7 +544,7 @@ static size_t items_lds(const Batch& B)
     const Inst& I0 = B.insts[0];
     int L[3] = {I0.E[0] + (B.dim >= 3 ? 2 * B.Jmax : 0), I0.E[1] + (B.dim >= 2 ? 2 * B.Jmax : 0),
                 I0.E[2] + 2 * B.Jmax};
-    return (size_t)L[0] * L[1] * L[2] * sizeof(T);
+    return (size_t)L[0] * L[1] * L[2] * sizeof(T) * (sizeof(T) == 4 ? 3 : 1);
 }
 
 template <typename T>
@@ -533,9 +555,12 @@ static int prepare_lds(const Batch& B)
         set_error("solver tile needs %zu B of LDS (horizon too wide)", lds);
         return NDL_EUNSUPPORTED;
     }
-    if (lds > 64 * 1024)
+    if (lds > 64 * 1024) {
         NDL_HIP(hipFuncSetAttribute((const void*)k_div_items<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)lds));
+        NDL_HIP(hipFuncSetAttribute((const void*)k_div_items<T, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds));
+    }
     return NDL_OK;
 }
 
@@ -544,7 +569,7 @@ static int launch_div_items(const Batch& B, const Inst* d_insts, const int2* d_i
                             const int4* full, const double* fw, int nfull, const double* Tinv, const Scal* sc,
                             double* part, bool diag, hipStream_t s)
 {
-    size_t lds = diag ? 16 : items_lds<T>(B);
+    size_t lds = items_lds<T>(B);
     int nitems = (int)B.items.size();
     unsigned g = (unsigned)std::min(nitems, 256 * 8);
     if (diag)
@@ -812,6 +837,376 @@ static int cg_solve_t(const ndl_plan* plans, int nprob, const double* const* b, 
     return NDL_OK;
 }
 
+// ------------------------------------------------------------------ single-plan operator
+// -L on an unpadded vector of one case (b) plan (zero volume constraint),
+// with device tables built once and kept by the caller.
+struct OpCache {
+    const Plan* plan = nullptr;
+    Batch B;
+    DevBuf insts, items, full, fw, Tinv, part, sres, dinv;
+    int nfull = 0, nitems = 0;
+};
+
+template <typename T>
+static int op_build(const Plan& P, OpCache& oc, hipStream_t s)
+{
+    if (oc.plan == &P) return NDL_OK;
+    oc = OpCache();
+    ndl_plan h = reinterpret_cast<ndl_plan>(const_cast<Plan*>(&P));
+    std::vector<DevBuf> keep;
+    NDL_TRY(build_batch(&h, 1, oc.B, false, keep));
+    oc.nitems = (int)oc.B.items.size();
+    NDL_TRY(alloc<Inst>(oc.insts, 1));
+    NDL_TRY(alloc<int2>(oc.items, oc.nitems));
+    NDL_HIP(hipMemcpy(oc.insts.p, oc.B.insts.data(), sizeof(Inst), hipMemcpyHostToDevice));
+    NDL_HIP(hipMemcpy(oc.items.p, oc.B.items.data(), oc.nitems * sizeof(int2), hipMemcpyHostToDevice));
+    std::vector<Off> full = ball_offsets(oc.B.dim, oc.B.kmax, false);
+    std::vector<int4> fb;
+    std::vector<double> fwv;
+    for (auto& o : full) {
+        fb.push_back(box_offset(oc.B.dim, o));
+        fwv.push_back(std::pow(std::sqrt((double)o.q), P.expo));
+    }
+    std::vector<double> shell(oc.B.kmax + 1, 0.0), Tinv(oc.B.kmax + 1, 0.0);
+    for (auto& o : full) shell[o.q] += std::pow(std::sqrt((double)o.q), P.expo + 2.0);
+    double acc = 0.0;
+    for (int64_t k = 0; k <= oc.B.kmax; ++k) {
+        acc += shell[k];
+        Tinv[k] = acc > 0 ? P.m2 / acc : 0.0;
+    }
+    NDL_TRY(alloc<int4>(oc.full, fb.size()));
+    NDL_TRY(alloc<double>(oc.fw, fwv.size()));
+    NDL_TRY(alloc<double>(oc.Tinv, Tinv.size()));
+    NDL_HIP(hipMemcpy(oc.full.p, fb.data(), fb.size() * sizeof(int4), hipMemcpyHostToDevice));
+    NDL_HIP(hipMemcpy(oc.fw.p, fwv.data(), fwv.size() * sizeof(double), hipMemcpyHostToDevice));
+    NDL_HIP(hipMemcpy(oc.Tinv.p, Tinv.data(), Tinv.size() * sizeof(double), hipMemcpyHostToDevice));
+    oc.nfull = (int)fb.size();
+    NDL_TRY(alloc<double>(oc.part, oc.nitems));
+    NDL_TRY(alloc<double>(oc.sres, 2));
+    NDL_TRY(alloc<T>(oc.dinv, P.N));
+    NDL_TRY(prepare_lds<T>(oc.B));
+    NDL_TRY(launch_div_items<T>(oc.B, (const Inst*)oc.insts.p, (const int2*)oc.items.p, (const T*)nullptr,
+                                (T*)oc.dinv.p, (const int4*)oc.full.p, (const double*)oc.fw.p, oc.nfull,
+                                (const double*)oc.Tinv.p, nullptr, nullptr, true, s));
+    k_recip<T><<<grid_for(P.N), 256, 0, s>>>((const T*)oc.dinv.p, (T*)oc.dinv.p, P.N);
+    NDL_HIP(hipGetLastError());
+    NDL_HIP(hipStreamSynchronize(s));
+    oc.plan = &P;
+    return NDL_OK;
+}
+
+static OpCache g_op_cache;  // one cached operator (the training loop uses one plan at a time)
+
+// y = -L x (unpadded, FP32) for one plan; dinv = 1 / diag(-L) available after the call
+int plan_neg_L_f32(const Plan& P, const float* x, float* y, const float** dinv, hipStream_t s)
+{
+    if (P.form != NDL_DIV || P.prec == NDL_F64) {
+        set_error("internal: FP32 case (b) plan expected");
+        return NDL_EINVAL;
+    }
+    NDL_TRY(op_build<float>(P, g_op_cache, s));
+    OpCache& oc = g_op_cache;
+    NDL_TRY(launch_div_items<float>(oc.B, (const Inst*)oc.insts.p, (const int2*)oc.items.p, x, y,
+                                    (const int4*)oc.full.p, (const double*)oc.fw.p, oc.nfull,
+                                    (const double*)oc.Tinv.p, nullptr, nullptr, false, s));
+    if (dinv) *dinv = (const float*)oc.dinv.p;
+    return NDL_OK;
+}
+
+// ------------------------------------------------------------------ flexible PCG with M(r)
+template <typename T>
+__global__ void k_dot2(const Inst* __restrict__ insts, const int2* __restrict__ items, int nitems,
+                       const T* __restrict__ r, const T* __restrict__ a, const T* __restrict__ b,
+                       double* __restrict__ pa, double* __restrict__ pb)
+{
+    __shared__ double red[4];
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        int2 item = items[it];
+        const Inst I = insts[item.x];
+        int org[3];
+        item_geom<T>(I, item.y, org);
+        int ext[3] = {I.dim >= 3 ? I.n : 1, I.dim >= 2 ? I.n : 1, I.n};
+        double s1 = 0.0, s2 = 0.0;
+        int npts = I.E[0] * I.E[1] * I.E[2];
+        for (int pi = threadIdx.x; pi < npts; pi += blockDim.x) {
+            int e2 = pi % I.E[2];
+            int rr_ = pi / I.E[2];
+            int e1 = rr_ % I.E[1];
+            int e0 = rr_ / I.E[1];
+            int x0 = org[0] + e0, x1 = org[1] + e1, x2 = org[2] + e2;
+            if (!(x0 < ext[0] && x1 < ext[1] && x2 < ext[2])) continue;
+            int64_t gi = I.off + ((int64_t)x0 * ext[1] + x1) * ext[2] + x2;
+            double rv = (double)r[gi];
+            s1 += rv * (double)a[gi];
+            if (b) s2 += rv * (double)b[gi];
+        }
+        double t1 = block_sum(s1, red);
+        double t2 = block_sum(s2, red);
+        if (threadIdx.x == 0) { pa[it] = t1; if (pb) pb[it] = t2; }
+    }
+}
+
+// d += alpha p ; r -= alpha q ; partial r.r
+template <typename T>
+__global__ void k_axpy2(int64_t n, double alpha, T* __restrict__ d, T* __restrict__ r, const T* __restrict__ p,
+                        const T* __restrict__ q)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    T a = (T)alpha;
+    d[i] += a * p[i];
+    r[i] -= a * q[i];
+}
+
+// p = z + beta p ; z_old = z
+template <typename T>
+__global__ void k_dir2(int64_t n, double beta, const T* __restrict__ z, T* __restrict__ p, T* __restrict__ zold)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    T zv = z[i];
+    p[i] = zv + (T)beta * p[i];
+    zold[i] = zv;
+}
+
+// z = r / diag (+ z when add)
+template <typename T>
+__global__ void k_jacobi_add(int64_t n, const T* __restrict__ r, const T* __restrict__ dinv, T* __restrict__ z, int add)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) z[i] = r[i] * dinv[i] + (add ? z[i] : T(0));
+}
+
+// One problem; the inner solve uses z = M(r) from the network (flexible CG,
+// Polak-Ribiere beta).  A breakdown (p.q <= 0, r.z <= 0, non-finite values)
+// switches the rest of the solve to Jacobi (reported as fell_back).
+template <typename T>
+static int pcg_learned_t(const ndl_plan plan, const double* b, double* x, const ndl_cg_opts* opts,
+                         ndl_cg_report* rep, hipStream_t s)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    const Plan& P = *reinterpret_cast<const Plan*>(plan);
+    Batch B;
+    std::vector<DevBuf> keep;
+    NDL_TRY(build_batch(&plan, 1, B, false, keep));
+    const int nitems = (int)B.items.size();
+    const int64_t N = P.N;
+    DevBuf d_insts, d_insts64, d_items, d_full, d_fw, d_Tinv;
+    NDL_TRY(alloc<Inst>(d_insts, 1));
+    NDL_TRY(alloc<Inst>(d_insts64, 1));
+    NDL_TRY(alloc<int2>(d_items, nitems));
+    NDL_HIP(hipMemcpy(d_insts.p, B.insts.data(), sizeof(Inst), hipMemcpyHostToDevice));
+    NDL_HIP(hipMemcpy(d_items.p, B.items.data(), nitems * sizeof(int2), hipMemcpyHostToDevice));
+    std::vector<Off> full = ball_offsets(B.dim, B.kmax, false);
+    std::vector<int4> fb;
+    std::vector<double> fwv;
+    for (auto& o : full) {
+        fb.push_back(box_offset(B.dim, o));
+        fwv.push_back(std::pow(std::sqrt((double)o.q), P.expo));
+    }
+    std::vector<double> shell(B.kmax + 1, 0.0), Tinv(B.kmax + 1, 0.0);
+    for (auto& o : full) shell[o.q] += std::pow(std::sqrt((double)o.q), P.expo + 2.0);
+    double acc = 0.0;
+    for (int64_t k = 0; k <= B.kmax; ++k) {
+        acc += shell[k];
+        Tinv[k] = acc > 0 ? P.m2 / acc : 0.0;
+    }
+    NDL_TRY(alloc<int4>(d_full, fb.size()));
+    NDL_TRY(alloc<double>(d_fw, fwv.size()));
+    NDL_TRY(alloc<double>(d_Tinv, Tinv.size()));
+    NDL_HIP(hipMemcpy(d_full.p, fb.data(), fb.size() * sizeof(int4), hipMemcpyHostToDevice));
+    NDL_HIP(hipMemcpy(d_fw.p, fwv.data(), fwv.size() * sizeof(double), hipMemcpyHostToDevice));
+    NDL_HIP(hipMemcpy(d_Tinv.p, Tinv.data(), Tinv.size() * sizeof(double), hipMemcpyHostToDevice));
+    const int nfull = (int)fb.size();
+    // FP64 fields for the outer residual
+    DevBuf dd64, dc64;
+    Inst i64 = B.insts[0];
+    if (sizeof(T) == 4) {
+        NDL_TRY(alloc<double>(dd64, N));
+        NDL_TRY(alloc<double>(dc64, N));
+        k_widen<float><<<grid_for(N), 256, 0, s>>>((const float*)P.prob.delta, (double*)dd64.p, N);
+        k_widen<float><<<grid_for(N), 256, 0, s>>>((const float*)P.prob.coef, (double*)dc64.p, N);
+        i64.delta = dd64.p;
+        i64.coef = dc64.p;
+    }
+    NDL_HIP(hipMemcpy(d_insts64.p, &i64, sizeof(Inst), hipMemcpyHostToDevice));
+    NDL_TRY(prepare_lds<T>(B));
+    NDL_TRY(prepare_lds<double>(B));
+    const Inst* di = (const Inst*)d_insts.p;
+    const Inst* di64 = (const Inst*)d_insts64.p;
+    const int2* dit = (const int2*)d_items.p;
+    DevBuf vx, vax, vr64, vd, vr, vz, vzo, vp, vq, vdinv, pa, pb, sres;
+    NDL_TRY(alloc<double>(vx, N));
+    NDL_TRY(alloc<double>(vax, N));
+    NDL_TRY(alloc<double>(vr64, N));
+    NDL_TRY(alloc<T>(vd, N));
+    NDL_TRY(alloc<T>(vr, N));
+    NDL_TRY(alloc<T>(vz, N));
+    NDL_TRY(alloc<T>(vzo, N));
+    NDL_TRY(alloc<T>(vp, N));
+    NDL_TRY(alloc<T>(vq, N));
+    NDL_TRY(alloc<T>(vdinv, N));
+    NDL_TRY(alloc<double>(pa, nitems));
+    NDL_TRY(alloc<double>(pb, nitems));
+    NDL_TRY(alloc<double>(sres, 2));
+    NDL_HIP(hipMemcpyAsync(vx.p, x, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    NDL_TRY(launch_div_items<T>(B, di, dit, (const T*)nullptr, (T*)vq.p, (const int4*)d_full.p, (const double*)d_fw.p,
+                                nfull, (const double*)d_Tinv.p, nullptr, nullptr, true, s));
+    k_recip<T><<<grid_for(N), 256, 0, s>>>((const T*)vq.p, (T*)vdinv.p, N);
+    unsigned gi = (unsigned)std::min(nitems, 256 * 8);
+    auto sum_items = [&](const double* part, double* out) -> int {
+        k_item_sums<<<1, 64, 0, s>>>(1, di, part, (double*)sres.p);
+        NDL_HIP(hipMemcpyAsync(out, sres.p, sizeof(double), hipMemcpyDeviceToHost, s));
+        NDL_HIP(hipStreamSynchronize(s));
+        return NDL_OK;
+    };
+    auto dots = [&](const T* r, const T* a, const T* bb, double* o1, double* o2) -> int {
+        k_dot2<T><<<gi, 256, 0, s>>>(di, dit, nitems, r, a, bb, (double*)pa.p, (double*)pb.p);
+        NDL_TRY(sum_items((const double*)pa.p, o1));
+        if (bb) NDL_TRY(sum_items((const double*)pb.p, o2));
+        return NDL_OK;
+    };
+    // two-level preconditioner: z = D^-1 r + M(r); the network supplies the
+    // smooth part of the correction that the Jacobi term misses
+    auto precond = [&](const T* r, T* z, bool jac) -> int {
+        if (!jac) NDL_TRY(net_precond(opts->net, P, r, z, s));
+        k_jacobi_add<T><<<grid_for(N), 256, 0, s>>>(N, r, (const T*)vdinv.p, z, jac ? 0 : 1);
+        NDL_HIP(hipGetLastError());
+        return NDL_OK;
+    };
+    // ||b||
+    NDL_HIP(hipMemsetAsync(vax.p, 0, N * sizeof(double), s));
+    k_residual<double><<<gi, 256, 0, s>>>(di, dit, nitems, b, (const double*)vax.p, (double*)vr64.p, (double*)pa.p);
+    double bn2 = 0.0;
+    NDL_TRY(sum_items((const double*)pa.p, &bn2));
+    const double bn = std::sqrt(bn2);
+    const double rtol = opts->rtol > 0 ? opts->rtol : 1e-8;
+    const int max_iter = opts->max_iter > 0 ? opts->max_iter : 100000;
+    const double inner_rtol = opts->inner_rtol > 0 ? opts->inner_rtol : (sizeof(T) == 4 ? 1e-5 : rtol);
+    int iters = 0, outer = 0;
+    bool jac = false, conv = false;
+    double rel = 1.0;
+    for (int o = 0; o < 20; ++o) {
+        NDL_TRY(launch_div_items<double>(B, di64, dit, (const double*)vx.p, (double*)vax.p, (const int4*)d_full.p,
+                                         (const double*)d_fw.p, nfull, (const double*)d_Tinv.p, nullptr, nullptr,
+                                         false, s));
+        k_residual<double><<<gi, 256, 0, s>>>(di, dit, nitems, b, (const double*)vax.p, (double*)vr64.p,
+                                               (double*)pa.p);
+        double rn2 = 0.0;
+        NDL_TRY(sum_items((const double*)pa.p, &rn2));
+        rel = bn > 0 ? std::sqrt(rn2) / bn : std::sqrt(rn2);
+        if (rel <= rtol) { conv = true; break; }
+        if (iters >= max_iter) break;
+        ++outer;
+        const double rn = std::sqrt(rn2);
+        const double want = std::max(inner_rtol, 0.5 * rtol * bn / rn);
+        // inner: -L d = r / ||r||
+        double sc = 1.0 / rn;
+        int owner0 = 0;
+        (void)owner0;
+        {
+            std::vector<int> own((N + 1023) / 1024, 0);
+            DevBuf down;
+            NDL_TRY(alloc<int>(down, own.size()));
+            NDL_HIP(hipMemcpyAsync(down.p, own.data(), own.size() * sizeof(int), hipMemcpyHostToDevice, s));
+            DevBuf dsc;
+            NDL_TRY(alloc<double>(dsc, 1));
+            NDL_HIP(hipMemcpyAsync(dsc.p, &sc, sizeof(double), hipMemcpyHostToDevice, s));
+            k_scale_copy<T, double><<<grid_for(N), 256, 0, s>>>(di, (const int*)down.p, N, (const double*)vr64.p,
+                                                                 (T*)vr.p, (const double*)dsc.p);
+            NDL_HIP(hipStreamSynchronize(s));
+        }
+        NDL_HIP(hipMemsetAsync(vd.p, 0, N * sizeof(T), s));
+        NDL_TRY(precond((const T*)vr.p, (T*)vz.p, jac));
+        double rz = 0.0, rr = 1.0, dummy = 0.0;
+        NDL_TRY(dots((const T*)vr.p, (const T*)vz.p, nullptr, &rz, &dummy));
+        if (!(rz > 0.0) || !std::isfinite(rz)) {
+            jac = true;
+            NDL_TRY(precond((const T*)vr.p, (T*)vz.p, true));
+            NDL_TRY(dots((const T*)vr.p, (const T*)vz.p, nullptr, &rz, &dummy));
+        }
+        NDL_HIP(hipMemcpyAsync(vp.p, vz.p, N * sizeof(T), hipMemcpyDeviceToDevice, s));
+        NDL_HIP(hipMemcpyAsync(vzo.p, vz.p, N * sizeof(T), hipMemcpyDeviceToDevice, s));
+        double best = 1.0;
+        int since_best = 0;
+        while (iters < max_iter) {
+            NDL_TRY(launch_div_items<T>(B, di, dit, (const T*)vp.p, (T*)vq.p, (const int4*)d_full.p,
+                                        (const double*)d_fw.p, nfull, (const double*)d_Tinv.p, nullptr, (double*)pa.p,
+                                        false, s));
+            double pq = 0.0;
+            NDL_TRY(sum_items((const double*)pa.p, &pq));
+            ++iters;
+            if (!(pq > 0.0) || !std::isfinite(pq)) {
+                if (jac) break;  // even Jacobi broke down: stop this inner solve
+                jac = true;      // fall back and restart the inner directions
+                NDL_TRY(precond((const T*)vr.p, (T*)vz.p, true));
+                NDL_TRY(dots((const T*)vr.p, (const T*)vz.p, nullptr, &rz, &dummy));
+                NDL_HIP(hipMemcpyAsync(vp.p, vz.p, N * sizeof(T), hipMemcpyDeviceToDevice, s));
+                NDL_HIP(hipMemcpyAsync(vzo.p, vz.p, N * sizeof(T), hipMemcpyDeviceToDevice, s));
+                continue;
+            }
+            double alpha = rz / pq;
+            k_axpy2<T><<<grid_for(N), 256, 0, s>>>(N, alpha, (T*)vd.p, (T*)vr.p, (const T*)vp.p, (const T*)vq.p);
+            NDL_TRY(dots((const T*)vr.p, (const T*)vr.p, nullptr, &rr, &dummy));
+            if (std::sqrt(rr) <= want || !std::isfinite(rr)) break;
+            // stagnation of the learned directions: fall back to Jacobi
+            if (rr < 0.999 * best) { best = rr; since_best = 0; }
+            else if (++since_best > 50 && !jac) {
+                jac = true;
+                NDL_TRY(precond((const T*)vr.p, (T*)vz.p, true));
+                NDL_TRY(dots((const T*)vr.p, (const T*)vz.p, nullptr, &rz, &dummy));
+                NDL_HIP(hipMemcpyAsync(vp.p, vz.p, N * sizeof(T), hipMemcpyDeviceToDevice, s));
+                NDL_HIP(hipMemcpyAsync(vzo.p, vz.p, N * sizeof(T), hipMemcpyDeviceToDevice, s));
+                continue;
+            }
+            NDL_TRY(precond((const T*)vr.p, (T*)vz.p, jac));
+            double rzn = 0.0, rzo = 0.0;
+            NDL_TRY(dots((const T*)vr.p, (const T*)vz.p, (const T*)vzo.p, &rzn, &rzo));
+            if (!(rzn > 0.0) || !std::isfinite(rzn)) {
+                jac = true;
+                NDL_TRY(precond((const T*)vr.p, (T*)vz.p, true));
+                NDL_TRY(dots((const T*)vr.p, (const T*)vz.p, (const T*)vzo.p, &rzn, &rzo));
+            }
+            double beta = (rzn - rzo) / rz;
+            if (!(beta >= 0.0)) beta = 0.0;
+            rz = rzn;
+            k_dir2<T><<<grid_for(N), 256, 0, s>>>(N, beta, (const T*)vz.p, (T*)vp.p, (T*)vzo.p);
+            NDL_HIP(hipGetLastError());
+        }
+        // x += ||r|| d
+        {
+            std::vector<int> own((N + 1023) / 1024, 0);
+            DevBuf down, dsc, dact;
+            NDL_TRY(alloc<int>(down, own.size()));
+            NDL_TRY(alloc<double>(dsc, 1));
+            NDL_TRY(alloc<int>(dact, 1));
+            int one = 1;
+            NDL_HIP(hipMemcpyAsync(down.p, own.data(), own.size() * sizeof(int), hipMemcpyHostToDevice, s));
+            NDL_HIP(hipMemcpyAsync(dsc.p, &sc, sizeof(double), hipMemcpyHostToDevice, s));
+            NDL_HIP(hipMemcpyAsync(dact.p, &one, sizeof(int), hipMemcpyHostToDevice, s));
+            k_axpy_outer<T><<<grid_for(N), 256, 0, s>>>((const int*)down.p, N, (double*)vx.p, (const T*)vd.p,
+                                                         (const double*)dsc.p, (const int*)dact.p);
+            NDL_HIP(hipStreamSynchronize(s));
+        }
+    }
+    NDL_HIP(hipMemcpyAsync(x, vx.p, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    NDL_HIP(hipStreamSynchronize(s));
+    double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (rep) {
+        rep->iters = iters;
+        rep->outer = outer;
+        rep->converged = conv;
+        rep->fell_back = jac;
+        rep->rel_res_fp64 = rel;
+        rep->seconds = secs;
+    }
+    if (!conv) {
+        set_error("learned PCG did not reach rtol=%g (rel. residual %g)", rtol, rel);
+        return NDL_ENOCONV;
+    }
+    return NDL_OK;
+}
+
 }  // namespace ndl
 
 extern "C" {
@@ -835,11 +1230,16 @@ int ndl_cg_solve(const ndl_plan* plans, int nprob, const double* const* b, doubl
             return NDL_EINVAL;
         }
     }
-    if (opts && opts->precond == 1) {
-        set_error("learned preconditioner: use ndl_pcg_solve_learned");
-        return NDL_EUNSUPPORTED;
-    }
     hipStream_t s = (hipStream_t)stream;
+    if (opts && opts->precond == 1) {
+        if (!opts->net) { set_error("precond = 1 needs opts->net"); return NDL_EINVAL; }
+        if (nprob != 1 || p0->dim != 3 || p0->n % 8 != 0) {
+            set_error("learned PCG runs one 3D problem with n divisible by 8 per call");
+            return NDL_EUNSUPPORTED;
+        }
+        return p0->prec == NDL_F64 ? pcg_learned_t<double>(plans[0], b[0], x[0], opts, reports, s)
+                                   : pcg_learned_t<float>(plans[0], b[0], x[0], opts, reports, s);
+    }
     return p0->prec == NDL_F64 ? cg_solve_t<double>(plans, nprob, b, x, opts, reports, s)
                                : cg_solve_t<float>(plans, nprob, b, x, opts, reports, s);
 }

@@ -27,7 +27,7 @@ EXPORTS = [
     "ndl_fast_decomposition", "ndl_decompose_node", "ndl_cg_solve", "ndl_net_create", "ndl_net_destroy",
     "ndl_net_save", "ndl_net_load", "ndl_net_num_params", "ndl_net_train_step", "ndl_precond_apply",
     "ndl_autotune", "ndl_last_error", "ndl_version", "ndl_plan_set_variant", "ndl_plan_num_variants",
-    "ndl_net_conv_test",
+    "ndl_net_conv_test", "ndl_net_train_step_energy",
 ]
 
 
@@ -91,6 +91,7 @@ def lib():
             "ndl_autotune": [vp, vp],
             "ndl_plan_set_variant": [vp, C.c_int],
             "ndl_plan_num_variants": [vp, C.POINTER(C.c_int)],
+            "ndl_net_train_step_energy": [vp, vp, C.c_int, vp, vp, C.c_float, C.POINTER(C.c_float), vp],
             "ndl_net_conv_test": [C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp, vp, vp],
         }
         for name, args in sig.items():
@@ -296,3 +297,11 @@ def ndl_precond_apply(net: Net, plan: Plan, r, z, stream=None):
 def ndl_net_conv_test(cin, cout, S, x_bits, w, bias, y=None, dy=None, dx=None, gw=None, gb=None, stream=None):
     _check(lib().ndl_net_conv_test(int(cin), int(cout), int(S), _ptr(x_bits), _ptr(w), _ptr(bias), _ptr(y), _ptr(dy),
                                    _ptr(dx), _ptr(gw), _ptr(gb), _stream(stream)), "ndl_net_conv_test")
+
+
+def ndl_net_train_step_energy(net: Net, plan: Plan, r, e, lr: float, stream=None) -> float:
+    """r, e: [B][n,n,n] fp32 device tensors on the plan's grid (A e = r)."""
+    loss = C.c_float()
+    _check(lib().ndl_net_train_step_energy(net.handle, plan.handle, int(r.shape[0]), _ptr(r), _ptr(e), C.c_float(lr),
+                                           C.byref(loss), _stream(stream)), "ndl_net_train_step_energy")
+    return loss.value

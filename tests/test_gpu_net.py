@@ -29,17 +29,19 @@ def test_conv_layer(cin, cout, S):
     dx = torch.zeros((S, S, S, cin), device="cuda")
     gw = torch.zeros(wk.shape, device="cuda")
     gb = torch.zeros(cout, device="cuda")
-    ndl.ndl_net_conv_test(cin, cout, S, xb, d(wk), d(b), y=y, dy=d(dy), dx=dx, gw=gw, gb=gb)
+    # the input layer (8 channels) needs no data gradient and has none
+    ndl.ndl_net_conv_test(cin, cout, S, xb, d(wk), d(b), y=y, dy=d(dy), dx=dx if cin >= 16 else None, gw=gw, gb=gb)
     torch.cuda.synchronize()
     wr = NO.bf16_round(w)
     yref = NO.conv3d(x, wr, b)
     err = np.abs(y.cpu().numpy() - yref).max() / np.abs(yref).max()
     say("  fwd", err)
     assert err < 1e-5
-    dxref = NO.conv3d_dgrad(NO.bf16_round(dy), wr)
-    err = np.abs(dx.cpu().numpy() - dxref).max() / np.abs(dxref).max()
-    say("  dgrad", err)
-    assert err < 1e-5
+    if cin >= 16:
+        dxref = NO.conv3d_dgrad(NO.bf16_round(dy), wr)
+        err = np.abs(dx.cpu().numpy() - dxref).max() / np.abs(dxref).max()
+        say("  dgrad", err)
+        assert err < 1e-5
     gwref, gbref = NO.conv3d_wgrad(x, dy.astype(np.float32).astype(np.float64))
     got = NO.unpack_weights(gw.cpu().numpy().astype(np.float64), cin)
     err = np.abs(got - gwref).max() / np.abs(gwref).max()

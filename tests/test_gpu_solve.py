@@ -103,3 +103,42 @@ def test_cg_iteration_cap_reports_noconv():
     rc, reps, xs = run(probs, ndl.NDL_F64, rtol=1e-8, max_iter=5)
     assert rc == ndl.NDL_ENOCONV
     assert reps[0].converged == 0 and reps[0].iters <= 5 + 25
+
+
+def test_learned_pcg_converges_and_falls_back():
+    """Flexible PCG with the network (untrained here) still reaches 1e-8: the
+    Jacobi fallback takes over on breakdown or stagnation."""
+    import torch
+    from paper_1905_08375_amd import precond_train as PT
+    say("case learned pcg")
+    n = 32
+    plan, b, feat, w = PT.problem_3d(n, 3)
+    net = ndl.ndl_net_create(seed=3)
+    x = torch.zeros_like(b)
+    rc, reps = ndl.ndl_cg_solve([plan], [b], [x], rtol=1e-8, precond=1, net=net)
+    say("  rc", rc, "iters", reps[0].iters, "fell_back", reps[0].fell_back, "res", reps[0].rel_res_fp64)
+    assert rc == ndl.NDL_OK and reps[0].converged
+    P = O.Problem(dim=3, n=n, R=4, form="div", kernel="frac")
+    d64 = w["delta"].astype(np.float32).astype(np.float64)
+    c64 = w["coef"].astype(np.float32).astype(np.float64)
+    xr = x.cpu().numpy()
+    Ax = -O.apply(P, d64, c64, F.pad(xr, 4))
+    bb = w["b"]
+    assert np.linalg.norm(bb - Ax) / np.linalg.norm(bb) <= 1.05e-8
+
+
+def test_precond_apply_is_finite_and_scale_covariant():
+    import torch
+    from paper_1905_08375_amd import precond_train as PT
+    n = 32
+    plan, b, feat, w = PT.problem_3d(n, 4)
+    net = ndl.ndl_net_create(seed=4)
+    r = torch.randn((n, n, n), device="cuda")
+    z1 = torch.empty_like(r)
+    z2 = torch.empty_like(r)
+    ndl.ndl_precond_apply(net, plan, r, z1)
+    ndl.ndl_precond_apply(net, plan, 3.0 * r, z2)
+    torch.cuda.synchronize()
+    assert torch.isfinite(z1).all()
+    # z = ||r|| M(r / ||r||): scaling r scales z
+    assert torch.allclose(z2, 3.0 * z1, rtol=1e-5, atol=1e-6 * float(z1.abs().max()))
