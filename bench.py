@@ -103,7 +103,7 @@ def bench_apply(prec, fast, steps, warmup):
     return dict(seconds=secs, wall=wall, n_points=n * n, info=info, out=out)
 
 
-def bench_solve(count=64, rtol=1e-8, prec=None):
+def bench_solve(count=64, rtol=1e-8, prec=None, max_iter=None):
     """64 batched case (b) solves on uneven grids {256..1024}^2, m in [2, 8]."""
     import torch
     from paper_1905_08375_amd import fields as F
@@ -122,7 +122,7 @@ def bench_solve(count=64, rtol=1e-8, prec=None):
         xs.append(torch.zeros((n, n), dtype=torch.float64, device="cuda"))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rc, reps = ndl.ndl_cg_solve(plans, bs, xs, rtol=rtol)
+    rc, reps = ndl.ndl_cg_solve(plans, bs, xs, rtol=rtol, max_iter=max_iter or 200000)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     pts = sum(n * n for n in sizes)
@@ -132,7 +132,7 @@ def bench_solve(count=64, rtol=1e-8, prec=None):
             "precision": "fp32 inner (compensated apply), fp64 reductions and refinement"}
 
 
-def bench_pcg_3d(n=256, seed=100, train_steps=0):
+def bench_pcg_3d(n=256, seed=100, train_steps=0, max_iter=None):
     """3D 256^3 case (b) solve to 1e-8: plain Jacobi-CG vs the learned two-level
     preconditioner (weights from precond_train.WEIGHTS when present, else the
     network is trained here on full fields for `train_steps` steps; training
@@ -151,7 +151,7 @@ def bench_pcg_3d(n=256, seed=100, train_steps=0):
         PT.train(net, data, steps=train_steps, log=log)
         train_s = time.perf_counter() - t0
         source = f"trained here ({train_steps} steps)"
-    res = PT.compare(net, n=n, seed=seed)
+    res = PT.compare(net, n=n, seed=seed, max_iter=max_iter)
     res["weights"] = source
     res["training_seconds"] = train_s
     return res
@@ -221,6 +221,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-rows", action="store_true", help="headline only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--only", default="", help="run one row only (profiling): cg64, pcg3d, pd, fast, f64")
+    ap.add_argument("--cg-iters", type=int, default=0, help="cap the solver iterations (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -230,6 +232,13 @@ def main():
     from paper_1905_08375_amd import ndl
     assert torch.cuda.is_available(), "needs a GPU"
     ndl.lib()
+    if args.only:
+        fn = {"cg64": lambda: bench_solve(max_iter=args.cg_iters or None),
+              "pcg3d": lambda: bench_pcg_3d(max_iter=args.cg_iters or None),
+              "pd": bench_pd, "f64": lambda: bench_apply(ndl.NDL_F64, False, args.steps, args.warmup)["seconds"],
+              "fast": lambda: bench_apply(ndl.NDL_F32C, True, args.steps, args.warmup)["seconds"]}[args.only]
+        print(json.dumps({"only": args.only, "result": fn()}, default=str), flush=True)
+        return
 
     log("headline: 2D 1024^2 direct apply, FP32 with Kahan-compensated sums")
     head = bench_apply(ndl.NDL_F32K, False, args.steps, args.warmup)

@@ -218,6 +218,21 @@ __global__ __launch_bounds__(256) void k_direct_nd(const T* __restrict__ u, T* _
     T* tile = reinterpret_cast<T*>(smem_raw);
     const int ncomp = MODEL ? 2 : 1;
     int tot = B.L[0] * B.L[1] * B.L[2];
+    // the half-ball table with this tile's flat LDS offsets (uniform reads in the pair loop)
+    constexpr int kStage = 512;
+    __shared__ int s_off[kStage], s_q[kStage];
+    __shared__ short s_zy[kStage], s_zx[kStage];
+    __shared__ T s_w[kStage];
+    const bool staged = npairs <= kStage;
+    if (staged)
+        for (int p = threadIdx.x; p < npairs; p += blockDim.x) {
+            int4 o = pairs[p];
+            s_off[p] = o.x * B.ls0 + o.y * B.ls1 + o.z;
+            s_q[p] = o.w;
+            s_zy[p] = (short)o.y;
+            s_zx[p] = (short)o.z;
+            s_w[p] = pw[p];
+        }
     int nb = B.tiles[0] * B.tiles[1] * B.tiles[2];
     int t = xcd_tile(blockIdx.x, nb);
     int t2 = t % B.tiles[2];
@@ -246,11 +261,22 @@ __global__ __launch_bounds__(256) void k_direct_nd(const T* __restrict__ u, T* _
         T im2 = POLY && valid ? invm2[gi] : T(0);
         Acc<T> A0, A1;
         for (int p = 0; p < npairs; p++) {
-            int4 o = pairs[p];
-            if (o.w > kw) break;
-            int off = o.x * B.ls0 + o.y * B.ls1 + o.z;
-            if (o.w <= k) {
-                T w = pw[p];
+            int4 o;
+            int off, qw;
+            T w;
+            if (staged) {
+                qw = s_q[p];
+                off = s_off[p];
+                w = s_w[p];
+                o = make_int4(0, MODEL ? (int)s_zy[p] : 0, MODEL ? (int)s_zx[p] : 0, qw);
+            } else {
+                o = pairs[p];
+                qw = o.w;
+                off = o.x * B.ls0 + o.y * B.ls1 + o.z;
+                w = pw[p];
+            }
+            if (qw > kw) break;
+            if (qw <= k) {
                 if (POLY) {
                     T r2 = (T)o.w * im2, g = 0, pp = 1;
                     for (int j = 0; j <= a.K; j++) { g += (T)a.poly[j] * pp; pp *= r2; }
@@ -400,11 +426,13 @@ static ScaleArgs scale_args(const Plan& p)
 // Kernels staging more than 64 KiB of LDS must opt in (gfx950 has 160 KiB per CU).
 static int lds_check(const void* fn, size_t lds)
 {
-    if (lds > 160 * 1024) {
+    if (lds + 16 * 1024 > 160 * 1024) {
         set_error("kernel tile needs %zu B of LDS (horizon too wide for this tile)", lds);
         return NDL_EUNSUPPORTED;
     }
-    if (lds > 64 * 1024) NDL_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    // the kernels also hold up to ~16 KiB of static LDS (staged offset tables)
+    if (lds + 16 * 1024 > 64 * 1024)
+        NDL_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     return NDL_OK;
 }
 

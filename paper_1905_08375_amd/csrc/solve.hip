@@ -27,6 +27,7 @@ namespace ndl {
 // ------------------------------------------------------------------ batched layout
 struct Inst {
     int dim, n, J, kmax;
+    int nq;                  // ball offsets with |z|^2 <= kmax (prefix of the shared table)
     int tiles[3];
     int E[3];
     int64_t N, off;          // points and offset into the concatenated vectors
@@ -79,7 +80,9 @@ __device__ __forceinline__ double block_sum(double v, double* red)
 // the collar takes (delta_i, c_i).  Per pair, in FP64:
 //   a = (delta_i + delta_j) (n/2),  k_ij = ceil(a*a) - 1  (exactly the rule of case (b)),
 //   w = (c'_i + c'_j) |z|^e M / T_e[k_ij],  c' = c n^2 / 2.
-template <typename T, bool DIAG>
+constexpr int kMaxOffs = 512;  // ball offsets staged per item (|z|^2 <= kmax)
+
+template <typename T, bool DIAG, bool DISC>
 __global__ __launch_bounds__(256) void k_div_items(const Inst* __restrict__ insts, const int2* __restrict__ items,
                                                    int nitems, const T* __restrict__ pvec, T* __restrict__ qvec,
                                                    const int4* __restrict__ full, const double* __restrict__ fw,
@@ -91,6 +94,8 @@ __global__ __launch_bounds__(256) void k_div_items(const Inst* __restrict__ inst
     T* tu = reinterpret_cast<T*>(smem_raw);
     __shared__ double red[4];
     __shared__ double tinv_s[256];
+    __shared__ int s_off[kMaxOffs], s_q[kMaxOffs];
+    __shared__ double s_fw[kMaxOffs];
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         int2 item = items[it];
         const Inst I = insts[item.x];
@@ -111,6 +116,14 @@ __global__ __launch_bounds__(256) void k_div_items(const Inst* __restrict__ inst
         const T* cf = static_cast<const T*>(I.coef);
         __syncthreads();
         for (int k = threadIdx.x; k <= I.kmax && k < 256; k += blockDim.x) tinv_s[k] = Tinv[k];
+        // this tile's flat LDS offsets of the ball (uniform reads in the pair loop)
+        const int nq = I.nq < kMaxOffs ? I.nq : kMaxOffs;
+        for (int q = threadIdx.x; q < nq; q += blockDim.x) {
+            int4 o = full[q];
+            s_off[q] = (o.x * L[1] + o.y) * L[2] + o.z;
+            s_q[q] = o.w;
+            s_fw[q] = fw[q];
+        }
         for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
             int l2 = idx % L[2];
             int r = idx / L[2];
@@ -145,16 +158,16 @@ __global__ __launch_bounds__(256) void k_div_items(const Inst* __restrict__ inst
             T u0 = DIAG ? T(0) : tu[cidx];
             Acc<T> acc;
             double dsum = 0.0;
-            for (int q = 0; q < nfull; q++) {
-                int4 o = full[q];
-                if (o.w > I.kmax) break;
+            for (int q = 0; q < nq; q++) {
+                const int off = s_off[q];
+                const int qw = s_q[q];
                 double dj, cj;
-                int off = (o.x * L[1] + o.y) * L[2] + o.z;
                 if (STAGE) {
                     dj = (double)td[cidx + off];
                     cj = (double)tc[cidx + off];
                     if (dj < 0.0) { dj = di; cj = ci; }
                 } else {
+                    int4 o = full[q];
                     int y0 = x0 + o.x, y1 = x1 + o.y, y2 = x2 + o.z;
                     dj = di;
                     cj = ci;
@@ -167,15 +180,15 @@ __global__ __launch_bounds__(256) void k_div_items(const Inst* __restrict__ inst
                 double am = (di + dj) * nh;
                 double tt = am * am;
                 int kij = (int)ceil(tt) - 1;
-                if (o.w > kij) continue;
+                if (qw > kij) continue;
                 double w;
-                if (I.norm == NDL_NORM_DISCRETE) {
-                    w = (cpi + cj * ch) * fw[q] * (kij < 256 ? tinv_s[kij] : Tinv[kij]);
+                if (DISC) {
+                    w = (cpi + cj * ch) * s_fw[q] * (kij < 256 ? tinv_s[kij] : Tinv[kij]);
                 } else {
                     double C = 0.5 * (ci + cj);
                     double dij = (di + dj) * 0.5;
                     double dd2 = pow(dij, (double)(I.dim + 2));
-                    double base = C * pow(am, -I.expo) * I.hd / dd2 * fw[q];
+                    double base = C * pow(am, -I.expo) * I.hd / dd2 * s_fw[q];
                     w = I.norm == NDL_NORM_CONTINUOUS ? base * I.m2 / I.contc : base;
                 }
                 if (DIAG) {
@@ -274,25 +287,44 @@ __global__ __launch_bounds__(256) void k_cg_dir(const Inst* __restrict__ insts, 
     }
 }
 
+// Sum of a problem's item partials by one block (fixed order: strided
+// per-thread sums, then a tree), valid in thread 0.
+__device__ __forceinline__ double problem_sum(const Inst& I, const double* __restrict__ part, double* sh)
+{
+    double a = 0.0;
+    for (int t = threadIdx.x; t < I.nitems; t += blockDim.x) a += part[I.item0 + t];
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
 // Per-problem scalar steps (one thread per problem, items summed in order).
 // phase 0: alpha = rz / p.q ; phase 1: rz_new, rr -> beta, convergence flag.
 __global__ void k_cg_scalars(int nprob, const Inst* __restrict__ insts, Scal* __restrict__ sc,
                              const double* __restrict__ p0, const double* __restrict__ p1, int phase, int max_iter)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double sh[256];
+    int i = blockIdx.x;
     if (i >= nprob) return;
-    Scal S = sc[i];
-    if (S.done) return;
+    if (sc[i].done) return;
     const Inst I = insts[i];
+    double s0 = problem_sum(I, p0, sh);
+    double s1 = phase == 1 ? problem_sum(I, p1, sh) : 0.0;
+    if (threadIdx.x != 0) return;
+    Scal S = sc[i];
     if (phase == 0) {
-        double pq = 0.0;
-        for (int t = 0; t < I.nitems; ++t) pq += p0[I.item0 + t];
+        double pq = s0;
         S.pq = pq;
         S.alpha = (pq > 0.0 && isfinite(pq)) ? S.rz / pq : 0.0;
         if (!(pq > 0.0) || !isfinite(pq)) S.done = 3;  // breakdown: not SPD or NaN
     } else {
-        double rz = 0.0, rr = 0.0;
-        for (int t = 0; t < I.nitems; ++t) { rz += p0[I.item0 + t]; rr += p1[I.item0 + t]; }
+        double rz = s0, rr = s1;
         S.rz_new = rz;
         S.rr = rr;
         S.beta = S.rz != 0.0 ? rz / S.rz : 0.0;
@@ -346,11 +378,13 @@ __global__ __launch_bounds__(256) void k_cg_init(const Inst* __restrict__ insts,
 __global__ void k_cg_start(int nprob, const Inst* __restrict__ insts, Scal* __restrict__ sc,
                            const double* __restrict__ prz, const double* __restrict__ prr, const double* __restrict__ tol2)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double sh[256];
+    int i = blockIdx.x;
     if (i >= nprob) return;
     const Inst I = insts[i];
-    double rz = 0.0, rr = 0.0;
-    for (int t = 0; t < I.nitems; ++t) { rz += prz[I.item0 + t]; rr += prr[I.item0 + t]; }
+    double rz = problem_sum(I, prz, sh);
+    double rr = problem_sum(I, prr, sh);
+    if (threadIdx.x != 0) return;
     Scal S = sc[i];
     S.rz = rz;
     S.rr = rr;
@@ -394,15 +428,16 @@ __global__ __launch_bounds__(256) void k_residual(const Inst* __restrict__ insts
     }
 }
 
+// one block per problem
 __global__ void k_item_sums(int nprob, const Inst* __restrict__ insts, const double* __restrict__ part,
                             double* __restrict__ out)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double sh[256];
+    int i = blockIdx.x;
     if (i >= nprob) return;
     const Inst I = insts[i];
-    double s = 0.0;
-    for (int t = 0; t < I.nitems; ++t) s += part[I.item0 + t];
-    out[i] = s;
+    double s = problem_sum(I, part, sh);
+    if (threadIdx.x == 0) out[i] = s;
 }
 
 // elementwise over the concatenated vectors: dst = (To)(src * scale[prob])
@@ -481,6 +516,13 @@ struct Batch {
 
 static int build_batch(const ndl_plan* plans, int nprob, Batch& B, bool f64_fields, std::vector<DevBuf>& keep)
 {
+    for (int i = 0; i < nprob; ++i) {
+        const Plan& p = *reinterpret_cast<const Plan*>(plans[i]);
+        if ((int)ball_offsets(p.dim, p.kmax, false).size() > kMaxOffs) {
+            set_error("solver: horizon ball of problem %d has more than %d offsets", i, kMaxOffs);
+            return NDL_EUNSUPPORTED;
+        }
+    }
     B.insts.resize(nprob);
     int64_t off = 0;
     for (int i = 0; i < nprob; ++i) {
@@ -490,6 +532,7 @@ static int build_batch(const ndl_plan* plans, int nprob, Batch& B, bool f64_fiel
         I.n = (int)p.n;
         I.J = p.J;
         I.kmax = (int)p.kmax;
+        I.nq = (int)ball_offsets(p.dim, p.kmax, false).size();
         if (p.dim == 2) { I.E[0] = 1; I.E[1] = 16; I.E[2] = 64; }
         else if (p.dim == 3) { I.E[0] = 4; I.E[1] = 8; I.E[2] = 32; }
         else { I.E[0] = 1; I.E[1] = 1; I.E[2] = 1024; }
@@ -551,15 +594,15 @@ template <typename T>
 static int prepare_lds(const Batch& B)
 {
     size_t lds = items_lds<T>(B);
-    if (lds > 160 * 1024) {
+    if (lds + 16 * 1024 > 160 * 1024) {
         set_error("solver tile needs %zu B of LDS (horizon too wide)", lds);
         return NDL_EUNSUPPORTED;
     }
-    if (lds > 64 * 1024) {
-        NDL_HIP(hipFuncSetAttribute((const void*)k_div_items<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)lds));
-        NDL_HIP(hipFuncSetAttribute((const void*)k_div_items<T, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)lds));
+    // plus ~14 KiB of static LDS (reduction, tables)
+    if (lds + 16 * 1024 > 64 * 1024) {
+        const void* fns[] = {(const void*)k_div_items<T, false, true>, (const void*)k_div_items<T, true, true>,
+                             (const void*)k_div_items<T, false, false>, (const void*)k_div_items<T, true, false>};
+        for (const void* f : fns) NDL_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     }
     return NDL_OK;
 }
@@ -572,10 +615,15 @@ static int launch_div_items(const Batch& B, const Inst* d_insts, const int2* d_i
     size_t lds = items_lds<T>(B);
     int nitems = (int)B.items.size();
     unsigned g = (unsigned)std::min(nitems, 256 * 8);
-    if (diag)
-        k_div_items<T, true><<<g, 256, lds, s>>>(d_insts, d_items, nitems, p, q, full, fw, nfull, Tinv, sc, part);
+    bool disc = B.insts[0].norm == NDL_NORM_DISCRETE;
+    if (diag && disc)
+        k_div_items<T, true, true><<<g, 256, lds, s>>>(d_insts, d_items, nitems, p, q, full, fw, nfull, Tinv, sc, part);
+    else if (diag)
+        k_div_items<T, true, false><<<g, 256, lds, s>>>(d_insts, d_items, nitems, p, q, full, fw, nfull, Tinv, sc, part);
+    else if (disc)
+        k_div_items<T, false, true><<<g, 256, lds, s>>>(d_insts, d_items, nitems, p, q, full, fw, nfull, Tinv, sc, part);
     else
-        k_div_items<T, false><<<g, 256, lds, s>>>(d_insts, d_items, nitems, p, q, full, fw, nfull, Tinv, sc, part);
+        k_div_items<T, false, false><<<g, 256, lds, s>>>(d_insts, d_items, nitems, p, q, full, fw, nfull, Tinv, sc, part);
     NDL_HIP(hipGetLastError());
     return NDL_OK;
 }
@@ -690,7 +738,7 @@ static int cg_solve_t(const ndl_plan* plans, int nprob, const double* const* b, 
     NDL_HIP(hipMemsetAsync(vax.p, 0, tot * sizeof(double), s));
     k_residual<T><<<gi, 256, 0, s>>>(di, dit, nitems, (const double*)vb.p, (const double*)vax.p, (double*)vr64.p,
                                       (double*)pn2.p);
-    k_item_sums<<<gp, 64, 0, s>>>(nprob, di, (const double*)pn2.p, (double*)sbn.p);
+    k_item_sums<<<nprob, 256, 0, s>>>(nprob, di, (const double*)pn2.p, (double*)sbn.p);
     std::vector<double> bn2(nprob), res2(nprob);
     NDL_HIP(hipMemcpyAsync(bn2.data(), sbn.p, nprob * sizeof(double), hipMemcpyDeviceToHost, s));
     NDL_HIP(hipStreamSynchronize(s));
@@ -709,11 +757,11 @@ static int cg_solve_t(const ndl_plan* plans, int nprob, const double* const* b, 
         NDL_TRY(launch_div_items<T>(B, di, dit, (const T*)vp.p, (T*)vq.p, (const int4*)d_full.p,
                                     (const double*)d_fw.p, nfull, (const double*)d_Tinv.p, (const Scal*)d_sc.p,
                                     (double*)ppq.p, false, st));
-        k_cg_scalars<<<gp, 64, 0, st>>>(nprob, di, (Scal*)d_sc.p, (const double*)ppq.p, nullptr, 0, max_iter);
+        k_cg_scalars<<<nprob, 256, 0, st>>>(nprob, di, (Scal*)d_sc.p, (const double*)ppq.p, nullptr, 0, max_iter);
         k_cg_update<T><<<gi, 256, 0, st>>>(di, dit, nitems, (const Scal*)d_sc.p, (T*)vd.p, (T*)vr.p, (T*)vz.p,
                                            (const T*)vp.p, (const T*)vq.p, (const T*)vdinv.p, (double*)prz.p,
                                            (double*)prr.p);
-        k_cg_scalars<<<gp, 64, 0, st>>>(nprob, di, (Scal*)d_sc.p, (const double*)prz.p, (const double*)prr.p, 1,
+        k_cg_scalars<<<nprob, 256, 0, st>>>(nprob, di, (Scal*)d_sc.p, (const double*)prz.p, (const double*)prr.p, 1,
                                          max_iter);
         k_cg_dir<T><<<gi, 256, 0, st>>>(di, dit, nitems, (const Scal*)d_sc.p, (const T*)vz.p, (T*)vp.p);
         NDL_HIP(hipGetLastError());
@@ -745,7 +793,7 @@ static int cg_solve_t(const ndl_plan* plans, int nprob, const double* const* b, 
                                          false, s));
         k_residual<double><<<gi, 256, 0, s>>>(di, dit, nitems, (const double*)vb.p, (const double*)vax.p,
                                                (double*)vr64.p, (double*)pn2.p);
-        k_item_sums<<<gp, 64, 0, s>>>(nprob, di, (const double*)pn2.p, (double*)sres.p);
+        k_item_sums<<<nprob, 256, 0, s>>>(nprob, di, (const double*)pn2.p, (double*)sres.p);
         NDL_HIP(hipMemcpyAsync(res2.data(), sres.p, nprob * sizeof(double), hipMemcpyDeviceToHost, s));
         NDL_HIP(hipStreamSynchronize(s));
         bool any = false;
@@ -775,7 +823,7 @@ static int cg_solve_t(const ndl_plan* plans, int nprob, const double* const* b, 
         // reset per-problem scalars; inactive problems start as done
         for (int i = 0; i < nprob; ++i) { hsc[i] = Scal{}; hsc[i].iters = iters[i]; }
         NDL_HIP(hipMemcpyAsync(d_sc.p, hsc.data(), nprob * sizeof(Scal), hipMemcpyHostToDevice, s));
-        k_cg_start<<<gp, 64, 0, s>>>(nprob, di, (Scal*)d_sc.p, (const double*)prz.p, (const double*)prr.p,
+        k_cg_start<<<nprob, 256, 0, s>>>(nprob, di, (Scal*)d_sc.p, (const double*)prz.p, (const double*)prr.p,
                                       (const double*)stol2.p);
         // replay the graph until every active problem has finished its inner solve
         for (;;) {
@@ -803,7 +851,7 @@ static int cg_solve_t(const ndl_plan* plans, int nprob, const double* const* b, 
                                      s));
     k_residual<double><<<gi, 256, 0, s>>>(di, dit, nitems, (const double*)vb.p, (const double*)vax.p,
                                            (double*)vr64.p, (double*)pn2.p);
-    k_item_sums<<<gp, 64, 0, s>>>(nprob, di, (const double*)pn2.p, (double*)sres.p);
+    k_item_sums<<<nprob, 256, 0, s>>>(nprob, di, (const double*)pn2.p, (double*)sres.p);
     NDL_HIP(hipMemcpyAsync(res2.data(), sres.p, nprob * sizeof(double), hipMemcpyDeviceToHost, s));
     for (int i = 0; i < nprob; ++i)
         NDL_HIP(hipMemcpyAsync(x[i], (double*)vx.p + B.insts[i].off, B.insts[i].N * sizeof(double),
@@ -1055,7 +1103,7 @@ static int pcg_learned_t(const ndl_plan plan, const double* b, double* x, const 
     k_recip<T><<<grid_for(N), 256, 0, s>>>((const T*)vq.p, (T*)vdinv.p, N);
     unsigned gi = (unsigned)std::min(nitems, 256 * 8);
     auto sum_items = [&](const double* part, double* out) -> int {
-        k_item_sums<<<1, 64, 0, s>>>(1, di, part, (double*)sres.p);
+        k_item_sums<<<1, 256, 0, s>>>(1, di, part, (double*)sres.p);
         NDL_HIP(hipMemcpyAsync(out, sres.p, sizeof(double), hipMemcpyDeviceToHost, s));
         NDL_HIP(hipStreamSynchronize(s));
         return NDL_OK;

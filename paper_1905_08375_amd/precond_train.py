@@ -92,19 +92,20 @@ def train(net, data, steps=300, batch=2, lr=1e-3, steps_per_field=10, seed=0, lo
     return hist
 
 
-def compare(net, n=256, seed=100, rtol=1e-8):
+def compare(net, n=256, seed=100, rtol=1e-8, max_iter=None):
     """Plain Jacobi-CG vs learned flexible PCG on one held-out field (same outer loop)."""
     import torch
     plan, b, _, _ = problem_3d(n, seed)
     x0 = torch.zeros_like(b)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rc, rep = ndl.ndl_cg_solve([plan], [b], [x0], rtol=rtol)
+    mi = max_iter or 200000
+    rc, rep = ndl.ndl_cg_solve([plan], [b], [x0], rtol=rtol, max_iter=mi)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     x1 = torch.zeros_like(b)
     t0 = time.perf_counter()
-    rc2, rep2 = ndl.ndl_cg_solve([plan], [b], [x1], rtol=rtol, precond=1, net=net)
+    rc2, rep2 = ndl.ndl_cg_solve([plan], [b], [x1], rtol=rtol, precond=1, net=net, max_iter=mi)
     torch.cuda.synchronize()
     t_learn = time.perf_counter() - t0
     plan.close()
