@@ -41,7 +41,7 @@ class ndl_problem(C.Structure):
 class ndl_plan_info(C.Structure):
     _fields_ = [("n_points", C.c_int64), ("k_max", C.c_int64), ("k_min", C.c_int64), ("ncomp", C.c_int32),
                 ("tile_x", C.c_int32), ("tile_y", C.c_int32), ("tile_z", C.c_int32), ("variant", C.c_int32),
-                ("fast_levels", C.c_int32), ("pairs_per_point", C.c_double)]
+                ("fast_levels", C.c_int32), ("pairs_per_point", C.c_double), ("pair_order", C.c_int32)]
 
 
 class ndl_cg_opts(C.Structure):

@@ -10,7 +10,7 @@ from paper_1905_08375_amd import ndl
 KNAME = {ndl.NDL_G_CONST: "const", ndl.NDL_G_INV_R: "inv_r", ndl.NDL_G_FRAC: "frac", ndl.NDL_G_POLY: "poly"}
 NNAME = {ndl.NDL_NORM_DISCRETE: "discrete", ndl.NDL_NORM_CONTINUOUS: "continuous", ndl.NDL_NORM_NONE: "none"}
 
-TOL = {ndl.NDL_F64: 1e-12, ndl.NDL_F32C: 1e-6}
+TOL = {ndl.NDL_F64: 1e-12, ndl.NDL_F32C: 1e-6, ndl.NDL_F32K: 1e-6}
 
 
 def say(*a):
