@@ -19,6 +19,7 @@
 #include <chrono>
 #include <cmath>
 #include <memory>
+#include <type_traits>
 
 #include "common.h"
 
@@ -209,6 +210,205 @@ __global__ __launch_bounds__(256) void k_div_items(const Inst* __restrict__ inst
         }
         if (part) {
             double s = block_sum(dot, red);
+            if (threadIdx.x == 0) part[it] = s;
+        }
+    }
+}
+
+// The same operator for batches of 2D problems with the discrete
+// normalisation, mapped for gfx950: each of the 4 waves of a block covers 4
+// rows of the 16 x 64 tile and each lane 4 nodes of one column, so the
+// uniform per-offset work (offset, |z|^2, |z|^e) is shared by 4 nodes and the
+// partner reads of one offset use immediate LDS offsets from one address.
+// The tile stages m = delta n/2 in FP64 (exact for FP32 delta, so that
+// m_i + m_j is exactly the (delta_i + delta_j) n/2 of the cutoff rule; FP64
+// data stage delta and form (delta_i + delta_j) n/2 as the rule writes it),
+// c n^2/2 and u in the element type.  Per pair:
+//   t = a^2 in FP64 with a as above; the pair is in the ball iff |z|^2 < t,
+//   i.e. |z|^2 <= ceil(t) - 1 = k_ij;  w = (c'_i + c'_j) |z|^e M / T_e[k_ij].
+// The membership test is skipped for offsets inside every pair's ball of the
+// tile (|z|^2 < (2 min m)^2) and the loop ends past the largest
+// (|z|^2 >= (2 max m)^2); a partner outside Omega takes (delta_i, c_i), which
+// only tiles within J of the boundary test for.
+template <typename T, bool DIAG, int JT>
+__global__ __launch_bounds__(256) void k_div2_items(const Inst* __restrict__ insts, const int2* __restrict__ items,
+                                                    int nitems, const T* __restrict__ pvec, T* __restrict__ qvec,
+                                                    const int4* __restrict__ full, const double* __restrict__ fw,
+                                                    const double* __restrict__ Tinv, const Scal* __restrict__ sc,
+                                                    double* __restrict__ part)
+{
+    constexpr bool F32 = sizeof(T) == 4;
+    constexpr int PY = 4;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[8];
+    __shared__ T tinv_s[256];
+    __shared__ int s_q[kMaxOffs];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int2 item = items[it];
+        const Inst I = insts[item.x];
+        if (sc && sc[item.x].done) {
+            if (threadIdx.x == 0 && part) part[it] = 0.0;
+            continue;
+        }
+        int org[3];
+        item_geom<T>(I, item.y, org);
+        // every problem of the batch uses the halo JT >= its own J, so the tile
+        // pitch is a compile-time constant and the partner reads of the PY
+        // nodes of a lane use immediate offsets
+        const int n = I.n;
+        constexpr int J = JT;
+        constexpr int PITCH = 64 + 2 * J, ROWS = 16 + 2 * J, tot = ROWS * PITCH;
+        double* tm = reinterpret_cast<double*>(smem_raw);
+        T* tcc = reinterpret_cast<T*>(tm + tot);
+        T* tu = tcc + tot;
+        const T* p = pvec + I.off;
+        const T* dlt = static_cast<const T*>(I.delta);
+        const T* cf = static_cast<const T*>(I.coef);
+        const double nh = 0.5 * (double)n;
+        const double ch = 0.5 * I.n2;
+        __syncthreads();  // the previous item's readers are done
+        for (int k = threadIdx.x; k <= I.kmax && k < 256; k += blockDim.x) tinv_s[k] = (T)Tinv[k];
+        const int nq = I.nq < kMaxOffs ? I.nq : kMaxOffs;
+        for (int q = threadIdx.x; q < nq; q += blockDim.x) s_q[q] = full[q].w;
+        const int y0 = org[1], x0 = org[2];
+        double mmax = 0.0, mmin = 1e300;
+        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+            const int r = idx / PITCH, c = idx - r * PITCH;
+            const int gy = y0 - J + r, gx = x0 - J + c;
+            const bool in = gy >= 0 && gy < n && gx >= 0 && gx < n;
+            const int64_t gg = (int64_t)gy * n + gx;
+            double m = -1.0;
+            T cc = 0, uu = 0;
+            if (in) {
+                m = F32 ? (double)dlt[gg] * nh : (double)dlt[gg];
+                cc = (T)((double)cf[gg] * ch);
+                if (!DIAG) uu = p[gg];
+                const double ms = F32 ? m : m * nh;
+                mmax = fmax(mmax, ms);
+                mmin = fmin(mmin, ms);
+            }
+            tm[idx] = m;
+            tcc[idx] = cc;
+            tu[idx] = uu;
+        }
+        // block extremes of m (uniform loop bounds)
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            mmax = fmax(mmax, __shfl_xor(mmax, o, 64));
+            mmin = fmin(mmin, __shfl_xor(mmin, o, 64));
+        }
+        if (lane == 0) {
+            red[wv] = mmax;
+            red[4 + wv] = mmin;
+        }
+        __syncthreads();
+        mmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+        mmin = fmin(fmin(red[4], red[5]), fmin(red[6], red[7]));
+        const double tmax = 4.0 * mmax * mmax;  // (2 max m)^2 >= every t of the tile
+        const double tmin = 4.0 * mmin * mmin;
+        const bool edge = y0 - J < 0 || x0 - J < 0 || y0 + 16 + J > n || x0 + 64 + J > n;
+
+        const int x = x0 + lane;
+        const int base = (wv * PY + J) * PITCH + lane + J;
+        double mi[PY];
+        T cci[PY], ui[PY];
+        bool valid[PY];
+        Acc<T> acc[PY];
+        double dsum[PY];
+#pragma unroll
+        for (int j = 0; j < PY; ++j) {
+            // nodes past the grid edge (ragged tiles) compute with m = c = 0,
+            // which keeps every k_ij within the table; they are not stored
+            valid[j] = x < n && y0 + wv * PY + j < n;
+            mi[j] = valid[j] ? tm[base + j * PITCH] : 0.0;
+            cci[j] = valid[j] ? tcc[base + j * PITCH] : T(0);
+            ui[j] = tu[base + j * PITCH];
+            dsum[j] = 0.0;
+        }
+        // offsets [0, p_in) lie inside every pair's ball of the tile, [p_in, p_end)
+        // need the per-pair test, the rest lie outside every ball (the table
+        // is sorted by |z|^2; uniform binary searches)
+        auto first_at_least = [&](double tq) {
+            int lo = 0, hi = nq;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if ((double)s_q[mid] < tq) lo = mid + 1;
+                else hi = mid;
+            }
+            return lo;
+        };
+        const int p_in = first_at_least(tmin);
+        const int p_end = first_at_least(tmax);
+        // one range of offsets; the table entries are uniform (scalar loads)
+        auto run = [&](int pb, int pe, auto edge_c, auto mask_c) {
+            constexpr bool EDGE = decltype(edge_c)::value;
+            constexpr bool MASK = decltype(mask_c)::value;
+            if (pb >= pe) return;
+            // the table entries of the next offset are loaded one iteration
+            // ahead (the table carries one sentinel entry past its end)
+            int4 o = full[pb];
+            double fwq = fw[pb];
+            for (int q = pb; q < pe; ++q) {
+                const int off = o.y * PITCH + o.z;
+                const double qd = (double)o.w;
+                const T fq = (T)fwq;
+                o = full[q + 1];
+                fwq = fw[q + 1];
+#pragma unroll
+                for (int j = 0; j < PY; ++j) {
+                    const int jj = base + j * PITCH + off;
+                    double mj = tm[jj];
+                    T ccj = tcc[jj];
+                    if (EDGE) {
+                        const bool out = mj < 0.0;
+                        mj = out ? mi[j] : mj;
+                        ccj = out ? cci[j] : ccj;
+                    }
+                    const double a = F32 ? mi[j] + mj : (mi[j] + mj) * nh;
+                    const double t = a * a;
+                    int kij = (int)ceil(t) - 1;
+                    if (MASK) kij = max(kij, 0);
+                    T w = (cci[j] + ccj) * tinv_s[kij] * fq;
+                    if (MASK) w = qd < t ? w : T(0);
+                    if (DIAG) {
+                        dsum[j] += (double)w;
+                    } else {
+                        acc[j].fma_(w, tu[jj] - ui[j]);
+                    }
+                }
+                if (!DIAG && F32 && (q & 7) == 7) {
+#pragma unroll
+                    for (int j = 0; j < PY; ++j) acc[j].flush();
+                }
+            }
+        };
+        using yes = std::integral_constant<bool, true>;
+        using no = std::integral_constant<bool, false>;
+        if (edge) {
+            run(0, p_in, yes{}, no{});
+            run(p_in, p_end, yes{}, yes{});
+        } else {
+            run(0, p_in, no{}, no{});
+            run(p_in, p_end, no{}, yes{});
+        }
+        double dot = 0.0;
+        T* qv = qvec + I.off;
+#pragma unroll
+        for (int j = 0; j < PY; ++j) {
+            if (!valid[j]) continue;
+            const int64_t gi = (int64_t)(y0 + wv * PY + j) * n + x;
+            if (DIAG) {
+                qv[gi] = (T)dsum[j];
+            } else {
+                const T val = -acc[j].value();  // A = -L
+                qv[gi] = val;
+                dot += (double)ui[j] * (double)val;
+            }
+        }
+        if (part) {
+            const double s = block_sum(dot, red);
             if (threadIdx.x == 0) part[it] = s;
         }
     }
@@ -581,13 +781,21 @@ static __global__ void k_widen(const T* __restrict__ a, double* __restrict__ b, 
 
 static unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+// 2D batches with the discrete normalisation run the specialised kernel
+static bool use_div2(const Batch& B)
+{
+    return B.dim == 2 && B.insts[0].norm == NDL_NORM_DISCRETE && B.kmax < 256 && B.Jmax >= 1 && B.Jmax <= 8;
+}
+
 template <typename T>
 static size_t items_lds(const Batch& B)
 {
     const Inst& I0 = B.insts[0];
     int L[3] = {I0.E[0] + (B.dim >= 3 ? 2 * B.Jmax : 0), I0.E[1] + (B.dim >= 2 ? 2 * B.Jmax : 0),
                 I0.E[2] + 2 * B.Jmax};
-    return (size_t)L[0] * L[1] * L[2] * sizeof(T) * (sizeof(T) == 4 ? 3 : 1);
+    size_t cells = (size_t)L[0] * L[1] * L[2];
+    if (use_div2(B)) return cells * (sizeof(double) + 2 * sizeof(T));
+    return cells * sizeof(T) * (sizeof(T) == 4 ? 3 : 1);
 }
 
 template <typename T>
@@ -603,6 +811,15 @@ static int prepare_lds(const Batch& B)
         const void* fns[] = {(const void*)k_div_items<T, false, true>, (const void*)k_div_items<T, true, true>,
                              (const void*)k_div_items<T, false, false>, (const void*)k_div_items<T, true, false>};
         for (const void* f : fns) NDL_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        const void* fns2[] = {(const void*)k_div2_items<T, false, 1>, (const void*)k_div2_items<T, true, 1>,
+                              (const void*)k_div2_items<T, false, 2>, (const void*)k_div2_items<T, true, 2>,
+                              (const void*)k_div2_items<T, false, 3>, (const void*)k_div2_items<T, true, 3>,
+                              (const void*)k_div2_items<T, false, 4>, (const void*)k_div2_items<T, true, 4>,
+                              (const void*)k_div2_items<T, false, 5>, (const void*)k_div2_items<T, true, 5>,
+                              (const void*)k_div2_items<T, false, 6>, (const void*)k_div2_items<T, true, 6>,
+                              (const void*)k_div2_items<T, false, 7>, (const void*)k_div2_items<T, true, 7>,
+                              (const void*)k_div2_items<T, false, 8>, (const void*)k_div2_items<T, true, 8>};
+        for (const void* f : fns2) NDL_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     }
     return NDL_OK;
 }
@@ -616,6 +833,29 @@ static int launch_div_items(const Batch& B, const Inst* d_insts, const int2* d_i
     int nitems = (int)B.items.size();
     unsigned g = (unsigned)std::min(nitems, 256 * 8);
     bool disc = B.insts[0].norm == NDL_NORM_DISCRETE;
+    if (use_div2(B)) {
+        switch (B.Jmax) {
+#define NDL_DIV2_CASE(JJ)                                                                                         \
+    case JJ:                                                                                                      \
+        if (diag)                                                                                                 \
+            k_div2_items<T, true, JJ><<<g, 256, lds, s>>>(d_insts, d_items, nitems, p, q, full, fw, Tinv, sc, part); \
+        else                                                                                                      \
+            k_div2_items<T, false, JJ><<<g, 256, lds, s>>>(d_insts, d_items, nitems, p, q, full, fw, Tinv, sc, part); \
+        break;
+            NDL_DIV2_CASE(1)
+            NDL_DIV2_CASE(2)
+            NDL_DIV2_CASE(3)
+            NDL_DIV2_CASE(4)
+            NDL_DIV2_CASE(5)
+            NDL_DIV2_CASE(6)
+            NDL_DIV2_CASE(7)
+            NDL_DIV2_CASE(8)
+#undef NDL_DIV2_CASE
+        default: return NDL_EUNSUPPORTED;
+        }
+        NDL_HIP(hipGetLastError());
+        return NDL_OK;
+    }
     if (diag && disc)
         k_div_items<T, true, true><<<g, 256, lds, s>>>(d_insts, d_items, nitems, p, q, full, fw, nfull, Tinv, sc, part);
     else if (diag)
@@ -656,6 +896,8 @@ static int cg_solve_t(const ndl_plan* plans, int nprob, const double* const* b, 
         fb.push_back(box_offset(B.dim, o));
         fwv.push_back(std::pow(std::sqrt((double)o.q), p0.expo));
     }
+    fb.push_back(make_int4(0, 0, 0, 1 << 30));  // sentinel: the 2D kernel reads one entry ahead
+    fwv.push_back(0.0);
     std::vector<double> shell(B.kmax + 1, 0.0), Tinv(B.kmax + 1, 0.0);
     for (auto& o : full) shell[o.q] += std::pow(std::sqrt((double)o.q), p0.expo + 2.0);
     double acc = 0.0;
@@ -915,6 +1157,8 @@ static int op_build(const Plan& P, OpCache& oc, hipStream_t s)
         fb.push_back(box_offset(oc.B.dim, o));
         fwv.push_back(std::pow(std::sqrt((double)o.q), P.expo));
     }
+    fb.push_back(make_int4(0, 0, 0, 1 << 30));  // sentinel: the 2D kernel reads one entry ahead
+    fwv.push_back(0.0);
     std::vector<double> shell(oc.B.kmax + 1, 0.0), Tinv(oc.B.kmax + 1, 0.0);
     for (auto& o : full) shell[o.q] += std::pow(std::sqrt((double)o.q), P.expo + 2.0);
     double acc = 0.0;
@@ -1052,6 +1296,8 @@ static int pcg_learned_t(const ndl_plan plan, const double* b, double* x, const 
         fb.push_back(box_offset(B.dim, o));
         fwv.push_back(std::pow(std::sqrt((double)o.q), P.expo));
     }
+    fb.push_back(make_int4(0, 0, 0, 1 << 30));  // sentinel: the 2D kernel reads one entry ahead
+    fwv.push_back(0.0);
     std::vector<double> shell(B.kmax + 1, 0.0), Tinv(B.kmax + 1, 0.0);
     for (auto& o : full) shell[o.q] += std::pow(std::sqrt((double)o.q), P.expo + 2.0);
     double acc = 0.0;
