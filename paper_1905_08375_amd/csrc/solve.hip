@@ -215,23 +215,26 @@ __global__ __launch_bounds__(256) void k_div_items(const Inst* __restrict__ inst
     }
 }
 
-// The same operator for batches of 2D problems with the discrete
-// normalisation, mapped for gfx950: each of the 4 waves of a block covers 4
-// rows of the 16 x 64 tile and each lane 4 nodes of one column, so the
-// uniform per-offset work (offset, |z|^2, |z|^e) is shared by 4 nodes and the
-// partner reads of one offset use immediate LDS offsets from one address.
-// The tile stages m = delta n/2 in FP64 (exact for FP32 delta, so that
+// The same operator for batches of 2D and 3D problems with the discrete
+// normalisation, mapped for gfx950: a block covers a 16 x 64 tile (2D, 4
+// waves of 4 rows) or an 8 x 4 x 64 tile (3D, 8 waves of one plane each), and
+// each lane 4 nodes of one column along axis dim-2, so the uniform per-offset
+// work (offset, |z|^2, |z|^e) is shared by 4 nodes and the partner reads of
+// one offset use immediate LDS offsets from one address.
+// 2D tiles stage m = delta n/2 in FP64 (exact for FP32 delta, so that
 // m_i + m_j is exactly the (delta_i + delta_j) n/2 of the cutoff rule; FP64
-// data stage delta and form (delta_i + delta_j) n/2 as the rule writes it),
-// c n^2/2 and u in the element type.  Per pair:
+// data stage delta and form (delta_i + delta_j) n/2 as the rule writes it);
+// 3D tiles (FP32 only) stage delta itself, 4 bytes, and form the same exact
+// FP64 value from it, so that the larger haloed tile keeps two waves per
+// SIMD.  c n^2/2 and u are staged in the element type.  Per pair:
 //   t = a^2 in FP64 with a as above; the pair is in the ball iff |z|^2 < t,
 //   i.e. |z|^2 <= ceil(t) - 1 = k_ij;  w = (c'_i + c'_j) |z|^e M / T_e[k_ij].
 // The membership test is skipped for offsets inside every pair's ball of the
 // tile (|z|^2 < (2 min m)^2) and the loop ends past the largest
 // (|z|^2 >= (2 max m)^2); a partner outside Omega takes (delta_i, c_i), which
 // only tiles within J of the boundary test for.
-template <typename T, bool DIAG, int JT>
-__global__ __launch_bounds__(256) void k_div2_items(const Inst* __restrict__ insts, const int2* __restrict__ items,
+template <typename T, bool DIAG, int JT, int DIM>
+__global__ __launch_bounds__(DIM == 3 ? 512 : 256) void k_div2_items(const Inst* __restrict__ insts, const int2* __restrict__ items,
                                                     int nitems, const T* __restrict__ pvec, T* __restrict__ qvec,
                                                     const int4* __restrict__ full, const double* __restrict__ fw,
                                                     const double* __restrict__ Tinv, const Scal* __restrict__ sc,
@@ -239,8 +242,12 @@ __global__ __launch_bounds__(256) void k_div2_items(const Inst* __restrict__ ins
 {
     constexpr bool F32 = sizeof(T) == 4;
     constexpr int PY = 4;
+    constexpr int NWAVES = DIM == 3 ? 8 : 4;
+    // staged horizon: MT values; SC = already scaled by n/2 (2D FP32 only)
+    using MT = typename std::conditional<DIM == 3, float, double>::type;
+    constexpr bool SC = DIM == 2 && F32;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double red[8];
+    __shared__ double red[16];
     __shared__ T tinv_s[256];
     __shared__ int s_q[kMaxOffs];
     const int lane = threadIdx.x & 63;
@@ -259,8 +266,10 @@ __global__ __launch_bounds__(256) void k_div2_items(const Inst* __restrict__ ins
         // nodes of a lane use immediate offsets
         const int n = I.n;
         constexpr int J = JT;
-        constexpr int PITCH = 64 + 2 * J, ROWS = 16 + 2 * J, tot = ROWS * PITCH;
-        double* tm = reinterpret_cast<double*>(smem_raw);
+        constexpr int TZ = DIM == 3 ? 8 : 1, TY = DIM == 3 ? 4 : 16, HZ = DIM == 3 ? J : 0;
+        constexpr int PITCH = 64 + 2 * J, SY = TY + 2 * J, SZ = TZ + 2 * HZ;
+        constexpr int PLANE = SY * PITCH, tot = SZ * PLANE;
+        MT* tm = reinterpret_cast<MT*>(smem_raw);
         T* tcc = reinterpret_cast<T*>(tm + tot);
         T* tu = tcc + tot;
         const T* p = pvec + I.off;
@@ -272,20 +281,22 @@ __global__ __launch_bounds__(256) void k_div2_items(const Inst* __restrict__ ins
         for (int k = threadIdx.x; k <= I.kmax && k < 256; k += blockDim.x) tinv_s[k] = (T)Tinv[k];
         const int nq = I.nq < kMaxOffs ? I.nq : kMaxOffs;
         for (int q = threadIdx.x; q < nq; q += blockDim.x) s_q[q] = full[q].w;
-        const int y0 = org[1], x0 = org[2];
+        const int z0 = org[0], y0 = org[1], x0 = org[2];
+        const int nz = DIM == 3 ? n : 1;
         double mmax = 0.0, mmin = 1e300;
         for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-            const int r = idx / PITCH, c = idx - r * PITCH;
-            const int gy = y0 - J + r, gx = x0 - J + c;
-            const bool in = gy >= 0 && gy < n && gx >= 0 && gx < n;
-            const int64_t gg = (int64_t)gy * n + gx;
-            double m = -1.0;
+            const int sz = idx / PLANE, rem = idx - sz * PLANE;
+            const int r = rem / PITCH, c = rem - r * PITCH;
+            const int gz = z0 - HZ + sz, gy = y0 - J + r, gx = x0 - J + c;
+            const bool in = gz >= 0 && gz < nz && gy >= 0 && gy < n && gx >= 0 && gx < n;
+            const int64_t gg = ((int64_t)gz * n + gy) * n + gx;
+            MT m = MT(-1);
             T cc = 0, uu = 0;
             if (in) {
-                m = F32 ? (double)dlt[gg] * nh : (double)dlt[gg];
+                m = SC ? (MT)((double)dlt[gg] * nh) : (MT)dlt[gg];
                 cc = (T)((double)cf[gg] * ch);
                 if (!DIAG) uu = p[gg];
-                const double ms = F32 ? m : m * nh;
+                const double ms = SC ? (double)m : (double)m * nh;
                 mmax = fmax(mmax, ms);
                 mmin = fmin(mmin, ms);
             }
@@ -301,17 +312,25 @@ __global__ __launch_bounds__(256) void k_div2_items(const Inst* __restrict__ ins
         }
         if (lane == 0) {
             red[wv] = mmax;
-            red[4 + wv] = mmin;
+            red[8 + wv] = mmin;
         }
         __syncthreads();
-        mmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-        mmin = fmin(fmin(red[4], red[5]), fmin(red[6], red[7]));
+        mmax = red[0];
+        mmin = red[8];
+#pragma unroll
+        for (int w = 1; w < NWAVES; ++w) {
+            mmax = fmax(mmax, red[w]);
+            mmin = fmin(mmin, red[8 + w]);
+        }
         const double tmax = 4.0 * mmax * mmax;  // (2 max m)^2 >= every t of the tile
         const double tmin = 4.0 * mmin * mmin;
-        const bool edge = y0 - J < 0 || x0 - J < 0 || y0 + 16 + J > n || x0 + 64 + J > n;
+        const bool edge = z0 - HZ < 0 || z0 + TZ + HZ > nz || y0 - J < 0 || x0 - J < 0 || y0 + TY + J > n ||
+                          x0 + 64 + J > n;
 
         const int x = x0 + lane;
-        const int base = (wv * PY + J) * PITCH + lane + J;
+        // 2D: wave wv holds rows 4 wv .. 4 wv + 3; 3D: plane wv, rows 0..3
+        const int wz = DIM == 3 ? wv : 0, wy = DIM == 3 ? 0 : wv * PY;
+        const int base = (wz + HZ) * PLANE + (wy + J) * PITCH + lane + J;
         double mi[PY];
         T cci[PY], ui[PY];
         bool valid[PY];
@@ -321,8 +340,8 @@ __global__ __launch_bounds__(256) void k_div2_items(const Inst* __restrict__ ins
         for (int j = 0; j < PY; ++j) {
             // nodes past the grid edge (ragged tiles) compute with m = c = 0,
             // which keeps every k_ij within the table; they are not stored
-            valid[j] = x < n && y0 + wv * PY + j < n;
-            mi[j] = valid[j] ? tm[base + j * PITCH] : 0.0;
+            valid[j] = x < n && y0 + wy + j < n && z0 + wz < nz;
+            mi[j] = valid[j] ? (double)tm[base + j * PITCH] : 0.0;
             cci[j] = valid[j] ? tcc[base + j * PITCH] : T(0);
             ui[j] = tu[base + j * PITCH];
             dsum[j] = 0.0;
@@ -351,7 +370,7 @@ __global__ __launch_bounds__(256) void k_div2_items(const Inst* __restrict__ ins
             int4 o = full[pb];
             double fwq = fw[pb];
             for (int q = pb; q < pe; ++q) {
-                const int off = o.y * PITCH + o.z;
+                const int off = (DIM == 3 ? o.x * PLANE : 0) + o.y * PITCH + o.z;
                 const double qd = (double)o.w;
                 const T fq = (T)fwq;
                 o = full[q + 1];
@@ -359,14 +378,14 @@ __global__ __launch_bounds__(256) void k_div2_items(const Inst* __restrict__ ins
 #pragma unroll
                 for (int j = 0; j < PY; ++j) {
                     const int jj = base + j * PITCH + off;
-                    double mj = tm[jj];
+                    double mj = (double)tm[jj];
                     T ccj = tcc[jj];
                     if (EDGE) {
                         const bool out = mj < 0.0;
                         mj = out ? mi[j] : mj;
                         ccj = out ? cci[j] : ccj;
                     }
-                    const double a = F32 ? mi[j] + mj : (mi[j] + mj) * nh;
+                    const double a = SC ? mi[j] + mj : (mi[j] + mj) * nh;
                     const double t = a * a;
                     int kij = (int)ceil(t) - 1;
                     if (MASK) kij = max(kij, 0);
@@ -398,7 +417,7 @@ __global__ __launch_bounds__(256) void k_div2_items(const Inst* __restrict__ ins
 #pragma unroll
         for (int j = 0; j < PY; ++j) {
             if (!valid[j]) continue;
-            const int64_t gi = (int64_t)(y0 + wv * PY + j) * n + x;
+            const int64_t gi = ((int64_t)(z0 + wz) * n + (y0 + wy + j)) * n + x;
             if (DIAG) {
                 qv[gi] = (T)dsum[j];
             } else {
@@ -734,7 +753,7 @@ static int build_batch(const ndl_plan* plans, int nprob, Batch& B, bool f64_fiel
         I.kmax = (int)p.kmax;
         I.nq = (int)ball_offsets(p.dim, p.kmax, false).size();
         if (p.dim == 2) { I.E[0] = 1; I.E[1] = 16; I.E[2] = 64; }
-        else if (p.dim == 3) { I.E[0] = 4; I.E[1] = 8; I.E[2] = 32; }
+        else if (p.dim == 3) { I.E[0] = 8; I.E[1] = 4; I.E[2] = 64; }
         else { I.E[0] = 1; I.E[1] = 1; I.E[2] = 1024; }
         int ext[3] = {p.dim >= 3 ? (int)p.n : 1, p.dim >= 2 ? (int)p.n : 1, (int)p.n};
         int nt = 1;
@@ -781,10 +800,16 @@ static __global__ void k_widen(const T* __restrict__ a, double* __restrict__ b, 
 
 static unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-// 2D batches with the discrete normalisation run the specialised kernel
-static bool use_div2(const Batch& B)
+// Batches with the discrete normalisation run the specialised kernel: 2D with
+// halo J <= 8, and 3D FP32 with J <= 3 (its 8 x 4 x 64 tile and halo must fit
+// the LDS of one CU).
+template <typename T>
+static bool use_div_spec(const Batch& B)
 {
-    return B.dim == 2 && B.insts[0].norm == NDL_NORM_DISCRETE && B.kmax < 256 && B.Jmax >= 1 && B.Jmax <= 8;
+    if (B.insts[0].norm != NDL_NORM_DISCRETE || B.kmax >= 256 || B.Jmax < 1) return false;
+    if (B.dim == 2) return B.Jmax <= 8;
+    if (B.dim == 3) return sizeof(T) == 4 && B.Jmax <= 3;
+    return false;
 }
 
 template <typename T>
@@ -794,7 +819,7 @@ static size_t items_lds(const Batch& B)
     int L[3] = {I0.E[0] + (B.dim >= 3 ? 2 * B.Jmax : 0), I0.E[1] + (B.dim >= 2 ? 2 * B.Jmax : 0),
                 I0.E[2] + 2 * B.Jmax};
     size_t cells = (size_t)L[0] * L[1] * L[2];
-    if (use_div2(B)) return cells * (sizeof(double) + 2 * sizeof(T));
+    if (use_div_spec<T>(B)) return cells * ((B.dim == 3 ? sizeof(float) : sizeof(double)) + 2 * sizeof(T));
     return cells * sizeof(T) * (sizeof(T) == 4 ? 3 : 1);
 }
 
@@ -811,14 +836,17 @@ static int prepare_lds(const Batch& B)
         const void* fns[] = {(const void*)k_div_items<T, false, true>, (const void*)k_div_items<T, true, true>,
                              (const void*)k_div_items<T, false, false>, (const void*)k_div_items<T, true, false>};
         for (const void* f : fns) NDL_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        const void* fns2[] = {(const void*)k_div2_items<T, false, 1>, (const void*)k_div2_items<T, true, 1>,
-                              (const void*)k_div2_items<T, false, 2>, (const void*)k_div2_items<T, true, 2>,
-                              (const void*)k_div2_items<T, false, 3>, (const void*)k_div2_items<T, true, 3>,
-                              (const void*)k_div2_items<T, false, 4>, (const void*)k_div2_items<T, true, 4>,
-                              (const void*)k_div2_items<T, false, 5>, (const void*)k_div2_items<T, true, 5>,
-                              (const void*)k_div2_items<T, false, 6>, (const void*)k_div2_items<T, true, 6>,
-                              (const void*)k_div2_items<T, false, 7>, (const void*)k_div2_items<T, true, 7>,
-                              (const void*)k_div2_items<T, false, 8>, (const void*)k_div2_items<T, true, 8>};
+        const void* fns2[] = {(const void*)k_div2_items<T, false, 1, 2>, (const void*)k_div2_items<T, true, 1, 2>,
+                              (const void*)k_div2_items<T, false, 2, 2>, (const void*)k_div2_items<T, true, 2, 2>,
+                              (const void*)k_div2_items<T, false, 3, 2>, (const void*)k_div2_items<T, true, 3, 2>,
+                              (const void*)k_div2_items<T, false, 4, 2>, (const void*)k_div2_items<T, true, 4, 2>,
+                              (const void*)k_div2_items<T, false, 5, 2>, (const void*)k_div2_items<T, true, 5, 2>,
+                              (const void*)k_div2_items<T, false, 6, 2>, (const void*)k_div2_items<T, true, 6, 2>,
+                              (const void*)k_div2_items<T, false, 7, 2>, (const void*)k_div2_items<T, true, 7, 2>,
+                              (const void*)k_div2_items<T, false, 8, 2>, (const void*)k_div2_items<T, true, 8, 2>,
+                              (const void*)k_div2_items<T, false, 1, 3>, (const void*)k_div2_items<T, true, 1, 3>,
+                              (const void*)k_div2_items<T, false, 2, 3>, (const void*)k_div2_items<T, true, 2, 3>,
+                              (const void*)k_div2_items<T, false, 3, 3>, (const void*)k_div2_items<T, true, 3, 3>};
         for (const void* f : fns2) NDL_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     }
     return NDL_OK;
@@ -833,23 +861,30 @@ static int launch_div_items(const Batch& B, const Inst* d_insts, const int2* d_i
     int nitems = (int)B.items.size();
     unsigned g = (unsigned)std::min(nitems, 256 * 8);
     bool disc = B.insts[0].norm == NDL_NORM_DISCRETE;
-    if (use_div2(B)) {
-        switch (B.Jmax) {
-#define NDL_DIV2_CASE(JJ)                                                                                         \
-    case JJ:                                                                                                      \
+    if (use_div_spec<T>(B)) {
+        const int key = B.dim * 16 + B.Jmax;
+        const unsigned nt = B.dim == 3 ? 512u : 256u;
+        switch (key) {
+#define NDL_DIV2_CASE(DD, JJ)                                                                                     \
+    case DD * 16 + JJ:                                                                                            \
         if (diag)                                                                                                 \
-            k_div2_items<T, true, JJ><<<g, 256, lds, s>>>(d_insts, d_items, nitems, p, q, full, fw, Tinv, sc, part); \
+            k_div2_items<T, true, JJ, DD><<<g, nt, lds, s>>>(d_insts, d_items, nitems, p, q, full, fw, Tinv, sc,   \
+                                                              part);                                              \
         else                                                                                                      \
-            k_div2_items<T, false, JJ><<<g, 256, lds, s>>>(d_insts, d_items, nitems, p, q, full, fw, Tinv, sc, part); \
+            k_div2_items<T, false, JJ, DD><<<g, nt, lds, s>>>(d_insts, d_items, nitems, p, q, full, fw, Tinv, sc,  \
+                                                               part);                                             \
         break;
-            NDL_DIV2_CASE(1)
-            NDL_DIV2_CASE(2)
-            NDL_DIV2_CASE(3)
-            NDL_DIV2_CASE(4)
-            NDL_DIV2_CASE(5)
-            NDL_DIV2_CASE(6)
-            NDL_DIV2_CASE(7)
-            NDL_DIV2_CASE(8)
+            NDL_DIV2_CASE(2, 1)
+            NDL_DIV2_CASE(2, 2)
+            NDL_DIV2_CASE(2, 3)
+            NDL_DIV2_CASE(2, 4)
+            NDL_DIV2_CASE(2, 5)
+            NDL_DIV2_CASE(2, 6)
+            NDL_DIV2_CASE(2, 7)
+            NDL_DIV2_CASE(2, 8)
+            NDL_DIV2_CASE(3, 1)
+            NDL_DIV2_CASE(3, 2)
+            NDL_DIV2_CASE(3, 3)
 #undef NDL_DIV2_CASE
         default: return NDL_EUNSUPPORTED;
         }

@@ -137,8 +137,10 @@ def test_precond_apply_is_finite_and_scale_covariant():
     z1 = torch.empty_like(r)
     z2 = torch.empty_like(r)
     ndl.ndl_precond_apply(net, plan, r, z1)
-    ndl.ndl_precond_apply(net, plan, 3.0 * r, z2)
+    ndl.ndl_precond_apply(net, plan, 4.0 * r, z2)
     torch.cuda.synchronize()
     assert torch.isfinite(z1).all()
-    # z = ||r|| M(r / ||r||): scaling r scales z
-    assert torch.allclose(z2, 3.0 * z1, rtol=1e-5, atol=1e-6 * float(z1.abs().max()))
+    # z = ||r|| M(r / ||r||): scaling r scales z.  The factor is a power of two
+    # so that r / ||r|| is bitwise the same for both calls (any other factor
+    # perturbs it by an ulp, which can flip the BF16 rounding of an input).
+    assert torch.allclose(z2, 4.0 * z1, rtol=1e-6, atol=1e-7 * float(z1.abs().max()))
