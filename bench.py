@@ -97,15 +97,18 @@ def src_hash(*names):
     return h.hexdigest()[:16]
 
 
-def load_traffic(tag, kernel_src):
+def load_traffic(tag, kernel_src, variant=None):
     """HBM traffic per launch measured with rocprofv3 counters (profiles/), or None
-    when the kernel source changed since the counters were taken."""
+    when the kernel source changed since the counters were taken or the timed
+    launch used another tile variant than the measured one."""
     path = os.path.join(ROOT, "profiles", f"traffic_{tag}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
     if rec.get("src_hash") != src_hash(*kernel_src):
+        return None
+    if variant is not None and rec.get("variant", variant) != variant:
         return None
     return rec.get("bytes_per_launch")
 
@@ -131,13 +134,16 @@ def c2_inputs(prec):
     return w, n, R, d, c, u
 
 
-def bench_apply(prec, fast, steps, warmup):
+def bench_apply(prec, fast, steps, warmup, variant=None):
     import torch
     from paper_1905_08375_amd import ndl
     w, n, R, d, c, u = c2_inputs(prec)
     plan = ndl.ndl_plan_create(ndl.make_problem(2, n, R, d, c, prec=prec), want_fast=fast, keep=(d, c))
     if not fast:
-        ndl.ndl_autotune(plan)  # plan-time tile choice (excluded from timing)
+        if variant is None:
+            ndl.ndl_autotune(plan)  # plan-time tile choice (excluded from timing)
+        else:
+            ndl.ndl_plan_set_variant(plan, variant)  # a fixed tile (profiling runs)
     out = torch.empty((n, n), dtype=u.dtype, device="cuda")
     fn = (lambda: ndl.ndl_apply_fast(plan, u, out, 1)) if fast else (lambda: ndl.ndl_apply(plan, u, out, 1))
     fn()
@@ -270,6 +276,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", default="", help="run one row only (profiling): cg64, pcg3d, pd, fast, f64")
     ap.add_argument("--cg-iters", type=int, default=0, help="cap the solver iterations (profiling)")
+    ap.add_argument("--variant", type=int, default=None,
+                    help="fixed tile variant for the headline instead of the autotuner's (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -288,12 +296,12 @@ def main():
         return
 
     log("headline: 2D 1024^2 direct apply, FP32 with Kahan-compensated sums")
-    head = bench_apply(ndl.NDL_F32K, False, args.steps, args.warmup)
+    head = bench_apply(ndl.NDL_F32K, False, args.steps, args.warmup, args.variant)
     N = head["n_points"]
     per = head["seconds"] / args.steps
     value = N * args.steps / head["seconds"] / 1e9
     alg_bytes = 16.0 * N  # u, k_i, s_i read once, Lu written once, 4 B each
-    traffic = load_traffic("c2_direct_f32k", ["direct2d.inc"])
+    traffic = load_traffic("c2_direct_f32k", ["direct2d.inc"], int(head["info"].variant))
     roof = {"bound": "hbm", "achieved": alg_bytes / per / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": alg_bytes / per / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "k_nd2<float,J=%d,E=-3,PY,NW,MODE=2,%s> tile %dx%d (FP32, Kahan)" % (
@@ -341,7 +349,8 @@ def main():
         "config": {"workload": "2d-nonlocal-diffusion-1024x1024-variable-horizon-m2to6-frac-s0.5-direct",
                    "n": 1024, "collar": 6, "k_max": int(head["info"].k_max), "k_min": int(head["info"].k_min),
                    "precision": "fp32-storage-fp32-kahan-sums", "parallelism": "single-gpu",
-                   "tile": [int(head["info"].tile_x), int(head["info"].tile_y)]},
+                   "tile": [int(head["info"].tile_x), int(head["info"].tile_y)],
+                   "tile_variant": int(head["info"].variant)},
         "roofline": roof,
         "cpu_baseline": cpu,
         "rows": rows,
