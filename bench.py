@@ -221,11 +221,13 @@ def bench_pd(steps=5, batch=8, n=2048):
     u = torch.from_numpy(w["u"].astype(np.float32)).cuda()
     plan = ndl.ndl_plan_create(ndl.make_problem(2, n, R, d, c, model=ndl.NDL_PERIDYNAMIC, kernel=ndl.NDL_G_INV_R,
                                                 prec=ndl.NDL_F32K), keep=(d, c))
+    ndl.ndl_autotune(plan)
     out = torch.empty((batch, 2, n, n), dtype=torch.float32, device="cuda")
     secs, _ = timed(lambda: ndl.ndl_apply(plan, u, out, batch), steps, 1)
     per = secs / steps
+    inf = plan.info()
     return {"ms_per_batch_apply": per * 1e3, "gpoint_fields_per_s": batch * n * n / per / 1e9,
-            "pairs_per_point": plan.info().pairs_per_point}
+            "pairs_per_point": inf.pairs_per_point, "tile": [inf.tile_x, inf.tile_y]}
 
 
 def bench_1d(steps=200):

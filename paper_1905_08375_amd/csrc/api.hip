@@ -142,9 +142,9 @@ int ndl_plan_get_info(ndl_plan plan, ndl_plan_info* info)
     info->tile_y = p->tile_y;
     info->tile_z = p->tile_z;
     if (direct_2d_applies(*p)) {
-        variant_tile_2d(p->variant, &info->tile_x, &info->tile_y);
+        variant_tile_2d(*p, p->variant, &info->tile_x, &info->tile_y);
         info->tile_z = 1;
-        info->pair_order = variant_order_2d(p->variant);
+        info->pair_order = variant_order_2d(*p, p->variant);
     }
     info->variant = p->variant;
     info->fast_levels = p->fast ? p->fast_S + 1 : 0;

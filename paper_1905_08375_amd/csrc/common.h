@@ -168,7 +168,7 @@ int launch_direct_2d_f64(Plan& p, const void* u, void* Lu, int batch, hipStream_
 int launch_direct_2d_f32c(Plan& p, const void* u, void* Lu, int batch, hipStream_t s);
 int launch_direct_2d_f32k(Plan& p, const void* u, void* Lu, int batch, hipStream_t s);
 int num_variants_2d();
-void variant_tile_2d(int variant, int* tx, int* ty);
-int variant_order_2d(int variant);
+void variant_tile_2d(const Plan& p, int variant, int* tx, int* ty);
+int variant_order_2d(const Plan& p, int variant);
 
 }  // namespace ndl

@@ -98,6 +98,40 @@ def test_pd_batched(prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_pd_every_tile_variant(prec):
+    """Peridynamics on a ragged 2D grid (horizon up to 12 nodes): every tile the
+    autotuner may pick matches the oracle, all bitwise alike (one pair order)."""
+    import torch
+    from gpuhelp import dev
+    say(f"case pd variants prec={prec}")
+    n, R, B = 83, 12, 2
+    g = np.random.default_rng(12)
+    X = F.mesh(n, 2)
+    delta = (7.5 + 4.5 * np.sin(2 * np.pi * X[0]) * np.cos(2 * np.pi * X[1])) / n
+    c = g.uniform(0.5, 2.0, (n, n))
+    u = np.stack([np.stack([F.pad(F.grf(n, 2, 1e-3, 0.1, 9, 5 * b + q), R) for q in range(2)]) for b in range(B)])
+    u += 1e-4 * g.standard_normal(u.shape)
+    kw = dict(model=ndl.NDL_PERIDYNAMIC, kernel=ndl.NDL_G_INV_R)
+    refs = [oracle_apply(2, n, R, delta, c, u[b], prec, **kw) for b in range(B)]
+    d_d, d_c, d_u = dev(delta, prec), dev(c, prec), dev(u, prec)
+    plan = ndl.ndl_plan_create(ndl.make_problem(2, n, R, d_d, d_c, model=ndl.NDL_PERIDYNAMIC,
+                                                kernel=ndl.NDL_G_INV_R, prec=prec), keep=(d_d, d_c))
+    out = torch.zeros((B, 2, n, n), dtype=d_u.dtype, device="cuda")
+    first = None
+    for v in range(ndl.ndl_plan_num_variants(plan)):
+        ndl.ndl_plan_set_variant(plan, v)
+        out.zero_()
+        ndl.ndl_apply(plan, d_u, out, B)
+        torch.cuda.synchronize()
+        o = out.cpu().numpy()
+        for b in range(B):
+            assert rel_l2(o[b], refs[b]) <= TOL[prec], (v, b)
+        first = o if first is None else first
+        assert np.array_equal(o, first), v
+        assert plan.info().pair_order == 1
+
+
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("dim,n,R", [(2, 70, 8), (3, 18, 4), (1, 200, 9)])
 def test_div(prec, dim, n, R):
     say(f"case div dim={dim} prec={prec}")
