@@ -210,6 +210,48 @@ def bench_pcg_3d(n=256, seed=100, train_steps=0, max_iter=None):
     return res
 
 
+def bench_sweep(n=1024, ms=(2, 4, 8, 16, 32, 64), example1=True):
+    """Direct sum vs the Section 3 evaluation for the constant profile (p^0 = g
+    exactly, so the hierarchical path is pure panel sums) at growing horizon
+    m = delta n; the last point is the paper's Example 1 (delta = 1/2, direct
+    sum out of reach of the LDS tile, hierarchical only)."""
+    import torch
+    from paper_1905_08375_amd import fields as F
+    from paper_1905_08375_amd import ndl
+    prec = ndl.NDL_F32C
+    out = []
+    cases = [(m, m / n) for m in ms] + ([(n // 2, 0.5)] if example1 else [])
+    u_base = F.grf(n, 2, 1.0, 0.1, 6, 1)
+    c = torch.from_numpy(np.exp(F.grf(n, 2, 0.5, 0.1, 6, 2)).astype(np.float32)).cuda()
+    for m, delta in cases:
+        R = int(np.ceil(m)) + 1
+        d = torch.full((n, n), delta, dtype=torch.float32, device="cuda")
+        u = torch.from_numpy(F.pad(u_base, R).astype(np.float32)).cuda()  # zero collar
+        plan = ndl.ndl_plan_create(ndl.make_problem(2, n, R, d, c, kernel=ndl.NDL_G_CONST, prec=prec), want_fast=1,
+                                   keep=(d, c))
+        o = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        row = {"m": m, "neighbours_per_node": plan.info().pairs_per_point}
+
+        def run(fn):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            first = time.perf_counter() - t0
+            k = int(max(2, min(50, 0.25 / max(first, 1e-6))))
+            secs, _ = timed(fn, k, 1)
+            return secs / k
+
+        row["fast_ms"] = run(lambda: ndl.ndl_apply_fast(plan, u, o, 1)) * 1e3
+        if delta < 0.5:
+            row["direct_ms"] = run(lambda: ndl.ndl_apply(plan, u, o, 1)) * 1e3
+            row["fast_speedup"] = row["direct_ms"] / row["fast_ms"]
+        plan.close()
+        out.append(row)
+    return {"n": n, "profile": "const (p^0 exact)", "precision": "fp32 data, fp64 panel sums", "points": out}
+
+
 def bench_pd(steps=5, batch=8, n=2048):
     import torch
     from paper_1905_08375_amd import fields as F
@@ -276,7 +318,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-rows", action="store_true", help="headline only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", default="", help="run one row only (profiling): cg64, pcg3d, pd, fast, f64")
+    ap.add_argument("--only", default="", help="run one row only (profiling): cg64, pcg3d, pd, sweep, fast, f64")
     ap.add_argument("--cg-iters", type=int, default=0, help="cap the solver iterations (profiling)")
     ap.add_argument("--variant", type=int, default=None,
                     help="fixed tile variant for the headline instead of the autotuner's (profiling runs)")
@@ -292,7 +334,7 @@ def main():
     if args.only:
         fn = {"cg64": lambda: bench_solve(max_iter=args.cg_iters or None),
               "pcg3d": lambda: bench_pcg_3d(max_iter=args.cg_iters or None),
-              "pd": bench_pd, "f64": lambda: bench_apply(ndl.NDL_F64, False, args.steps, args.warmup)["seconds"],
+              "pd": bench_pd, "sweep": bench_sweep, "f64": lambda: bench_apply(ndl.NDL_F64, False, args.steps, args.warmup)["seconds"],
               "fast": lambda: bench_apply(ndl.NDL_F32C, True, args.steps, args.warmup)["seconds"]}[args.only]
         print(json.dumps({"only": args.only, "result": fn()}, default=str), flush=True)
         return
@@ -326,6 +368,8 @@ def main():
             log("row:", nm)
             r = bench_apply(prec, True, k, 20)
             rows[nm] = {"gpoint_per_s": N * k / r["seconds"] / 1e9, "us_per_apply": r["seconds"] / k * 1e6}
+        log("row: direct vs hierarchical sweep over the horizon (constant profile)")
+        rows["sweep_const_2d_1024"] = bench_sweep()
         log("row: 1D 4096 direct FP64")
         rows["direct_1d_4096_f64"] = bench_1d()
         log("row: peridynamics 2048^2 x 8 fields")
