@@ -192,18 +192,19 @@ def bench_pcg_3d(n=256, seed=100, train_steps=0, max_iter=None):
     time is reported separately and is not part of the solve times)."""
     from paper_1905_08375_amd import ndl
     from paper_1905_08375_amd import precond_train as PT
-    net = ndl.ndl_net_create(seed=1)
-    source = "untrained"
+    source = "untrained (output layer at zero: plain Jacobi)"
     train_s = 0.0
     if os.path.exists(PT.WEIGHTS):
-        ndl.ndl_net_load(net, PT.WEIGHTS)
-        source = os.path.relpath(PT.WEIGHTS, ROOT)
-    elif train_steps > 0:
-        t0 = time.perf_counter()
-        data = PT.make_pairs(n, range(2), ks=(16, 64, 256), log=log)
-        PT.train(net, data, steps=train_steps, log=log)
-        train_s = time.perf_counter() - t0
-        source = f"trained here ({train_steps} steps)"
+        net = PT.load_net(PT.WEIGHTS)
+        source = os.path.relpath(PT.WEIGHTS, ROOT) + " (linear mode)"
+    else:
+        net = PT.new_net(seed=1)
+        if train_steps > 0:
+            t0 = time.perf_counter()
+            data = PT.make_pairs(n, range(2), ks=PT.TRAIN_KS, log=log)
+            PT.train(net, data, steps=train_steps, log=log)
+            train_s = time.perf_counter() - t0
+            source = f"trained here ({train_steps} steps, linear mode)"
     res = PT.compare(net, n=n, seed=seed, max_iter=max_iter)
     res["weights"] = source
     res["training_seconds"] = train_s

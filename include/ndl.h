@@ -176,6 +176,13 @@ int ndl_cg_solve(const ndl_plan* plans, int nprob, const double* const* b, doubl
 typedef struct ndl_net_s* ndl_net;
 int ndl_net_create(int levels, const int* channels, uint64_t seed, ndl_net* out);
 int ndl_net_destroy(ndl_net net);
+/* Linear mode of the preconditioner network (linear != 0): no activations and
+ * no biases, the input is the residual alone, and residual and output are
+ * scaled by D^-1/2 (D the diagonal of A = -L of the plan), so that
+ * M(r) = D^-1/2 N(D^-1/2 r) is linear in r and sees delta and c through D.
+ * Applies to inference, training and the learned PCG of an FP32 case (b)
+ * plan; weights files are shared between modes. */
+int ndl_net_set_linear(ndl_net net, int linear);
 int ndl_net_save(ndl_net net, const char* path);
 int ndl_net_load(ndl_net net, const char* path);
 int ndl_net_num_params(ndl_net net, int64_t* count);

@@ -58,8 +58,9 @@ constexpr int kpad(int cin) { return ((27 * cin + 31) / 32) * 32; }
 
 // ------------------------------------------------------------------ forward conv (MFMA)
 // in  : [S][S][S][CIN] bf16, w : [COUT][KP] bf16, bias : [COUT] fp32 (may be null)
-// out : [S][S][S][COUT] bf16 (ACT 1 = relu) or fp32 when OUTF32
-template <int CIN, int COUT, int XB, int ACT, bool OUTF32>
+// out : [S][S][S][COUT] bf16 (OUTK 0, ACT 1 = relu), fp32 (OUTK 1), or only
+// channel 0 as a compact fp32 [S][S][S] (OUTK 2, the network's output layer)
+template <int CIN, int COUT, int XB, int ACT, int OUTK>
 __global__ __launch_bounds__(256) void k_conv_fwd(const bf16_t* __restrict__ in, const bf16_t* __restrict__ w,
                                                   const float* __restrict__ bias, void* __restrict__ out, int S)
 {
@@ -142,7 +143,9 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const bf16_t* __restrict__ in,
                 float v = acc[t][c][i] + bv;
                 if (ACT == 1) v = v > 0.f ? v : 0.f;
                 int64_t o = (((int64_t)z * S + y) * S + x) * COUT + co;
-                if (OUTF32) reinterpret_cast<float*>(out)[o] = v;
+                if (OUTK == 2) {
+                    if (co == 0) reinterpret_cast<float*>(out)[((int64_t)z * S + y) * S + x] = v;
+                } else if (OUTK == 1) reinterpret_cast<float*>(out)[o] = v;
                 else reinterpret_cast<bf16_t*>(out)[o] = f2bf(v);
             }
         }
@@ -248,34 +251,51 @@ __global__ void k_relu_mask(const float* __restrict__ dy, const bf16_t* __restri
 // 2x average pool, NDHWC: out[S/2] from in[S]
 __global__ void k_pool(const bf16_t* __restrict__ in, bf16_t* __restrict__ out, int S, int C)
 {
-    int So = S / 2;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t tot = (int64_t)So * So * So * C;
+    // one thread per 8 channels of an output voxel (16-byte loads and stores)
+    const int So = S / 2, C8 = C / 8;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tot = (int64_t)So * So * So * C8;
     if (i >= tot) return;
-    int c = (int)(i % C);
-    int64_t v = i / C;
-    int x = (int)(v % So), y = (int)((v / So) % So), z = (int)(v / ((int64_t)So * So));
-    float s = 0.f;
+    const int c8 = (int)(i % C8);
+    const int v = (int)(i / C8);
+    const int x = v % So, y = (v / So) % So, z = v / (So * So);
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const uint4* src = reinterpret_cast<const uint4*>(in);
+#pragma unroll
     for (int m = 0; m < 8; ++m) {
-        int xx = 2 * x + (m & 1), yy = 2 * y + ((m >> 1) & 1), zz = 2 * z + (m >> 2);
-        s += bf2f(in[(((int64_t)zz * S + yy) * S + xx) * C + c]);
+        const int xx = 2 * x + (m & 1), yy = 2 * y + ((m >> 1) & 1), zz = 2 * z + (m >> 2);
+        const uint4 q = src[(((int64_t)zz * S + yy) * S + xx) * C8 + c8];
+        const bf16_t* e = reinterpret_cast<const bf16_t*>(&q);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k] += bf2f(e[k]);
     }
-    out[i] = f2bf(0.125f * s);
+    uint4 o;
+    bf16_t* oe = reinterpret_cast<bf16_t*>(&o);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) oe[k] = f2bf(0.125f * acc[k]);
+    reinterpret_cast<uint4*>(out)[i] = o;
 }
 
-// out[S] = up2(coarse[S/2]) + skip[S]  (bf16)
+// out[S] = up2(coarse[S/2]) + skip[S]  (bf16; one thread per 8 channels of a voxel)
 __global__ void k_up_add(const bf16_t* __restrict__ coarse, const bf16_t* __restrict__ skip, bf16_t* __restrict__ out,
                          int S, int C)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t tot = (int64_t)S * S * S * C;
+    const int C8 = C / 8, Sc = S / 2;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tot = (int64_t)S * S * S * C8;
     if (i >= tot) return;
-    int c = (int)(i % C);
-    int64_t v = i / C;
-    int x = (int)(v % S), y = (int)((v / S) % S), z = (int)(v / ((int64_t)S * S));
-    int Sc = S / 2;
-    float a = bf2f(coarse[(((int64_t)(z / 2) * Sc + y / 2) * Sc + x / 2) * C + c]);
-    out[i] = f2bf(a + bf2f(skip[i]));
+    const int c8 = (int)(i % C8);
+    const int v = (int)(i / C8);
+    const int x = v % S, y = (v / S) % S, z = v / (S * S);
+    const uint4 a = reinterpret_cast<const uint4*>(coarse)[(((int64_t)(z / 2) * Sc + y / 2) * Sc + x / 2) * C8 + c8];
+    const uint4 b = reinterpret_cast<const uint4*>(skip)[i];
+    const bf16_t* ae = reinterpret_cast<const bf16_t*>(&a);
+    const bf16_t* be = reinterpret_cast<const bf16_t*>(&b);
+    uint4 o;
+    bf16_t* oe = reinterpret_cast<bf16_t*>(&o);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) oe[k] = f2bf(bf2f(ae[k]) + bf2f(be[k]));
+    reinterpret_cast<uint4*>(out)[i] = o;
 }
 
 // backward of up_add: dcoarse[S/2] (+)= sum of the 8 children of dout; dskip += dout
@@ -364,8 +384,8 @@ __global__ void k_pack_input(const T* __restrict__ r, const double* __restrict__
     double rs = rscale ? *rscale : 1.0;
     bf16_t* o = x + i * 8;
     o[0] = f2bf((float)((double)r[i] * rs));
-    o[1] = f2bf((float)((log((double)coef[i]) - mu) * isd));
-    o[2] = f2bf((float)((double)delta[i] * (double)S * 0.25));
+    o[1] = coef ? f2bf((float)((log((double)coef[i]) - mu) * isd)) : bf16_t(0);
+    o[2] = delta ? f2bf((float)((double)delta[i] * (double)S * 0.25)) : bf16_t(0);
 #pragma unroll
     for (int c = 3; c < 8; ++c) o[c] = 0;
 }
@@ -388,13 +408,31 @@ __global__ void k_pack_train(const float* __restrict__ r, const float* __restric
 constexpr double kTargetScale = 32.0;
 
 // z = (channel 0 of the fp32 head output) / (rscale * kTargetScale)
+// linear mode: rs = r * sqrt(dinv) (FP32)
+template <typename T>
+__global__ void k_scale_in(const T* __restrict__ r, const T* __restrict__ dinv, int64_t n, float* __restrict__ rs)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) rs[i] = (float)((double)r[i] * sqrt((double)dinv[i]));
+}
+
+// linear mode: z = sqrt(dinv) * y0 / (rscale * target scale)
+template <typename T>
+__global__ void k_unpack_scaled(const float* __restrict__ y, const double* __restrict__ rscale,
+                                const T* __restrict__ dinv, int64_t n, T* __restrict__ z)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    z[i] = (T)(sqrt((double)dinv[i]) * (double)y[i] / (*rscale * kTargetScale));
+}
+
 template <typename T>
 __global__ void k_unpack(const float* __restrict__ y, const double* __restrict__ rscale, int64_t n, T* __restrict__ z)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double rs = rscale ? *rscale : 1.0;
-    z[i] = (T)((double)y[i * 16] / (rs * kTargetScale));
+    z[i] = (T)((double)y[i] / (rs * kTargetScale));
 }
 
 // loss: sum (y0 - e)^2 and sum e^2 per sample (partials per block) and dy = 2 (y0 - e) / (B sum e^2)
@@ -403,7 +441,7 @@ __global__ void k_loss_parts(const float* __restrict__ y, const float* __restric
     __shared__ double s1[256], s2[256];
     double a = 0.0, b = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        double d = (double)y[i * 16] - (double)e[i];
+        double d = (double)y[i] - (double)e[i];
         a += d * d;
         b += (double)e[i] * (double)e[i];
     }
@@ -431,7 +469,7 @@ __global__ void k_loss_grad(const float* __restrict__ y, const float* __restrict
     __syncthreads();
     double den = den_s;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        float d = (float)(2.0 * ((double)y[i * 16] - (double)e[i]) / den) * inv_b;
+        float d = (float)(2.0 * ((double)y[i] - (double)e[i]) / den) * inv_b;
         dy[i * 16] = d;
 #pragma unroll
         for (int c = 1; c < 16; ++c) dy[i * 16 + c] = 0.f;
@@ -591,7 +629,7 @@ static int net_workspace(Net& n, int S)
     NDL_TRY(dmalloc(n, &n.u[2], vox(2) * 32));
     NDL_TRY(dmalloc(n, &n.u[1], vox(1) * 16));
     NDL_TRY(dmalloc(n, &n.u[0], vox(0) * 16));
-    NDL_TRY(dmalloc(n, &n.head, vox(0) * 16));
+    NDL_TRY(dmalloc(n, &n.head, vox(0)));  // output channel 0 only, FP32
     NDL_TRY(dmalloc(n, &n.lpart, 2 * 1024));
     NDL_TRY(dmalloc(n, &n.lossacc, 1));
     NDL_TRY(dmalloc(n, &n.rscale, 1));
@@ -600,7 +638,7 @@ static int net_workspace(Net& n, int S)
 
 // forward convolution dispatch
 template <int CIN, int COUT>
-static int conv_fwd_t(const bf16_t* in, const bf16_t* w, const float* bias, void* out, int S, int act, bool f32,
+static int conv_fwd_t(const bf16_t* in, const bf16_t* w, const float* bias, void* out, int S, int act, int outk,
                       hipStream_t s)
 {
     constexpr int XB = CIN >= 32 ? 32 : 64;
@@ -608,21 +646,23 @@ static int conv_fwd_t(const bf16_t* in, const bf16_t* w, const float* bias, void
     size_t lds = (size_t)3 * 6 * (XB + 2) * CIN * 2 + (size_t)COUT * KP * 2;
     dim3 grid((unsigned)((S + XB - 1) / XB), (unsigned)((S + 3) / 4), (unsigned)S);
     const void* fn;
-    if (f32) fn = (const void*)k_conv_fwd<CIN, COUT, XB, 0, true>;
-    else if (act) fn = (const void*)k_conv_fwd<CIN, COUT, XB, 1, false>;
-    else fn = (const void*)k_conv_fwd<CIN, COUT, XB, 0, false>;
+    if (outk == 2) fn = (const void*)k_conv_fwd<CIN, COUT, XB, 0, 2>;
+    else if (outk == 1) fn = (const void*)k_conv_fwd<CIN, COUT, XB, 0, 1>;
+    else if (act) fn = (const void*)k_conv_fwd<CIN, COUT, XB, 1, 0>;
+    else fn = (const void*)k_conv_fwd<CIN, COUT, XB, 0, 0>;
     if (lds > 64 * 1024) NDL_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    if (f32) k_conv_fwd<CIN, COUT, XB, 0, true><<<grid, 256, lds, s>>>(in, w, bias, out, S);
-    else if (act) k_conv_fwd<CIN, COUT, XB, 1, false><<<grid, 256, lds, s>>>(in, w, bias, out, S);
-    else k_conv_fwd<CIN, COUT, XB, 0, false><<<grid, 256, lds, s>>>(in, w, bias, out, S);
+    if (outk == 2) k_conv_fwd<CIN, COUT, XB, 0, 2><<<grid, 256, lds, s>>>(in, w, bias, out, S);
+    else if (outk == 1) k_conv_fwd<CIN, COUT, XB, 0, 1><<<grid, 256, lds, s>>>(in, w, bias, out, S);
+    else if (act) k_conv_fwd<CIN, COUT, XB, 1, 0><<<grid, 256, lds, s>>>(in, w, bias, out, S);
+    else k_conv_fwd<CIN, COUT, XB, 0, 0><<<grid, 256, lds, s>>>(in, w, bias, out, S);
     NDL_HIP(hipGetLastError());
     return NDL_OK;
 }
 
 static int conv_fwd(int cin, int cout, const bf16_t* in, const bf16_t* w, const float* bias, void* out, int S, int act,
-                    bool f32, hipStream_t s)
+                    int outk, hipStream_t s)
 {
-#define NDL_CF(A, B) if (cin == A && cout == B) return conv_fwd_t<A, B>(in, w, bias, out, S, act, f32, s)
+#define NDL_CF(A, B) if (cin == A && cout == B) return conv_fwd_t<A, B>(in, w, bias, out, S, act, outk, s)
     NDL_CF(8, 16);
     NDL_CF(16, 16);
     NDL_CF(16, 32);
@@ -696,6 +736,15 @@ struct NetState {
     int Sg = 0;
     double feat_mu = 0.0, feat_isd = 1.0;
     const void* feat_plan = nullptr;
+    // linear mode: no activations or biases, the input is the residual alone,
+    // scaled by D^-1/2 on the way in and out (M = D^-1/2 N D^-1/2, linear in r)
+    bool linear = false;
+    float* rsc = nullptr;  // scaled residual, N floats
+    int64_t rsc_n = 0;
+    ~NetState()
+    {
+        if (rsc) (void)hipFree(rsc);
+    }
 };
 
 static int grads_workspace(NetState& st, int S)
@@ -739,34 +788,34 @@ static const bf16_t* layer_input(Net& n, int i)
     }
 }
 
-static int net_forward(Net& n, int S, hipStream_t s)
+static int net_forward(Net& n, int S, hipStream_t s, bool linear = false)
 {
     int Sl[4] = {S, S / 2, S / 4, S / 8};
     auto conv = [&](int i) -> int {
         Layer& l = n.L[i];
         int lv = level_of_layer(i);
         bool head = i == kNumLayers - 1;
-        return conv_fwd(l.sp.cin, l.sp.cout, layer_input(n, i), l.wbf, l.b32, head ? (void*)n.head : (void*)n.a[i],
-                        Sl[lv], l.sp.act, head, s);
+        return conv_fwd(l.sp.cin, l.sp.cout, layer_input(n, i), l.wbf, linear ? nullptr : l.b32,
+                        head ? (void*)n.head : (void*)n.a[i], Sl[lv], linear ? 0 : l.sp.act, head ? 2 : 0, s);
     };
     auto vox = [&](int l) { return (int64_t)Sl[l] * Sl[l] * Sl[l]; };
     NDL_TRY(conv(0));
     NDL_TRY(conv(1));
-    k_pool<<<nb(vox(1) * 16), 256, 0, s>>>(n.a[1], n.p[1], Sl[0], 16);
+    k_pool<<<nb(vox(1) * 2), 256, 0, s>>>(n.a[1], n.p[1], Sl[0], 16);
     NDL_TRY(conv(2));
     NDL_TRY(conv(3));
-    k_pool<<<nb(vox(2) * 16), 256, 0, s>>>(n.a[3], n.p[2], Sl[1], 16);
+    k_pool<<<nb(vox(2) * 2), 256, 0, s>>>(n.a[3], n.p[2], Sl[1], 16);
     NDL_TRY(conv(4));
     NDL_TRY(conv(5));
-    k_pool<<<nb(vox(3) * 32), 256, 0, s>>>(n.a[5], n.p[3], Sl[2], 32);
+    k_pool<<<nb(vox(3) * 4), 256, 0, s>>>(n.a[5], n.p[3], Sl[2], 32);
     NDL_TRY(conv(6));
     NDL_TRY(conv(7));
-    k_up_add<<<nb(vox(2) * 32), 256, 0, s>>>(n.a[7], n.a[5], n.u[2], Sl[2], 32);
+    k_up_add<<<nb(vox(2) * 4), 256, 0, s>>>(n.a[7], n.a[5], n.u[2], Sl[2], 32);
     NDL_TRY(conv(8));
     NDL_TRY(conv(9));
-    k_up_add<<<nb(vox(1) * 16), 256, 0, s>>>(n.a[9], n.a[3], n.u[1], Sl[1], 16);
+    k_up_add<<<nb(vox(1) * 2), 256, 0, s>>>(n.a[9], n.a[3], n.u[1], Sl[1], 16);
     NDL_TRY(conv(10));
-    k_up_add<<<nb(vox(0) * 16), 256, 0, s>>>(n.a[10], n.a[1], n.u[0], Sl[0], 16);
+    k_up_add<<<nb(vox(0) * 2), 256, 0, s>>>(n.a[10], n.a[1], n.u[0], Sl[0], 16);
     NDL_TRY(conv(11));
     NDL_TRY(conv(12));
     NDL_HIP(hipGetLastError());
@@ -787,9 +836,10 @@ static int net_backward(NetState& st, int S, hipStream_t s)
         int64_t cnt = vox(lv) * l.sp.cout;
         const bf16_t* y = i == kNumLayers - 1 ? nullptr : n.a[i];
         // masked gradient (fp32 in n.g0, bf16 in n.gb16)
-        k_relu_mask<<<nb(cnt), 256, 0, s>>>(g.d[i], y ? y : n.gb16, n.gb16, n.g0, cnt, y ? l.sp.act : 0);
+        k_relu_mask<<<nb(cnt), 256, 0, s>>>(g.d[i], y ? y : n.gb16, n.gb16, n.g0, cnt,
+                                            (y && !st.linear) ? l.sp.act : 0);
         NDL_TRY(conv_wgrad(l.sp.cin, l.sp.cout, layer_input(n, i), n.g0, n, l, Sl[lv], s));
-        if (dst) NDL_TRY(conv_fwd(l.sp.cout, l.sp.cin, n.gb16, l.wt, nullptr, dst, Sl[lv], 0, true, s));
+        if (dst) NDL_TRY(conv_fwd(l.sp.cout, l.sp.cin, n.gb16, l.wt, nullptr, dst, Sl[lv], 0, 1, s));
         return NDL_OK;
     };
     NDL_TRY(back(12, g.d[11]));
@@ -873,11 +923,12 @@ __global__ void k_logc_moments(const T* __restrict__ c, int64_t n, double* __res
 //   ||e - z||_A^2 / ||e||_A^2 = (e - z).(r - A z) / (e.r),   A = -L, A e = r,
 // and its gradient with respect to z is 2 (A z - r) / (e.r).
 __global__ void k_z_two_level(const float* __restrict__ y, const double* __restrict__ rscale, const float* __restrict__ r,
-                              const float* __restrict__ dinv, int64_t n, float* __restrict__ z)
+                              const float* __restrict__ dinv, int64_t n, int linear, float* __restrict__ z)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    z[i] = (float)((double)r[i] * (double)dinv[i] + (double)y[i * 16] / (*rscale * kTargetScale));
+    const double sc = linear ? sqrt((double)dinv[i]) : 1.0;
+    z[i] = (float)((double)r[i] * (double)dinv[i] + sc * (double)y[i] / (*rscale * kTargetScale));
 }
 
 __global__ void k_energy_parts(const float* __restrict__ e, const float* __restrict__ z, const float* __restrict__ r,
@@ -901,7 +952,8 @@ __global__ void k_energy_parts(const float* __restrict__ e, const float* __restr
 
 __global__ void k_energy_grad(const float* __restrict__ r, const float* __restrict__ az, int64_t n,
                               const double* __restrict__ part, int nparts, const double* __restrict__ rscale,
-                              float inv_b, float* __restrict__ dy, float* __restrict__ loss_acc)
+                              const float* __restrict__ dinv, int linear, float inv_b, float* __restrict__ dy,
+                              float* __restrict__ loss_acc)
 {
     __shared__ double den_s;
     if (threadIdx.x == 0) {
@@ -915,7 +967,8 @@ __global__ void k_energy_grad(const float* __restrict__ r, const float* __restri
     double dzdy = 1.0 / (*rscale * kTargetScale);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         double g = 2.0 * ((double)az[i] - (double)r[i]) / den;
-        dy[i * 16] = (float)(g * dzdy) * inv_b;
+        const double sc = linear ? sqrt((double)dinv[i]) : 1.0;
+        dy[i * 16] = (float)(g * sc * dzdy) * inv_b;
 #pragma unroll
         for (int c = 1; c < 16; ++c) dy[i * 16 + c] = 0.f;
     }
@@ -923,13 +976,31 @@ __global__ void k_energy_grad(const float* __restrict__ r, const float* __restri
 
 // z = M(r) for a plan's cube (n^3, n % 8 == 0): input (r / ||r||, standardised log c, m / 4)
 template <typename T>
-static int precond_t(NetState& st, const Plan& p, const T* r, T* z, hipStream_t s)
+static int precond_t(NetState& st, const Plan& p, const T* r, T* z, hipStream_t s, const T* dinv = nullptr)
 {
     Net& n = st.net;
     int S = (int)p.n;
     if (n.S != S) {
         NDL_TRY(net_workspace(n, S));
         st.Sg = 0;  // gradient buffers lived in the old workspace
+    }
+    if (st.linear) {
+        if (!dinv) { set_error("internal: linear preconditioner needs the Jacobi diagonal"); return NDL_EINVAL; }
+        if (st.rsc_n != p.N) {
+            if (st.rsc) (void)hipFree(st.rsc);
+            st.rsc = nullptr;
+            st.rsc_n = 0;
+            NDL_HIP(hipMalloc(&st.rsc, p.N * sizeof(float)));
+            st.rsc_n = p.N;
+        }
+        k_scale_in<T><<<nb(p.N), 256, 0, s>>>(r, dinv, p.N, st.rsc);
+        k_sumsq<float><<<256, 256, 0, s>>>(st.rsc, p.N, n.lpart);
+        k_rscale<<<1, 64, 0, s>>>(n.lpart, 256, (double)p.N, n.rscale);
+        k_pack_input<float><<<nb(p.N), 256, 0, s>>>(st.rsc, n.rscale, nullptr, nullptr, p.N, S, 0.0, 1.0, n.x_in);
+        NDL_TRY(net_forward(n, S, s, true));
+        if (z) k_unpack_scaled<T><<<nb(p.N), 256, 0, s>>>(n.head, n.rscale, dinv, p.N, z);
+        NDL_HIP(hipGetLastError());
+        return NDL_OK;
     }
     if (st.feat_plan != (const void*)&p) {
         k_logc_moments<T><<<256, 256, 0, s>>>((const T*)p.prob.coef, p.N, n.lpart);
@@ -953,15 +1024,24 @@ static int precond_t(NetState& st, const Plan& p, const T* r, T* z, hipStream_t 
     return NDL_OK;
 }
 
-int net_precond(void* net, const Plan& p, const void* r, void* z, hipStream_t s)
+int net_precond(void* net, const Plan& p, const void* r, void* z, hipStream_t s, const void* dinv)
 {
     NetState& st = *reinterpret_cast<NetState*>(net);
     if (p.dim != 3 || p.n % 8 != 0) {
         set_error("learned preconditioner needs a 3D cube with n divisible by 8");
         return NDL_EUNSUPPORTED;
     }
-    return p.prec == NDL_F64 ? precond_t<double>(st, p, (const double*)r, (double*)z, s)
-                             : precond_t<float>(st, p, (const float*)r, (float*)z, s);
+    if (st.linear && !dinv) {
+        if (p.prec == NDL_F64 || p.form != NDL_DIV) {
+            set_error("the linear preconditioner needs an FP32 case (b) plan");
+            return NDL_EUNSUPPORTED;
+        }
+        const float* d = nullptr;
+        NDL_TRY(plan_dinv_f32(p, &d, s));
+        dinv = d;
+    }
+    return p.prec == NDL_F64 ? precond_t<double>(st, p, (const double*)r, (double*)z, s, (const double*)dinv)
+                             : precond_t<float>(st, p, (const float*)r, (float*)z, s, (const float*)dinv);
 }
 
 }  // namespace ndl
@@ -985,6 +1065,13 @@ int ndl_net_create(int levels, const int* channels, uint64_t seed, ndl_net* out)
     int rc = net_init(st->net, seed);
     if (rc != NDL_OK) { delete st; return rc; }
     *out = reinterpret_cast<ndl_net>(st);
+    return NDL_OK;
+}
+
+int ndl_net_set_linear(ndl_net net, int linear)
+{
+    if (!net) { set_error("null argument"); return NDL_EINVAL; }
+    reinterpret_cast<NetState*>(net)->linear = linear != 0;
     return NDL_OK;
 }
 
@@ -1123,8 +1210,11 @@ int ndl_net_train_step_energy(ndl_net net, ndl_plan plan, int batch, const float
     hipStream_t hs = (hipStream_t)stream;
     int S = (int)P.n;
     int64_t N = P.N;
-    // forward once to size the workspace and the features
-    NDL_TRY(precond_t<float>(st, P, r, nullptr, hs));
+    // the Jacobi diagonal (built with the operator cache), then one forward to
+    // size the workspace and the features
+    const float* dinv = nullptr;
+    NDL_TRY(plan_dinv_f32(P, &dinv, hs));
+    NDL_TRY(precond_t<float>(st, P, r, nullptr, hs, dinv));
     NDL_TRY(grads_workspace(st, S));
     float *z = nullptr, *az = nullptr;
     NDL_HIP(hipMalloc(&z, N * sizeof(float)));
@@ -1138,16 +1228,14 @@ int ndl_net_train_step_energy(ndl_net net, ndl_plan plan, int batch, const float
     for (int b = 0; b < batch && rc == NDL_OK; ++b) {
         const float* rb = r + (size_t)b * N;
         const float* eb = e + (size_t)b * N;
-        rc = precond_t<float>(st, P, rb, nullptr, hs);  // head output for rb
-        const float* dinv = nullptr;
-        if (rc == NDL_OK) rc = plan_neg_L_f32(P, z, az, &dinv, hs);  // builds dinv on first use
+        rc = precond_t<float>(st, P, rb, nullptr, hs, dinv);  // head output for rb
         if (rc != NDL_OK) break;
-        k_z_two_level<<<nb(N), 256, 0, hs>>>(n.head, n.rscale, rb, dinv, N, z);
+        k_z_two_level<<<nb(N), 256, 0, hs>>>(n.head, n.rscale, rb, dinv, N, st.linear ? 1 : 0, z);
         rc = plan_neg_L_f32(P, z, az, nullptr, hs);
         if (rc != NDL_OK) break;
         k_energy_parts<<<256, 256, 0, hs>>>(eb, z, rb, az, N, n.lpart);
-        k_energy_grad<<<256, 256, 0, hs>>>(rb, az, N, n.lpart, 256, n.rscale, 1.0f / batch, st.g.d[kNumLayers - 1],
-                                           n.lossacc);
+        k_energy_grad<<<256, 256, 0, hs>>>(rb, az, N, n.lpart, 256, n.rscale, dinv, st.linear ? 1 : 0, 1.0f / batch,
+                                           st.g.d[kNumLayers - 1], n.lossacc);
         rc = net_backward(st, S, hs);
     }
     (void)hipStreamSynchronize(hs);
@@ -1197,12 +1285,12 @@ int ndl_net_conv_test(int cin, int cout, int S, const uint16_t* x, const float* 
     int rc = NDL_OK;
     float* yb = nullptr;
     int64_t vox = (int64_t)S * S * S;
-    if (y) rc = conv_fwd(cin, cout, x, l.wbf, bias, y, S, 0, true, s);
+    if (y) rc = conv_fwd(cin, cout, x, l.wbf, bias, y, S, 0, 1, s);
     if (rc == NDL_OK && dy) {
         bf16_t* dyb = nullptr;
         NDL_HIP(hipMalloc(&dyb, vox * cout * sizeof(bf16_t)));
         k_to_bf16<<<nb(vox * cout), 256, 0, s>>>(dy, dyb, vox * cout);
-        if (dx) rc = conv_fwd(cout, cin, dyb, l.wt, nullptr, dx, S, 0, true, s);
+        if (dx) rc = conv_fwd(cout, cin, dyb, l.wt, nullptr, dx, S, 0, 1, s);
         if (rc == NDL_OK && gw) {
             size_t blocks = (size_t)((S + 63) / 64) * ((S + 3) / 4) * S;
             tmp.part_elems = (blocks + 1) * cout * (l.KP + 1);

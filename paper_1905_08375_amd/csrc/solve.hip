@@ -1240,6 +1240,17 @@ int plan_neg_L_f32(const Plan& P, const float* x, float* y, const float** dinv, 
     return NDL_OK;
 }
 
+int plan_dinv_f32(const Plan& P, const float** dinv, hipStream_t s)
+{
+    if (P.form != NDL_DIV || P.prec == NDL_F64) {
+        set_error("internal: FP32 case (b) plan expected");
+        return NDL_EINVAL;
+    }
+    NDL_TRY(op_build<float>(P, g_op_cache, s));
+    *dinv = (const float*)g_op_cache.dinv.p;
+    return NDL_OK;
+}
+
 // ------------------------------------------------------------------ flexible PCG with M(r)
 template <typename T>
 __global__ void k_dot2(const Inst* __restrict__ insts, const int2* __restrict__ items, int nitems,
@@ -1398,7 +1409,7 @@ static int pcg_learned_t(const ndl_plan plan, const double* b, double* x, const 
     // two-level preconditioner: z = D^-1 r + M(r); the network supplies the
     // smooth part of the correction that the Jacobi term misses
     auto precond = [&](const T* r, T* z, bool jac) -> int {
-        if (!jac) NDL_TRY(net_precond(opts->net, P, r, z, s));
+        if (!jac) NDL_TRY(net_precond(opts->net, P, r, z, s, vdinv.p));
         k_jacobi_add<T><<<grid_for(N), 256, 0, s>>>(N, r, (const T*)vdinv.p, z, jac ? 0 : 1);
         NDL_HIP(hipGetLastError());
         return NDL_OK;

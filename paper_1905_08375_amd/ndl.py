@@ -24,7 +24,7 @@ NDL_NORM_DISCRETE, NDL_NORM_CONTINUOUS, NDL_NORM_NONE = 0, 1, 2
 # every symbol include/ndl.h declares
 EXPORTS = [
     "ndl_plan_create", "ndl_plan_destroy", "ndl_plan_get_info", "ndl_apply", "ndl_apply_fast",
-    "ndl_fast_decomposition", "ndl_decompose_node", "ndl_cg_solve", "ndl_net_create", "ndl_net_destroy",
+    "ndl_fast_decomposition", "ndl_decompose_node", "ndl_cg_solve", "ndl_net_create", "ndl_net_destroy", "ndl_net_set_linear",
     "ndl_net_save", "ndl_net_load", "ndl_net_num_params", "ndl_net_train_step", "ndl_precond_apply",
     "ndl_autotune", "ndl_last_error", "ndl_version", "ndl_plan_set_variant", "ndl_plan_num_variants",
     "ndl_net_conv_test", "ndl_net_train_step_energy",
@@ -83,6 +83,7 @@ def lib():
                              C.POINTER(ndl_cg_report), vp],
             "ndl_net_create": [C.c_int, C.POINTER(C.c_int), C.c_uint64, C.POINTER(vp)],
             "ndl_net_destroy": [vp],
+            "ndl_net_set_linear": [vp, C.c_int32],
             "ndl_net_save": [vp, C.c_char_p],
             "ndl_net_load": [vp, C.c_char_p],
             "ndl_net_num_params": [vp, C.POINTER(i64)],
@@ -261,6 +262,10 @@ def ndl_net_create(levels: int = 4, channels=(16, 16, 32, 32), seed: int = 0) ->
     ch = (C.c_int * len(channels))(*channels)
     _check(lib().ndl_net_create(int(levels), ch, C.c_uint64(seed), C.byref(h)), "ndl_net_create")
     return Net(h)
+
+
+def ndl_net_set_linear(net: Net, linear: bool = True):
+    _check(lib().ndl_net_set_linear(net.handle, int(bool(linear))), "ndl_net_set_linear")
 
 
 def ndl_net_destroy(net: Net):

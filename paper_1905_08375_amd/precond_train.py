@@ -1,14 +1,25 @@
 """Training and evaluation of the learned preconditioner (3D case (b) workload).
 
 Training pairs come from plain Jacobi-CG runs of the library on seeded fields:
-for each training field the solver is run to a tight tolerance (x*) and, from
-the same start, for k = k_1 < k_2 < ... iterations (x_k); the pair is the
+for each training field the solver is run to a tight tolerance (x*) and, in
+one warm-started run, to k_1 < k_2 < ... iterations (x_k); the pair is the
 residual r_k = b + L x_k and the correction e_k = x* - x_k on the whole
 field.  The network is trained on full fields with the energy norm that CG
 minimises: for the two-level preconditioner z = D^-1 r + M(r) the loss is
 ||e - z||_A^2 / ||e||_A^2 (A = -L), evaluated with the library's operator.
+
+The network runs in its linear mode, M(r) = D^-1/2 N(D^-1/2 r) with N
+free of activations and biases: the correction CG needs is A^-1 r, a linear
+map of r, and a linear network fits it from few pairs and holds on unseen
+fields, where the activated network with (r, log c, m) inputs did not.  Its
+output layer starts at zero, so training starts from plain Jacobi (loss
+about 1) and only moves where the energy decreases.
+
 Every arithmetic step runs in libndl (the operator, the solves, the
 network's forward/backward and Adam); torch only holds the tensors.
+
+`python -m paper_1905_08375_amd.precond_train` writes the shipped weights
+(`weights/precond_3d.bin`, linear mode).
 """
 from __future__ import annotations
 
@@ -48,15 +59,19 @@ def neg_L(plan, x, n, R=4):
     return -out
 
 
-def cg_iterate(plan, b, iters, rtol=1e-10):
+def cg_iterate(plan, b, iters, rtol=1e-10, x0=None):
+    """Plain Jacobi-CG for `iters` iterations from x0 (zero by default)."""
     import torch
-    x = torch.zeros_like(b)
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
     ndl.ndl_cg_solve([plan], [b], [x], rtol=rtol, max_iter=iters)
     return x
 
 
 def make_pairs(n=256, seeds=range(8), ks=(8, 16, 32, 64, 128, 256), log=print):
-    """Per training field: its plan and the CG pairs (r_k, e_k) as FP32 fields."""
+    """Per training field: its plan and residual/correction pairs (r_k, e_k =
+    x* - x_k) as FP32 fields, with x_k the plain-CG iterates at the iteration
+    counts ks (one warm-started run per field: each segment continues from
+    the previous iterate) and x* the solve to 1e-9."""
     import torch
     out = []
     for sd in seeds:
@@ -64,14 +79,57 @@ def make_pairs(n=256, seeds=range(8), ks=(8, 16, 32, 64, 128, 256), log=print):
         plan, b, feat, _ = problem_3d(n, sd)
         xs = cg_iterate(plan, b, 100000, rtol=1e-9)
         pairs = []
-        for k in ks:
-            xk = cg_iterate(plan, b, k)
+        xk, done = None, 0
+        for k in sorted(ks):
+            xk = cg_iterate(plan, b, k - done, x0=xk)
+            done = k
             ek = (xs - xk).float()
             rk = (b - neg_L(plan, xk, n)).float()
             pairs.append((rk, ek))
         out.append((plan, pairs))
         log(f"pairs: seed {sd} done in {time.perf_counter() - t0:.1f}s")
     return out
+
+
+def zero_output_layer(net):
+    """Zero the output layer's weights and bias (a save / edit / load round
+    trip: the file is an 8-byte magic, an int64 step count, then per layer an
+    int32 pair (cout, KP), FP32 weights [cout][KP] and FP32 biases [cout])."""
+    import struct
+    import tempfile
+    fd, path = tempfile.mkstemp(suffix=".bin")
+    os.close(fd)
+    try:
+        ndl.ndl_net_save(net, path)
+        with open(path, "rb") as f:
+            raw = bytearray(f.read())
+        off, last = 16, None
+        while off < len(raw):
+            cout, kp = struct.unpack_from("<ii", raw, off)
+            last = (off, cout, kp)
+            off += 8 + 4 * (cout * kp + cout)
+        o, cout, kp = last
+        raw[o + 8:o + 8 + 4 * (cout * kp + cout)] = bytes(4 * (cout * kp + cout))
+        with open(path, "wb") as f:
+            f.write(raw)
+        ndl.ndl_net_load(net, path)
+    finally:
+        os.remove(path)
+
+
+def new_net(seed=1):
+    """The shipped configuration: linear mode, output layer at zero."""
+    net = ndl.ndl_net_create(seed=seed)
+    zero_output_layer(net)
+    ndl.ndl_net_set_linear(net, True)
+    return net
+
+
+def load_net(path=WEIGHTS):
+    net = ndl.ndl_net_create(seed=1)
+    ndl.ndl_net_load(net, path)
+    ndl.ndl_net_set_linear(net, True)
+    return net
 
 
 def train(net, data, steps=300, batch=2, lr=1e-3, steps_per_field=10, seed=0, log=print):
@@ -115,19 +173,23 @@ def compare(net, n=256, seed=100, rtol=1e-8, max_iter=None):
             "speedup": t_plain / t_learn if t_learn > 0 else None}
 
 
+TRAIN_KS = (4, 8, 16, 32, 64, 96, 128, 192, 256, 384)
+
+
 def main():
     import argparse
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--seeds", type=int, default=8)
-    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--seeds", type=int, default=12)
+    ap.add_argument("--steps", type=int, default=800)
+    ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--out", default=WEIGHTS)
     args = ap.parse_args()
     t0 = time.perf_counter()
-    data = make_pairs(args.n, range(args.seeds))
+    data = make_pairs(args.n, range(args.seeds), ks=TRAIN_KS)
     t1 = time.perf_counter()
-    net = ndl.ndl_net_create(seed=1)
-    train(net, data, steps=args.steps)
+    net = new_net(seed=1)
+    train(net, data, steps=args.steps, lr=args.lr)
     t2 = time.perf_counter()
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
     ndl.ndl_net_save(net, args.out)
