@@ -60,94 +60,151 @@ constexpr int kpad(int cin) { return ((27 * cin + 31) / 32) * 32; }
 // in  : [S][S][S][CIN] bf16, w : [COUT][KP] bf16, bias : [COUT] fp32 (may be null)
 // out : [S][S][S][COUT] bf16 (OUTK 0, ACT 1 = relu), fp32 (OUTK 1), or only
 // channel 0 as a compact fp32 [S][S][S] (OUTK 2, the network's output layer)
-template <int CIN, int COUT, int XB, int ACT, int OUTK>
+//
+// A block computes an XB x 4 (x, y) patch for ZB consecutive z planes; each of
+// its 4 waves owns one y row.  The input is held as a rolling window of three
+// haloed planes in LDS: plane z+2 is read from HBM into registers while plane
+// z is being convolved and written into the slot of plane z-1 afterwards, so
+// each input plane is fetched once per block and the weights once per ZB
+// planes.  The 3x3x3 convolution is an implicit GEMM on
+// v_mfma_f32_16x16x32_bf16: A = 16 output voxels x 32 of the 27 CIN taps,
+// B = the same 32 taps x 16 output channels.
+template <int CIN, int XB>
+struct ConvPlane {
+    static constexpr int LX = XB + 2, LY = 6, CPV = CIN / 8;
+    static constexpr int CHUNKS = LY * LX * CPV;  // 16-byte chunks of one haloed plane
+    static constexpr int PER = (CHUNKS + 255) / 256;
+};
+
+template <int CIN, int XB, int PER>
+__device__ __forceinline__ void conv_fetch_plane(uint4 (&r)[PER], const bf16_t* __restrict__ in, int S, int x0,
+                                                 int y0, int gz)
+{
+    using CPL = ConvPlane<CIN, XB>;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int c = threadIdx.x + q * 256;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (c < CPL::CHUNKS) {
+            const int cc = c % CPL::CPV, vox = c / CPL::CPV;
+            const int lx = vox % CPL::LX, ly = vox / CPL::LX;
+            const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+            if (gz >= 0 && gz < S && gx >= 0 && gx < S && gy >= 0 && gy < S)
+                v = reinterpret_cast<const uint4*>(in + (((int64_t)gz * S + gy) * S + gx) * CIN)[cc];
+        }
+        r[q] = v;
+    }
+}
+
+template <int CIN, int XB, int PER>
+__device__ __forceinline__ void conv_store_plane(const uint4 (&r)[PER], bf16_t* __restrict__ slot)
+{
+    using CPL = ConvPlane<CIN, XB>;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int c = threadIdx.x + q * 256;
+        if (c < CPL::CHUNKS) reinterpret_cast<uint4*>(slot)[c] = r[q];
+    }
+}
+
+template <int CIN, int COUT, int XB, int ACT, int OUTK, int ZB>
 __global__ __launch_bounds__(256) void k_conv_fwd(const bf16_t* __restrict__ in, const bf16_t* __restrict__ w,
                                                   const float* __restrict__ bias, void* __restrict__ out, int S)
 {
+    using CPL = ConvPlane<CIN, XB>;
     constexpr int KP = kpad(CIN);
-    constexpr int LX = XB + 2, LY = 6, LZ = 3;
-    constexpr int NT = XB / 16;    // MFMA row tiles per wave
-    constexpr int NC = COUT / 16;  // MFMA column tiles
+    constexpr int LX = CPL::LX, LY = CPL::LY;
+    constexpr int PLANE = LY * LX * CIN;  // bf16 elements of one haloed plane
+    constexpr int NT = XB / 16;           // MFMA row tiles per wave
+    constexpr int NC = COUT / 16;         // MFMA column tiles
     extern __shared__ __align__(16) unsigned char smem[];
-    bf16_t* sin = reinterpret_cast<bf16_t*>(smem);                 // [LZ][LY][LX][CIN]
-    bf16_t* sw = sin + LZ * LY * LX * CIN;                         // [COUT][KP]
-    const int x0 = blockIdx.x * XB, y0 = blockIdx.y * 4, z = blockIdx.z;
-    // stage weights (16-byte chunks)
+    bf16_t* sin = reinterpret_cast<bf16_t*>(smem);  // [3][LY][LX][CIN], plane p in slot p mod 3
+    bf16_t* sw = sin + 3 * PLANE;                   // [COUT][KP]
+    const int x0 = blockIdx.x * XB, y0 = blockIdx.y * 4, zb = blockIdx.z * ZB;
+    const int zend = min(zb + ZB, S);
+    // weights (16-byte chunks) and the first three planes zb-1, zb, zb+1
     const int wchunks = COUT * KP / 8;
     for (int c = threadIdx.x; c < wchunks; c += 256)
         reinterpret_cast<uint4*>(sw)[c] = reinterpret_cast<const uint4*>(w)[c];
-    // stage input rows, 8 channels per chunk
-    constexpr int CPV = CIN / 8;
-    const int ichunks = LZ * LY * LX * CPV;
-    for (int c = threadIdx.x; c < ichunks; c += 256) {
-        int cc = c % CPV;
-        int vox = c / CPV;
-        int lx = vox % LX;
-        int r = vox / LX;
-        int ly = r % LY;
-        int lz = r / LY;
-        int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z - 1 + lz;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (gx >= 0 && gx < S && gy >= 0 && gy < S && gz >= 0 && gz < S)
-            v = reinterpret_cast<const uint4*>(in + (((int64_t)gz * S + gy) * S + gx) * CIN)[cc];
-        reinterpret_cast<uint4*>(sin)[c] = v;
+    uint4 pre[CPL::PER];
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz) {
+        conv_fetch_plane<CIN, XB, CPL::PER>(pre, in, S, x0, y0, zb + dz);
+        conv_store_plane<CIN, XB, CPL::PER>(pre, sin + ((zb + dz + 3) % 3) * PLANE);
     }
+    conv_fetch_plane<CIN, XB, CPL::PER>(pre, in, S, x0, y0, zb + 2);  // in flight during plane zb
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int row = lane & 15, kb = lane >> 4;
-    f32x4 acc[NT][NC];
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int c = 0; c < NC; ++c) acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-    for (int kc = 0; kc < KP / 32; ++kc) {
-        const int k0 = kc * 32 + kb * 8;
-        const int tap = k0 / CIN, ci = k0 % CIN;
-        bf16x8 a[NT];
-        if (tap < 27) {
-            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const int lx = t * 16 + row + dx;
-                const bf16_t* src = sin + (((dz * LY) + (wv + dy)) * LX + lx) * CIN + ci;
-                a[t] = *reinterpret_cast<const bf16x8*>(src);
-            }
-        } else {
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                uint4 zz = make_uint4(0, 0, 0, 0);
-                a[t] = *reinterpret_cast<const bf16x8*>(&zz);
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const bf16x8 b = *reinterpret_cast<const bf16x8*>(sw + (c * 16 + row) * KP + k0);
-#pragma unroll
-            for (int t = 0; t < NT; ++t) acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], b, acc[t][c], 0, 0, 0);
-        }
-    }
-    // D layout: lane holds rows 4*kb .. 4*kb+3 of column `row`
     const int y = y0 + wv;
-    if (y >= S) return;
+    for (int z = zb; z < zend; ++z) {
+        f32x4 acc[NT][NC];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
+        for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const int co = c * 16 + row;
-            const float bv = bias ? bias[co] : 0.f;
+            for (int c = 0; c < NC; ++c) acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const int s0 = (z + 2) % 3;  // slot of plane z - 1 (z >= 0, so z + 2 > 0)
+#pragma unroll 2
+        for (int kc = 0; kc < KP / 32; ++kc) {
+            const int k0 = kc * 32 + kb * 8;
+            const int tap = k0 / CIN, ci = k0 % CIN;
+            bf16x8 a[NT];
+            if (tap < 27) {
+                const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+                int sl = s0 + dz;
+                sl = sl >= 3 ? sl - 3 : sl;
+                const bf16_t* pl = sin + sl * PLANE;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int x = x0 + t * 16 + kb * 4 + i;
-                if (x >= S) continue;
-                float v = acc[t][c][i] + bv;
-                if (ACT == 1) v = v > 0.f ? v : 0.f;
-                int64_t o = (((int64_t)z * S + y) * S + x) * COUT + co;
-                if (OUTK == 2) {
-                    if (co == 0) reinterpret_cast<float*>(out)[((int64_t)z * S + y) * S + x] = v;
-                } else if (OUTK == 1) reinterpret_cast<float*>(out)[o] = v;
-                else reinterpret_cast<bf16_t*>(out)[o] = f2bf(v);
+                for (int t = 0; t < NT; ++t) {
+                    const int lx = t * 16 + row + dx;
+                    a[t] = *reinterpret_cast<const bf16x8*>(pl + ((wv + dy) * LX + lx) * CIN + ci);
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    uint4 zz = make_uint4(0, 0, 0, 0);
+                    a[t] = *reinterpret_cast<const bf16x8*>(&zz);
+                }
             }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const bf16x8 bb = *reinterpret_cast<const bf16x8*>(sw + (c * 16 + row) * KP + k0);
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], bb, acc[t][c], 0, 0, 0);
+            }
+        }
+        // D layout: lane holds rows 4*kb .. 4*kb+3 of column `row`
+        if (y < S) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const int co = c * 16 + row;
+                    const float bv = bias ? bias[co] : 0.f;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int x = x0 + t * 16 + kb * 4 + i;
+                        if (x >= S) continue;
+                        float v = acc[t][c][i] + bv;
+                        if (ACT == 1) v = v > 0.f ? v : 0.f;
+                        const int64_t o = (((int64_t)z * S + y) * S + x) * COUT + co;
+                        if (OUTK == 2) {
+                            if (co == 0) reinterpret_cast<float*>(out)[((int64_t)z * S + y) * S + x] = v;
+                        } else if (OUTK == 1) {
+                            reinterpret_cast<float*>(out)[o] = v;
+                        } else {
+                            reinterpret_cast<bf16_t*>(out)[o] = f2bf(v);
+                        }
+                    }
+                }
+            }
+        }
+        if (z + 1 < zend) {
+            __syncthreads();  // every wave is done with plane z - 1
+            conv_store_plane<CIN, XB, CPL::PER>(pre, sin + s0 * PLANE);  // plane z + 2 into its slot
+            __syncthreads();
+            if (z + 2 < zend) conv_fetch_plane<CIN, XB, CPL::PER>(pre, in, S, x0, y0, z + 3);
         }
     }
 }
@@ -644,17 +701,18 @@ static int conv_fwd_t(const bf16_t* in, const bf16_t* w, const float* bias, void
     constexpr int XB = CIN >= 32 ? 32 : 64;
     constexpr int KP = kpad(CIN);
     size_t lds = (size_t)3 * 6 * (XB + 2) * CIN * 2 + (size_t)COUT * KP * 2;
-    dim3 grid((unsigned)((S + XB - 1) / XB), (unsigned)((S + 3) / 4), (unsigned)S);
+    constexpr int ZB = 8;
+    dim3 grid((unsigned)((S + XB - 1) / XB), (unsigned)((S + 3) / 4), (unsigned)((S + ZB - 1) / ZB));
     const void* fn;
-    if (outk == 2) fn = (const void*)k_conv_fwd<CIN, COUT, XB, 0, 2>;
-    else if (outk == 1) fn = (const void*)k_conv_fwd<CIN, COUT, XB, 0, 1>;
-    else if (act) fn = (const void*)k_conv_fwd<CIN, COUT, XB, 1, 0>;
-    else fn = (const void*)k_conv_fwd<CIN, COUT, XB, 0, 0>;
+    if (outk == 2) fn = (const void*)k_conv_fwd<CIN, COUT, XB, 0, 2, ZB>;
+    else if (outk == 1) fn = (const void*)k_conv_fwd<CIN, COUT, XB, 0, 1, ZB>;
+    else if (act) fn = (const void*)k_conv_fwd<CIN, COUT, XB, 1, 0, ZB>;
+    else fn = (const void*)k_conv_fwd<CIN, COUT, XB, 0, 0, ZB>;
     if (lds > 64 * 1024) NDL_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    if (outk == 2) k_conv_fwd<CIN, COUT, XB, 0, 2><<<grid, 256, lds, s>>>(in, w, bias, out, S);
-    else if (outk == 1) k_conv_fwd<CIN, COUT, XB, 0, 1><<<grid, 256, lds, s>>>(in, w, bias, out, S);
-    else if (act) k_conv_fwd<CIN, COUT, XB, 1, 0><<<grid, 256, lds, s>>>(in, w, bias, out, S);
-    else k_conv_fwd<CIN, COUT, XB, 0, 0><<<grid, 256, lds, s>>>(in, w, bias, out, S);
+    if (outk == 2) k_conv_fwd<CIN, COUT, XB, 0, 2, ZB><<<grid, 256, lds, s>>>(in, w, bias, out, S);
+    else if (outk == 1) k_conv_fwd<CIN, COUT, XB, 0, 1, ZB><<<grid, 256, lds, s>>>(in, w, bias, out, S);
+    else if (act) k_conv_fwd<CIN, COUT, XB, 1, 0, ZB><<<grid, 256, lds, s>>>(in, w, bias, out, S);
+    else k_conv_fwd<CIN, COUT, XB, 0, 0, ZB><<<grid, 256, lds, s>>>(in, w, bias, out, S);
     NDL_HIP(hipGetLastError());
     return NDL_OK;
 }
