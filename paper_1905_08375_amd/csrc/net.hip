@@ -211,75 +211,111 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const bf16_t* __restrict__ in,
 
 // ------------------------------------------------------------------ weight gradient (FP32 VALU)
 // part[blk][co][k] = sum over the block's voxels of dy[v][co] * x[v + tap][ci]
-// (k = tap * CIN + ci), blocks of 64 x 4 x 1 voxels; bias gradient in k = KP.
-template <int CIN, int COUT>
+// (k = tap * CIN + ci); a block covers 64 x 4 voxels of ZB consecutive z
+// planes and keeps its sums in registers across the planes, so the partials
+// written (and reduced afterwards) shrink by ZB.  Bias gradient in k = KP.
+template <int CIN, int COUT, int ZB>
 __global__ __launch_bounds__(256) void k_conv_wgrad(const bf16_t* __restrict__ x, const float* __restrict__ dy,
                                                     float* __restrict__ part, int S)
 {
     constexpr int KP = kpad(CIN);
     constexpr int LX = 66, LY = 6, LZ = 3;
+    constexpr int UNITS = 27 * (CIN / 4) * (COUT / 4);  // (tap, ci block of 4, co block of 4)
+    constexpr int NU = (UNITS + 255) / 256;
     extern __shared__ __align__(16) unsigned char smem[];
-    bf16_t* sx = reinterpret_cast<bf16_t*>(smem);                       // [LZ][LY][LX][CIN]
-    float* sd = reinterpret_cast<float*>(sx + LZ * LY * LX * CIN);       // [256][COUT]
-    const int x0 = blockIdx.x * 64, y0 = blockIdx.y * 4, z = blockIdx.z;
-    const int nblk = (int)(gridDim.x * gridDim.y * gridDim.z);
+    bf16_t* sx = reinterpret_cast<bf16_t*>(smem);                  // [LZ][LY][LX][CIN]
+    float* sd = reinterpret_cast<float*>(sx + LZ * LY * LX * CIN);  // [256][COUT]
+    const int x0 = blockIdx.x * 64, y0 = blockIdx.y * 4, zb = blockIdx.z * ZB;
     const int blk = (int)((blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x);
-    for (int c = threadIdx.x; c < LZ * LY * LX * CIN; c += 256) {
-        int ci = c % CIN;
-        int vox = c / CIN;
-        int lx = vox % LX;
-        int r = vox / LX;
-        int ly = r % LY;
-        int lz = r / LY;
-        int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z - 1 + lz;
-        bf16_t v = 0;
-        if (gx >= 0 && gx < S && gy >= 0 && gy < S && gz >= 0 && gz < S) v = x[(((int64_t)gz * S + gy) * S + gx) * CIN + ci];
-        sx[c] = v;
-    }
-    for (int c = threadIdx.x; c < 256 * COUT; c += 256) {
-        int co = c % COUT;
-        int v = c / COUT;
-        int gx = x0 + (v & 63), gy = y0 + (v >> 6);
-        float d = 0.f;
-        if (gx < S && gy < S) d = dy[(((int64_t)z * S + gy) * S + gx) * COUT + co];
-        sd[c] = d;
-    }
-    __syncthreads();
-    // units: (tap, ci block of 4, co block of 4) -> 16 entries
-    constexpr int UNITS = 27 * (CIN / 4) * (COUT / 4);
-    for (int u = threadIdx.x; u < UNITS; u += 256) {
-        int cb = u % (COUT / 4);
-        int r = u / (COUT / 4);
-        int ib = r % (CIN / 4);
-        int tap = r / (CIN / 4);
-        int dz = tap / 9, dyy = (tap / 3) % 3, dx = tap % 3;
-        float acc[4][4] = {};
-        for (int v = 0; v < 256; ++v) {
-            int vx = v & 63, vy = v >> 6;
-            const bf16_t* xs = sx + (((dz * LY) + (vy + dyy)) * LX + (vx + dx)) * CIN + ib * 4;
-            float xv[4] = {bf2f(xs[0]), bf2f(xs[1]), bf2f(xs[2]), bf2f(xs[3])};
-            const float4 dv = *reinterpret_cast<const float4*>(sd + v * COUT + cb * 4);
-            float d4[4] = {dv.x, dv.y, dv.z, dv.w};
+    float acc[NU][4][4];
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = fmaf(d4[a], xv[b], acc[a][b]);
-        }
-        float* pb = part + (size_t)blk * COUT * (KP + 1);
+    for (int q = 0; q < NU; ++q)
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) pb[(cb * 4 + a) * (KP + 1) + tap * CIN + ib * 4 + b] = acc[a][b];
+            for (int b = 0; b < 4; ++b) acc[q][a][b] = 0.f;
+    float bacc = 0.f;  // bias sum of channel threadIdx.x (< COUT)
+    for (int z = zb; z < zb + ZB && z < S; ++z) {
+        __syncthreads();  // the previous plane's readers are done
+        for (int c = threadIdx.x; c < LZ * LY * LX * CIN; c += 256) {
+            int ci = c % CIN;
+            int vox = c / CIN;
+            int lx = vox % LX;
+            int r = vox / LX;
+            int ly = r % LY;
+            int lz = r / LY;
+            int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z - 1 + lz;
+            bf16_t v = 0;
+            if (gx >= 0 && gx < S && gy >= 0 && gy < S && gz >= 0 && gz < S)
+                v = x[(((int64_t)gz * S + gy) * S + gx) * CIN + ci];
+            sx[c] = v;
+        }
+        for (int c = threadIdx.x; c < 256 * COUT; c += 256) {
+            int co = c % COUT;
+            int v = c / COUT;
+            int gx = x0 + (v & 63), gy = y0 + (v >> 6);
+            float d = 0.f;
+            if (gx < S && gy < S) d = dy[(((int64_t)z * S + gy) * S + gx) * COUT + co];
+            sd[c] = d;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NU; ++q) {
+            const int u = threadIdx.x + q * 256;
+            if (u < UNITS) {
+                int cb = u % (COUT / 4);
+                int r = u / (COUT / 4);
+                int ib = r % (CIN / 4);
+                int tap = r / (CIN / 4);
+                int dz = tap / 9, dyy = (tap / 3) % 3, dx = tap % 3;
+                for (int v = 0; v < 256; ++v) {
+                    int vx = v & 63, vy = v >> 6;
+                    const bf16_t* xs = sx + (((dz * LY) + (vy + dyy)) * LX + (vx + dx)) * CIN + ib * 4;
+                    float xv[4] = {bf2f(xs[0]), bf2f(xs[1]), bf2f(xs[2]), bf2f(xs[3])};
+                    const float4 dv = *reinterpret_cast<const float4*>(sd + v * COUT + cb * 4);
+                    float d4[4] = {dv.x, dv.y, dv.z, dv.w};
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) acc[q][a][b] = fmaf(d4[a], xv[b], acc[q][a][b]);
+                }
+            }
+        }
+        if (threadIdx.x < COUT)
+            for (int v = 0; v < 256; ++v) bacc += sd[v * COUT + threadIdx.x];
+    }
+    float* pb = part + (size_t)blk * COUT * (KP + 1);
+#pragma unroll
+    for (int q = 0; q < NU; ++q) {
+        const int u = threadIdx.x + q * 256;
+        if (u < UNITS) {
+            int cb = u % (COUT / 4);
+            int r = u / (COUT / 4);
+            int ib = r % (CIN / 4);
+            int tap = r / (CIN / 4);
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) pb[(cb * 4 + a) * (KP + 1) + tap * CIN + ib * 4 + b] = acc[q][a][b];
+        }
     }
     // bias partials and the padded K entries
-    for (int c = threadIdx.x; c < COUT; c += 256) {
-        float s = 0.f;
-        for (int v = 0; v < 256; ++v) s += sd[v * COUT + c];
-        float* pb = part + (size_t)blk * COUT * (KP + 1);
-        pb[c * (KP + 1) + KP] = s;
-        for (int k = 27 * CIN; k < KP; ++k) pb[c * (KP + 1) + k] = 0.f;
+    if (threadIdx.x < COUT) {
+        pb[threadIdx.x * (KP + 1) + KP] = bacc;
+        for (int k = 27 * CIN; k < KP; ++k) pb[threadIdx.x * (KP + 1) + k] = 0.f;
     }
-    (void)nblk;
+}
+
+// first reduction pass: red[chunk][e] = sum over the chunk's blocks of
+// part[blk][e] (chunks of consecutive blocks, fixed order)
+__global__ void k_reduce_chunks(const float* __restrict__ part, int nblk, int nent, int per, float* __restrict__ red)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nent) return;
+    const int b0 = blockIdx.y * per, b1 = min(b0 + per, nblk);
+    float s = 0.f;
+    for (int b = b0; b < b1; ++b) s += part[(size_t)b * nent + e];
+    red[(size_t)blockIdx.y * nent + e] = s;
 }
 
 // grad[e] (+)= sum over blocks of part[blk][e], fixed order
@@ -747,20 +783,25 @@ static int conv_wgrad_t(const bf16_t* x, const float* dy, float* part, size_t pa
                         hipStream_t s)
 {
     constexpr int KP = kpad(CIN);
+    constexpr int ZB = 8;
     size_t lds = (size_t)3 * 6 * 66 * CIN * 2 + (size_t)256 * COUT * 4;
-    dim3 grid((unsigned)((S + 63) / 64), (unsigned)((S + 3) / 4), (unsigned)S);
+    dim3 grid((unsigned)((S + 63) / 64), (unsigned)((S + 3) / 4), (unsigned)((S + ZB - 1) / ZB));
     int nblk = (int)(grid.x * grid.y * grid.z);
     int nent = COUT * (KP + 1);
-    if ((size_t)(nblk + 1) * nent > part_elems) {
+    const int nchunk = std::min(nblk, 64);
+    const int per = (nblk + nchunk - 1) / nchunk;
+    if ((size_t)(nblk + nchunk + 1) * nent > part_elems) {
         set_error("internal: weight-gradient scratch too small");
         return NDL_EINVAL;
     }
     if (lds > 64 * 1024)
-        NDL_HIP(hipFuncSetAttribute((const void*)k_conv_wgrad<CIN, COUT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)lds));
-    k_conv_wgrad<CIN, COUT><<<grid, 256, lds, s>>>(x, dy, part, S);
-    float* red = part + (size_t)nblk * nent;
-    k_reduce_parts<<<nb(nent), 256, 0, s>>>(part, nblk, nent, red, 0);
+        NDL_HIP(hipFuncSetAttribute((const void*)k_conv_wgrad<CIN, COUT, ZB>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    k_conv_wgrad<CIN, COUT, ZB><<<grid, 256, lds, s>>>(x, dy, part, S);
+    float* red1 = part + (size_t)nblk * nent;
+    float* red = red1 + (size_t)nchunk * nent;
+    k_reduce_chunks<<<dim3(nb(nent), (unsigned)nchunk), 256, 0, s>>>(part, nblk, nent, per, red1);
+    k_reduce_parts<<<nb(nent), 256, 0, s>>>(red1, nchunk, nent, red, 0);
     k_split_grad<<<nb(nent), 256, 0, s>>>(red, gw, gb, COUT, KP);
     NDL_HIP(hipGetLastError());
     return NDL_OK;
@@ -819,8 +860,9 @@ static int grads_workspace(NetState& st, int S)
     NDL_TRY(dmalloc(n, &st.g.du[2], vox(2) * 32));
     NDL_TRY(dmalloc(n, &n.g0, vox(0) * 32));
     NDL_TRY(dmalloc(n, &n.gb16, vox(0) * 32));
-    size_t blocks0 = (size_t)((S + 63) / 64) * ((S + 3) / 4) * S;
-    n.part_elems = (blocks0 + 1) * 32 * (kpad(32) + 1);
+    // weight-gradient partials: one per block of 64 x 4 x 8 voxels, 64 chunk sums, the total
+    size_t blocks0 = (size_t)((S + 63) / 64) * ((S + 3) / 4) * ((S + 7) / 8);
+    n.part_elems = (blocks0 + 64 + 1) * 32 * (kpad(32) + 1);
     NDL_TRY(dmalloc(n, &n.part, n.part_elems));
     st.Sg = S;
     return NDL_OK;
