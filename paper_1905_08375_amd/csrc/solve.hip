@@ -1489,9 +1489,11 @@ static int pcg_learned_t(const ndl_plan plan, const double* b, double* x, const 
             k_axpy2<T><<<grid_for(N), 256, 0, s>>>(N, alpha, (T*)vd.p, (T*)vr.p, (const T*)vp.p, (const T*)vq.p);
             NDL_TRY(dots((const T*)vr.p, (const T*)vr.p, nullptr, &rr, &dummy));
             if (std::sqrt(rr) <= want || !std::isfinite(rr)) break;
-            // stagnation of the learned directions: fall back to Jacobi
+            // stagnation of the learned directions (no 0.1% drop of the residual
+            // in 200 iterations; CG residuals may plateau for a while): fall
+            // back to Jacobi
             if (rr < 0.999 * best) { best = rr; since_best = 0; }
-            else if (++since_best > 50 && !jac) {
+            else if (++since_best > 200 && !jac) {
                 jac = true;
                 NDL_TRY(precond((const T*)vr.p, (T*)vz.p, true));
                 NDL_TRY(dots((const T*)vr.p, (const T*)vz.p, nullptr, &rz, &dummy));

@@ -69,6 +69,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIBPATH):
             raise ImportError(f"{LIBPATH} is missing: run __graft_entry__.build() (no fallback path exists)")
+        # torch first: the library then binds to the HIP runtime torch already
+        # loaded, so that one process holds one runtime (two copies of it do
+        # not share devices)
+        import torch  # noqa: F401
         L = C.CDLL(LIBPATH)
         vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
         sig = {
