@@ -198,8 +198,13 @@ int ndl_net_train_step(ndl_net net, int batch, int s, const float* r, const floa
  * back-propagated; *loss is its batch mean. */
 int ndl_net_train_step_energy(ndl_net net, ndl_plan plan, int batch, const float* r, const float* e, float lr,
                               float* loss, void* stream);
-/* z = M(r): r, z device arrays of n^3 (element type of the plan's prec);
- * the plan (3D, n divisible by 8) supplies delta and c for the features. */
+/* z = M(r), the network's part of the two-level preconditioner (the solver
+ * adds D^-1 r): r, z device arrays of n^3 (element type of the plan's prec).
+ * The plan (3D, n divisible by 8) supplies delta and c for the features; in
+ * linear mode it must be an FP32 case (b) plan, whose -L diagonal D (built
+ * once and cached with the plan's operator tables) scales the residual and
+ * the output.  Guide for the solver, not a solve: its quality is measured by
+ * ndl_cg_solve(precond = 1). */
 int ndl_precond_apply(ndl_net net, ndl_plan plan, const void* r, void* z, void* stream);
 
 /* Test hook: one 3x3x3 convolution layer of the network (zero padding) with
