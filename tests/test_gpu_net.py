@@ -74,3 +74,81 @@ def test_train_step_reduces_loss_and_roundtrips(tmp_path):
     l1 = ndl.ndl_net_train_step(net, r, feat, e, 0.0)
     l2 = ndl.ndl_net_train_step(net2, r, feat, e, 0.0)
     assert abs(l1 - l2) <= 1e-6 * abs(l1)
+
+
+def _read_layers(net):
+    """FP32 master weights and biases of each layer, read back through the
+    library's save format (8-byte magic, int64 step, then per layer int32
+    (cout, KP), weights [cout][KP], biases [cout])."""
+    import os
+    import struct
+    import tempfile
+    fd, path = tempfile.mkstemp(suffix=".bin")
+    os.close(fd)
+    try:
+        ndl.ndl_net_save(net, path)
+        raw = open(path, "rb").read()
+    finally:
+        os.remove(path)
+    off, layers = 16, []
+    while off < len(raw):
+        cout, kp = struct.unpack_from("<ii", raw, off)
+        w = np.frombuffer(raw, np.float32, cout * kp, off + 8).reshape(cout, kp).astype(np.float64)
+        b = np.frombuffer(raw, np.float32, cout, off + 8 + 4 * cout * kp).astype(np.float64)
+        layers.append((w, b))
+        off += 8 + 4 * (cout * kp + cout)
+    return layers
+
+
+def test_linear_network_forward_matches_oracle():
+    """The whole preconditioner network in linear mode (the shipped weights) on a
+    16^3 field against the FP64 reference composed from the oracle's layers:
+    residual scaled by D^-1/2 (D from the oracle's case (b) diagonal) and
+    normalised to unit RMS, 13 convolutions without biases or activations,
+    3 average poolings, 3 nearest upsamplings with skip additions, BF16 at the
+    GPU's storage points, channel 0 of the output layer rescaled."""
+    import torch
+    import oracle as O
+    from paper_1905_08375_amd import precond_train as PT
+    if not __import__("os").path.exists(PT.WEIGHTS):
+        pytest.skip("no trained weights in the tree")
+    say("case linear network forward")
+    n = 16
+    plan, b, feat, w = PT.problem_3d(n, 7)
+    net = PT.load_net(PT.WEIGHTS)
+    g = np.random.default_rng(5)
+    r = g.standard_normal((n, n, n)).astype(np.float32)
+    z = torch.empty((n, n, n), device="cuda")
+    ndl.ndl_precond_apply(net, plan, torch.from_numpy(r).cuda(), z)
+    torch.cuda.synchronize()
+    got = z.cpu().numpy().astype(np.float64)
+    # reference
+    P = O.Problem(dim=3, n=n, R=4, form="div", kernel="frac")
+    diag = O.div_diag(P, w["delta"].astype(np.float32), w["coef"].astype(np.float32))
+    diag = np.abs(diag)
+    dinv = (np.float32(1.0) / diag.astype(np.float32)).astype(np.float64)
+    sq = np.sqrt(dinv)
+    rs = (r.astype(np.float64) * sq).astype(np.float32).astype(np.float64)
+    rscale = np.sqrt(rs.size / np.sum(rs * rs))
+    x = np.zeros((n, n, n, 8))
+    x[..., 0] = NO.bf16_round(rs * rscale)
+    layers = _read_layers(net)
+    cins = [8, 16, 16, 16, 16, 32, 32, 32, 32, 32, 16, 16, 16]
+
+    def conv(i, a):
+        wk, _ = layers[i]
+        return NO.conv3d(a, NO.unpack_weights(NO.bf16_round(wk), cins[i]))
+
+    bf = NO.bf16_round
+    a0 = bf(conv(0, x)); a1 = bf(conv(1, a0))
+    a2 = bf(conv(2, bf(NO.pool2(a1)))); a3 = bf(conv(3, a2))
+    a4 = bf(conv(4, bf(NO.pool2(a3)))); a5 = bf(conv(5, a4))
+    a6 = bf(conv(6, bf(NO.pool2(a5)))); a7 = bf(conv(7, a6))
+    a8 = bf(conv(8, bf(NO.up2(a7) + a5))); a9 = bf(conv(9, a8))
+    a10 = bf(conv(10, bf(NO.up2(a9) + a3)))
+    a11 = bf(conv(11, bf(NO.up2(a10) + a1)))
+    head = conv(12, a11)[..., 0]
+    ref = sq * head / (rscale * PT.TARGET_SCALE)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    say("  rel l2", err)
+    assert err < 2e-3
