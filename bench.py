@@ -246,7 +246,9 @@ def bench_sweep(n=1024, ms=(2, 4, 8, 16, 32, 64), example1=True):
 
         row["fast_ms"] = run(lambda: ndl.ndl_apply_fast(plan, u, o, 1)) * 1e3
         if delta < 0.5:
+            ndl.ndl_autotune(plan)
             row["direct_ms"] = run(lambda: ndl.ndl_apply(plan, u, o, 1)) * 1e3
+            row["direct_tile"] = [plan.info().tile_x, plan.info().tile_y]
             row["fast_speedup"] = row["direct_ms"] / row["fast_ms"]
         plan.close()
         out.append(row)

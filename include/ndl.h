@@ -110,8 +110,10 @@ typedef struct {
     int32_t fast_levels;  /* tree levels used by the hierarchical path (0 = none) */
     double pairs_per_point; /* average lattice-ball size (neighbours per node) */
     int32_t pair_order;   /* summation order of the direct kernel in use: 0 = pairs
-                             by increasing |z|^2, 1 = column by column; variants
-                             with the same order give bitwise identical results */
+                             by increasing |z|^2, 1 = column by column (unrolled),
+                             2 = column by column for run-time horizons (2D
+                             diffusion with J > 7); variants with the same order
+                             give bitwise identical results */
 } ndl_plan_info;
 int ndl_plan_get_info(ndl_plan plan, ndl_plan_info* info);
 

@@ -28,7 +28,7 @@ int hip_fail(hipError_t e, const char* what, const char* file, int line)
 static void free_plan(Plan* p)
 {
     if (!p) return;
-    void* bufs[] = {p->d_k, p->d_scale, p->d_invm2, p->d_split, p->d_invT, p->d_pairs, p->d_pairw,
+    void* bufs[] = {p->d_k, p->d_scale, p->d_invm2, p->d_split, p->d_invT, p->d_pairs, p->d_pairw, p->d_wq,
                     p->d_full, p->d_fullw, p->d_pyr, p->d_cntM};
     for (void* b : bufs)
         if (b) (void)hipFree(b);

@@ -70,6 +70,7 @@ struct Plan {
     // half-ball pair table of the generic direct kernel (device, sorted by q)
     int4* d_pairs = nullptr;   // (z0, z1, z2, q)
     void* d_pairw = nullptr;   // weights |z|^expo (diffusion) or |z|^(expo-2) (PD)
+    double* d_wq = nullptr;    // |z|^expo by q = |z|^2, q = 0..kmax (2D diffusion, large horizons)
     int npairs = 0;
     int4* d_full = nullptr;    // full ball (case (b))
     void* d_fullw = nullptr;

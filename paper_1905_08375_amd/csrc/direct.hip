@@ -497,6 +497,11 @@ static int plan_fields_t(Plan& p, hipStream_t s)
     p.nfull = (int)fb.size();
     NDL_TRY(upload((void**)&p.d_pairs, hb));
     NDL_TRY(upload(&p.d_pairw, hw));
+    if (p.dim == 2 && p.model == NDL_DIFFUSION && p.form == NDL_ND) {
+        std::vector<double> wq(p.kmax + 1, 0.0);
+        for (int64_t q = 1; q <= p.kmax; ++q) wq[q] = std::pow(std::sqrt((double)q), e);
+        NDL_TRY(upload((void**)&p.d_wq, wq));
+    }
     NDL_TRY(upload((void**)&p.d_full, fb));
     NDL_TRY(upload(&p.d_fullw, fw));
     // T_e[k] = sum_{0<|z|^2<=k} |z|^(e+2): the discrete second moment up to the m factor

@@ -98,6 +98,36 @@ def test_pd_batched(prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("kernel", [ndl.NDL_G_FRAC, ndl.NDL_G_CONST])
+def test_2d_wide_horizon_every_variant(prec, kernel):
+    """2D diffusion with horizons of 8 to 21 nodes (past the unrolled tables:
+    the run-time-horizon kernel) on a ragged grid: every tile matches the
+    oracle and all are bitwise alike."""
+    import torch
+    from gpuhelp import dev
+    say(f"case 2d wide prec={prec} kernel={kernel}")
+    n, R = 100, 22
+    delta, c, u = rand_problem(2, n, R, 8.0, 21.0, seed=55)
+    kw = dict(kernel=kernel)
+    ref = oracle_apply(2, n, R, delta, c, u, prec, **kw)
+    d_d, d_c, d_u = dev(delta, prec), dev(c, prec), dev(u, prec)
+    plan = ndl.ndl_plan_create(ndl.make_problem(2, n, R, d_d, d_c, kernel=kernel, prec=prec), keep=(d_d, d_c))
+    out = torch.zeros((n, n), dtype=d_u.dtype, device="cuda")
+    first = None
+    for v in range(ndl.ndl_plan_num_variants(plan)):
+        ndl.ndl_plan_set_variant(plan, v)
+        assert plan.info().pair_order == 2
+        out.zero_()
+        ndl.ndl_apply(plan, d_u, out, 1)
+        torch.cuda.synchronize()
+        o = out.cpu().numpy()
+        err = rel_l2(o, ref)
+        assert err <= TOL[prec], (v, err)
+        first = o if first is None else first
+        assert np.array_equal(o, first), v
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_pd_every_tile_variant(prec):
     """Peridynamics on a ragged 2D grid (horizon up to 12 nodes): every tile the
     autotuner may pick matches the oracle, all bitwise alike (one pair order)."""
