@@ -48,6 +48,11 @@ __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b)  // ceil(a / b), b
     return -fdiv(-a, b);
 }
 
+// floor and ceiling of v / 2^s (panel sides are powers of two: shifts, not
+// 64-bit divisions; the arithmetic right shift rounds toward minus infinity)
+__host__ __device__ inline int64_t fshr(int64_t v, int s) { return v >> s; }
+__host__ __device__ inline int64_t cshr(int64_t v, int s) { return -((-v) >> s); }
+
 // farthest squared offset from x to the panel [j a, j a + a - 1] on one axis
 __host__ __device__ inline int64_t far2(int64_t x, int64_t j, int64_t a)
 {
@@ -55,14 +60,14 @@ __host__ __device__ inline int64_t far2(int64_t x, int64_t j, int64_t a)
     return lo * lo > hi * hi ? lo * lo : hi * hi;
 }
 
-// panels of side a on the last axis lying inside {|d| <= isqrt(A)} and inside Omega
-__host__ __device__ inline void inside_run(int64_t x, int64_t A, int64_t a, int64_t E, int64_t& lo, int64_t& hi)
+// panels of side 2^s on the last axis lying inside {|d| <= isqrt(A)} and inside Omega
+__host__ __device__ inline void inside_run(int64_t x, int64_t A, int s, int64_t E, int64_t& lo, int64_t& hi)
 {
     if (A < 0 || E <= 0) { lo = 0; hi = -1; return; }
     int64_t r = isqrt64(A);
-    lo = cdiv(x - r, a);
+    lo = cshr(x - r, s);
     if (lo < 0) lo = 0;
-    hi = fdiv(x + r + 1, a) - 1;
+    hi = fshr(x + r + 1, s) - 1;
     if (hi > E - 1) hi = E - 1;
 }
 
@@ -107,9 +112,9 @@ __host__ __device__ inline void decompose_runs(int dim, int64_t n, const int64_t
         // row ranges on leading axes
         int64_t rlo[2] = {0, 0}, rhi[2] = {0, 0};
         for (int ax = 0; ax < dim - 1; ++ax) {
-            rlo[ax] = cdiv(x[ax] - J, a);
+            rlo[ax] = cshr(x[ax] - J, s);
             if (rlo[ax] < 0) rlo[ax] = 0;
-            rhi[ax] = fdiv(x[ax] + J + 1, a) - 1;
+            rhi[ax] = fshr(x[ax] + J + 1, s) - 1;
             if (rhi[ax] > E - 1) rhi[ax] = E - 1;
         }
         for (int64_t r0 = rlo[0]; r0 <= rhi[0]; ++r0) {
@@ -125,10 +130,10 @@ __host__ __device__ inline void decompose_runs(int dim, int64_t n, const int64_t
                     if (prow) { if ((r1 >> 1) > Ep - 1) prow = false; else Ap -= far2(x[1], r1 >> 1, 2 * a); }
                 }
                 int64_t lo, hi;
-                inside_run(xl, A, a, E, lo, hi);
+                inside_run(xl, A, s, E, lo, hi);
                 if (lo > hi) continue;
                 int64_t plo = 0, phi = -1;
-                if (prow) inside_run(xl, Ap, 2 * a, Ep, plo, phi);
+                if (prow) inside_run(xl, Ap, s + 1, Ep, plo, phi);
                 if (plo > phi) {
                     emit(s, r0, r1, lo, hi);
                 } else {
