@@ -28,6 +28,7 @@
 namespace ndl {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint16_t bf16_t;  // storage type
 
@@ -65,77 +66,141 @@ constexpr int kpad(int cin) { return ((27 * cin + 31) / 32) * 32; }
 // its 4 waves owns one y row.  The input is held as a rolling window of three
 // haloed planes in LDS: plane z+2 is read from HBM into registers while plane
 // z is being convolved and written into the slot of plane z-1 afterwards, so
-// each input plane is fetched once per block and the weights once per ZB
-// planes.  The 3x3x3 convolution is an implicit GEMM on
-// v_mfma_f32_16x16x32_bf16: A = 16 output voxels x 32 of the 27 CIN taps,
-// B = the same 32 taps x 16 output channels.
+// each input plane is fetched once per block and the weights once per block.
+// The 3x3x3 convolution is an implicit GEMM on v_mfma_f32_16x16x32_bf16 with
+// the weights as the A operand (16 output channels x 32 of the 27 CIN taps)
+// and the input as B (the same 32 taps x 16 output voxels), so that a lane's
+// four results are four consecutive channels of one voxel: one 8-byte (BF16)
+// or 16-byte (FP32) store per lane and tile, 16 voxels of a wave contiguous.
+//
+// Everything that does not depend on z is computed once per block: the LDS
+// offset of every (chunk of 32 taps, lane) input fragment, the global offset
+// and LDS slot of every staged 16-byte chunk, and (for the full-resolution
+// layers, at most 14 fragments) the weight fragments, held in registers.
+//
+// LDS plane layout: voxel v of the haloed plane holds CIN/8 chunks of 8
+// channels; chunk h sits at slot v CPV + (h ^ ((v / (8/CPV)) mod CPV)), so
+// that 8 consecutive voxels read at one chunk index cover all 32 banks.
 template <int CIN, int XB>
 struct ConvPlane {
     static constexpr int LX = XB + 2, LY = 6, CPV = CIN / 8;
     static constexpr int CHUNKS = LY * LX * CPV;  // 16-byte chunks of one haloed plane
     static constexpr int PER = (CHUNKS + 255) / 256;
+    static constexpr int VPL = 8 / CPV;  // voxels per 128 bytes
 };
 
-template <int CIN, int XB, int PER>
-__device__ __forceinline__ void conv_fetch_plane(uint4 (&r)[PER], const bf16_t* __restrict__ in, int S, int x0,
-                                                 int y0, int gz)
+template <int CPV>
+__host__ __device__ constexpr int plane_slot(int v, int h)
 {
-    using CPL = ConvPlane<CIN, XB>;
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        const int c = threadIdx.x + q * 256;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (c < CPL::CHUNKS) {
-            const int cc = c % CPL::CPV, vox = c / CPL::CPV;
-            const int lx = vox % CPL::LX, ly = vox / CPL::LX;
-            const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-            if (gz >= 0 && gz < S && gx >= 0 && gx < S && gy >= 0 && gy < S)
-                v = reinterpret_cast<const uint4*>(in + (((int64_t)gz * S + gy) * S + gx) * CIN)[cc];
-        }
-        r[q] = v;
-    }
+    return CPV == 1 ? v : v * CPV + (h ^ ((v / (8 / CPV)) & (CPV - 1)));
 }
 
-template <int CIN, int XB, int PER>
-__device__ __forceinline__ void conv_store_plane(const uint4 (&r)[PER], bf16_t* __restrict__ slot)
+// tap of the 8 k-values that lane group kb feeds in chunk kc (27 or more = padding)
+template <int CIN>
+__host__ __device__ constexpr int chunk_tap(int kc, int kb)
 {
-    using CPL = ConvPlane<CIN, XB>;
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        const int c = threadIdx.x + q * 256;
-        if (c < CPL::CHUNKS) reinterpret_cast<uint4*>(slot)[c] = r[q];
-    }
+    return (kc * 32 + kb * 8) / CIN;
 }
 
 template <int CIN, int COUT, int XB, int ACT, int OUTK, int ZB>
 __global__ __launch_bounds__(256) void k_conv_fwd(const bf16_t* __restrict__ in, const bf16_t* __restrict__ w,
-                                                  const float* __restrict__ bias, void* __restrict__ out, int S)
+                                                  const float* __restrict__ bias, void* __restrict__ out, int S,
+                                                  int nbx, int nby, int nblocks)
 {
     using CPL = ConvPlane<CIN, XB>;
+    constexpr int CPV = CPL::CPV, LX = CPL::LX, PER = CPL::PER;
     constexpr int KP = kpad(CIN);
-    constexpr int LX = CPL::LX, LY = CPL::LY;
-    constexpr int PLANE = LY * LX * CIN;  // bf16 elements of one haloed plane
-    constexpr int NT = XB / 16;           // MFMA row tiles per wave
-    constexpr int NC = COUT / 16;         // MFMA column tiles
+    constexpr int KC = KP / 32;   // chunks of 32 k-values
+    constexpr int NT = XB / 16;   // MFMA voxel tiles per wave
+    constexpr int NC = COUT / 16; // MFMA channel tiles
+    constexpr int PL16 = CPL::CHUNKS;  // 16-byte slots of one haloed plane
+    constexpr bool WREG = KC * NC <= 14;
+    constexpr int KPL = KP + 8;   // LDS pitch of a weight row (breaks the bank period)
     extern __shared__ __align__(16) unsigned char smem[];
-    bf16_t* sin = reinterpret_cast<bf16_t*>(smem);  // [3][LY][LX][CIN], plane p in slot p mod 3
-    bf16_t* sw = sin + 3 * PLANE;                   // [COUT][KP]
-    const int x0 = blockIdx.x * XB, y0 = blockIdx.y * 4, zb = blockIdx.z * ZB;
+    uint4* sin = reinterpret_cast<uint4*>(smem);                // [3][PL16], plane p in slot p mod 3
+    bf16_t* sw = reinterpret_cast<bf16_t*>(sin + 3 * PL16);     // [COUT][KPL] (weights in LDS only)
+
+    // XCD-aware order: each XCD walks a contiguous run of patches, x fastest,
+    // so the y neighbours that share halo rows sit in the same L2
+    const int b = xcd_tile(blockIdx.x, nblocks);
+    const int bx = b % nbx, byz = b / nbx;
+    const int x0 = bx * XB, y0 = (byz % nby) * 4, zb = (byz / nby) * ZB;
     const int zend = min(zb + ZB, S);
-    // weights (16-byte chunks) and the first three planes zb-1, zb, zb+1
-    const int wchunks = COUT * KP / 8;
-    for (int c = threadIdx.x; c < wchunks; c += 256)
-        reinterpret_cast<uint4*>(sw)[c] = reinterpret_cast<const uint4*>(w)[c];
-    uint4 pre[CPL::PER];
-#pragma unroll
-    for (int dz = -1; dz <= 1; ++dz) {
-        conv_fetch_plane<CIN, XB, CPL::PER>(pre, in, S, x0, y0, zb + dz);
-        conv_store_plane<CIN, XB, CPL::PER>(pre, sin + ((zb + dz + 3) % 3) * PLANE);
-    }
-    conv_fetch_plane<CIN, XB, CPL::PER>(pre, in, S, x0, y0, zb + 2);  // in flight during plane zb
-    __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int row = lane & 15, kb = lane >> 4;
+    const int64_t pstride = (int64_t)S * S * CIN;  // elements per input plane
+
+    // staged chunks of this thread: byte offset within an input plane (past
+    // any plane outside the grid in x or y, where the buffer load returns
+    // zero) and LDS slot
+    int goff[PER], gslot[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int c = threadIdx.x + q * 256;
+        const int vox = c / CPV, cc = c - vox * CPV;
+        const int ly = vox / LX, lx = vox - ly * LX;
+        const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+        const bool ok = c < CPL::CHUNKS && gx >= 0 && gx < S && gy >= 0 && gy < S;
+        goff[q] = ok ? ((gy * S + gx) * CIN + cc * 8) * 2 : (int)0x80000000u;
+        gslot[q] = c < CPL::CHUNKS ? plane_slot<CPV>(vox, cc) : -1;
+    }
+    // one input plane as a buffer resource: planes outside the grid get no
+    // records, so every load from them returns zero
+    const int plane_bytes = S * S * CIN * 2;
+    auto fetch = [&](uint4 (&r)[PER], int gz) {
+        const bool zin = gz >= 0 && gz < S;
+        const bf16_t* pz = in + (int64_t)(zin ? gz : 0) * pstride;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t*>(pz), (short)0, zin ? plane_bytes : 0, 0x00020000);
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            r[q] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, goff[q], 0, 0));
+    };
+    auto store = [&](const uint4 (&r)[PER], int slot) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            if ((q + 1) * 256 <= CPL::CHUNKS || gslot[q] >= 0) sin[slot * PL16 + gslot[q]] = r[q];
+    };
+
+    // weights: registers (A fragments of every chunk) or LDS
+    uint4 wr[WREG ? KC * NC : 1];
+    if (WREG) {
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                wr[kc * NC + c] = *reinterpret_cast<const uint4*>(w + (c * 16 + row) * KP + kc * 32 + kb * 8);
+    } else {
+        for (int e = threadIdx.x; e < COUT * (KP / 8); e += 256) {
+            const int co = e / (KP / 8), k8 = e - co * (KP / 8);
+            *reinterpret_cast<uint4*>(sw + co * KPL + k8 * 8) = reinterpret_cast<const uint4*>(w)[e];
+        }
+    }
+    float bv[NC][4];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bv[c][e] = bias ? bias[c * 16 + 4 * kb + e] : 0.f;
+
+    // LDS slot (within a plane) of this lane's B fragment of every chunk, tile 0
+    int aoff[KC];
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+        const int k0 = kc * 32 + kb * 8;
+        const int tap = k0 / CIN, h = (k0 % CIN) / 8;
+        const int t2 = tap < 27 ? tap : 0;
+        const int dy = (t2 / 3) % 3, dx = t2 % 3;
+        aoff[kc] = plane_slot<CPV>((wv + dy) * LX + row + dx, h);
+    }
+
+    uint4 pre[PER];
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz) {
+        fetch(pre, zb + dz);
+        store(pre, (zb + dz + 3) % 3);
+    }
+    fetch(pre, zb + 2);  // in flight during plane zb
+    __syncthreads();
     const int y = y0 + wv;
     for (int z = zb; z < zend; ++z) {
         f32x4 acc[NT][NC];
@@ -144,67 +209,73 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const bf16_t* __restrict__ in,
 #pragma unroll
             for (int c = 0; c < NC; ++c) acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
         const int s0 = (z + 2) % 3;  // slot of plane z - 1 (z >= 0, so z + 2 > 0)
-#pragma unroll 2
-        for (int kc = 0; kc < KP / 32; ++kc) {
-            const int k0 = kc * 32 + kb * 8;
-            const int tap = k0 / CIN, ci = k0 % CIN;
-            bf16x8 a[NT];
-            if (tap < 27) {
-                const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
-                int sl = s0 + dz;
-                sl = sl >= 3 ? sl - 3 : sl;
-                const bf16_t* pl = sin + sl * PLANE;
+        const int sb[3] = {s0 * PL16, (s0 == 2 ? 0 : s0 + 1) * PL16, (s0 == 0 ? 2 : s0 - 1) * PL16};
 #pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    const int lx = t * 16 + row + dx;
-                    a[t] = *reinterpret_cast<const bf16x8*>(pl + ((wv + dy) * LX + lx) * CIN + ci);
-                }
+        for (int kc = 0; kc < KC; ++kc) {
+            // plane of this lane's tap: a chunk spans at most two planes
+            const int tlo = chunk_tap<CIN>(kc, 0), thi = min(chunk_tap<CIN>(kc, 3), 26);
+            const int dzlo = tlo / 9, dzhi = thi / 9;
+            int base;
+            if (dzlo == dzhi) {
+                base = sb[dzlo];
             } else {
+                const int dzl = min(chunk_tap<CIN>(kc, kb), 26) / 9;
+                base = dzl == dzlo ? sb[dzlo] : sb[dzhi];
+            }
+            const uint4* src = sin + base + aoff[kc];
+            bf16x8 bfrag[NT];
 #pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    uint4 zz = make_uint4(0, 0, 0, 0);
-                    a[t] = *reinterpret_cast<const bf16x8*>(&zz);
-                }
+            for (int t = 0; t < NT; ++t) {
+                uint4 v = src[t * 16 * CPV];
+                if (chunk_tap<CIN>(kc, 3) >= 27 && chunk_tap<CIN>(kc, kb) >= 27) v = make_uint4(0, 0, 0, 0);
+                bfrag[t] = *reinterpret_cast<const bf16x8*>(&v);
             }
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                const bf16x8 bb = *reinterpret_cast<const bf16x8*>(sw + (c * 16 + row) * KP + k0);
+                uint4 wa;
+                if (WREG) wa = wr[(WREG ? kc * NC + c : 0)];
+                else wa = *reinterpret_cast<const uint4*>(sw + (c * 16 + row) * KPL + kc * 32 + kb * 8);
+                const bf16x8 afrag = *reinterpret_cast<const bf16x8*>(&wa);
 #pragma unroll
                 for (int t = 0; t < NT; ++t)
-                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], bb, acc[t][c], 0, 0, 0);
+                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag[t], acc[t][c], 0, 0, 0);
             }
         }
-        // D layout: lane holds rows 4*kb .. 4*kb+3 of column `row`
+        // D layout: lane holds channels c 16 + 4 kb .. + 3 of voxel t 16 + row
         if (y < S) {
+            const int64_t vrow = ((int64_t)z * S + y) * S + x0;
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
+                const int x = x0 + t * 16 + row;
+                if (x >= S) continue;
+                const int64_t vo = vrow + t * 16 + row;
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
-                    const int co = c * 16 + row;
-                    const float bv = bias ? bias[co] : 0.f;
+                    float v[4];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int x = x0 + t * 16 + kb * 4 + i;
-                        if (x >= S) continue;
-                        float v = acc[t][c][i] + bv;
-                        if (ACT == 1) v = v > 0.f ? v : 0.f;
-                        const int64_t o = (((int64_t)z * S + y) * S + x) * COUT + co;
-                        if (OUTK == 2) {
-                            if (co == 0) reinterpret_cast<float*>(out)[((int64_t)z * S + y) * S + x] = v;
-                        } else if (OUTK == 1) {
-                            reinterpret_cast<float*>(out)[o] = v;
-                        } else {
-                            reinterpret_cast<bf16_t*>(out)[o] = f2bf(v);
-                        }
+                    for (int e = 0; e < 4; ++e) {
+                        v[e] = acc[t][c][e] + bv[c][e];
+                        if (ACT == 1) v[e] = v[e] > 0.f ? v[e] : 0.f;
+                    }
+                    if (OUTK == 2) {
+                        if (c == 0 && kb == 0) reinterpret_cast<float*>(out)[vo] = v[0];
+                    } else if (OUTK == 1) {
+                        *reinterpret_cast<float4*>(reinterpret_cast<float*>(out) + vo * COUT + c * 16 + 4 * kb) =
+                            make_float4(v[0], v[1], v[2], v[3]);
+                    } else {
+                        bf16x4 o;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) o[e] = (__bf16)v[e];
+                        *reinterpret_cast<bf16x4*>(reinterpret_cast<bf16_t*>(out) + vo * COUT + c * 16 + 4 * kb) = o;
                     }
                 }
             }
         }
         if (z + 1 < zend) {
             __syncthreads();  // every wave is done with plane z - 1
-            conv_store_plane<CIN, XB, CPL::PER>(pre, sin + s0 * PLANE);  // plane z + 2 into its slot
+            store(pre, s0);   // plane z + 2 into its slot
             __syncthreads();
-            if (z + 2 < zend) conv_fetch_plane<CIN, XB, CPL::PER>(pre, in, S, x0, y0, z + 3);
+            if (z + 2 < zend) fetch(pre, z + 3);
         }
     }
 }
@@ -736,19 +807,23 @@ static int conv_fwd_t(const bf16_t* in, const bf16_t* w, const float* bias, void
 {
     constexpr int XB = CIN >= 32 ? 32 : 64;
     constexpr int KP = kpad(CIN);
-    size_t lds = (size_t)3 * 6 * (XB + 2) * CIN * 2 + (size_t)COUT * KP * 2;
     constexpr int ZB = 8;
-    dim3 grid((unsigned)((S + XB - 1) / XB), (unsigned)((S + 3) / 4), (unsigned)((S + ZB - 1) / ZB));
+    using CPL = ConvPlane<CIN, XB>;
+    constexpr bool WREG = (KP / 32) * (COUT / 16) <= 14;
+    const size_t lds = (size_t)3 * CPL::CHUNKS * 16 + (WREG ? 0 : (size_t)COUT * (KP + 8) * 2);
+    const int nbx = (S + XB - 1) / XB, nby = (S + 3) / 4, nbz = (S + ZB - 1) / ZB;
+    const int nblocks = nbx * nby * nbz;
     const void* fn;
     if (outk == 2) fn = (const void*)k_conv_fwd<CIN, COUT, XB, 0, 2, ZB>;
     else if (outk == 1) fn = (const void*)k_conv_fwd<CIN, COUT, XB, 0, 1, ZB>;
     else if (act) fn = (const void*)k_conv_fwd<CIN, COUT, XB, 1, 0, ZB>;
     else fn = (const void*)k_conv_fwd<CIN, COUT, XB, 0, 0, ZB>;
     if (lds > 64 * 1024) NDL_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    if (outk == 2) k_conv_fwd<CIN, COUT, XB, 0, 2, ZB><<<grid, 256, lds, s>>>(in, w, bias, out, S);
-    else if (outk == 1) k_conv_fwd<CIN, COUT, XB, 0, 1, ZB><<<grid, 256, lds, s>>>(in, w, bias, out, S);
-    else if (act) k_conv_fwd<CIN, COUT, XB, 1, 0, ZB><<<grid, 256, lds, s>>>(in, w, bias, out, S);
-    else k_conv_fwd<CIN, COUT, XB, 0, 0, ZB><<<grid, 256, lds, s>>>(in, w, bias, out, S);
+    dim3 grid((unsigned)nblocks);
+    if (outk == 2) k_conv_fwd<CIN, COUT, XB, 0, 2, ZB><<<grid, 256, lds, s>>>(in, w, bias, out, S, nbx, nby, nblocks);
+    else if (outk == 1) k_conv_fwd<CIN, COUT, XB, 0, 1, ZB><<<grid, 256, lds, s>>>(in, w, bias, out, S, nbx, nby, nblocks);
+    else if (act) k_conv_fwd<CIN, COUT, XB, 1, 0, ZB><<<grid, 256, lds, s>>>(in, w, bias, out, S, nbx, nby, nblocks);
+    else k_conv_fwd<CIN, COUT, XB, 0, 0, ZB><<<grid, 256, lds, s>>>(in, w, bias, out, S, nbx, nby, nblocks);
     NDL_HIP(hipGetLastError());
     return NDL_OK;
 }

@@ -52,6 +52,37 @@ def test_conv_layer(cin, cout, S):
     assert np.all(gw.cpu().numpy()[:, 27 * cin:] == 0)
 
 
+@pytest.mark.parametrize("cin,cout,S", [(8, 16, 72), (16, 16, 72), (16, 32, 40), (32, 32, 40), (32, 16, 40)])
+def test_conv_layer_many_patches(cin, cout, S):
+    """Forward and data gradient over many (x, y, z) patches with ragged
+    edges on every axis (the patch grid is walked in its XCD order)."""
+    import torch
+    say(f"case conv {cin}->{cout} S={S} (many patches)")
+    g = np.random.default_rng(cin * 1000 + cout + S)
+    x = NO.bf16_round(g.standard_normal((S, S, S, cin)))
+    w = g.standard_normal((cout, 27, cin)) / np.sqrt(27 * cin)
+    b = g.standard_normal(cout)
+    dy = g.standard_normal((S, S, S, cout))
+    wk = NO.pack_weights(w)
+    d = lambda a, t=torch.float32: torch.from_numpy(np.ascontiguousarray(a)).to(t).cuda()
+    xb = torch.from_numpy(NO.bf16_bits(x).view(np.int16)).cuda()
+    y = torch.zeros((S, S, S, cout), device="cuda")
+    dx = torch.zeros((S, S, S, cin), device="cuda")
+    ndl.ndl_net_conv_test(cin, cout, S, xb, d(wk), d(b), y=y, dy=d(dy) if cin >= 16 else None,
+                          dx=dx if cin >= 16 else None)
+    torch.cuda.synchronize()
+    wr = NO.bf16_round(w)
+    yref = NO.conv3d(x, wr, b)
+    err = np.abs(y.cpu().numpy() - yref).max() / np.abs(yref).max()
+    say("  fwd", err)
+    assert err < 1e-5
+    if cin >= 16:
+        dxref = NO.conv3d_dgrad(NO.bf16_round(dy), wr)
+        err = np.abs(dx.cpu().numpy() - dxref).max() / np.abs(dxref).max()
+        say("  dgrad", err)
+        assert err < 1e-5
+
+
 def test_train_step_reduces_loss_and_roundtrips(tmp_path):
     import torch
     say("case train")
