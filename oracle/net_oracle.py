@@ -45,6 +45,21 @@ def conv3d(x, w, b=None):
     return y
 
 
+def conv3d_planes(x, w, b, zs):
+    """The planes z in zs of conv3d(x, w, b), each from its own three input planes."""
+    S = x.shape[0]
+    p = np.pad(x, ((1, 1), (1, 1), (1, 1), (0, 0)))
+    out = []
+    for z in zs:
+        y = np.zeros((S, S, w.shape[0]))
+        for t, (dz, dy, dx) in enumerate(TAPS):
+            y += p[z + dz, dy:dy + S, dx:dx + S] @ w[:, t, :].T
+        if b is not None:
+            y += b
+        out.append(y)
+    return np.stack(out)
+
+
 def conv3d_dgrad(dy, w):
     """dx[v][c] = sum_{tap, o} w[o][tap][c] dy[v - off(tap)][o] (the adjoint of conv3d)."""
     S = dy.shape[0]

@@ -62,8 +62,8 @@ constexpr int kpad(int cin) { return ((27 * cin + 31) / 32) * 32; }
 // out : [S][S][S][COUT] bf16 (OUTK 0, ACT 1 = relu), fp32 (OUTK 1), or only
 // channel 0 as a compact fp32 [S][S][S] (OUTK 2, the network's output layer)
 //
-// A block computes an XB x 4 (x, y) patch for ZB consecutive z planes; each of
-// its 4 waves owns one y row.  The input is held as a rolling window of three
+// A block computes an XB x NWV (x, y) patch for ZB consecutive z planes; each
+// of its NWV waves owns one y row.  The input is held as a rolling window of three
 // haloed planes in LDS: plane z+2 is read from HBM into registers while plane
 // z is being convolved and written into the slot of plane z-1 afterwards, so
 // each input plane is fetched once per block and the weights once per block.
@@ -81,11 +81,29 @@ constexpr int kpad(int cin) { return ((27 * cin + 31) / 32) * 32; }
 // LDS plane layout: voxel v of the haloed plane holds CIN/8 chunks of 8
 // channels; chunk h sits at slot v CPV + (h ^ ((v / (8/CPV)) mod CPV)), so
 // that 8 consecutive voxels read at one chunk index cover all 32 banks.
-template <int CIN, int XB>
+// a + b for 8 BF16 pairs, summed in FP32 and rounded to nearest even
+__device__ __forceinline__ uint32_t bf16x2_add(uint32_t a, uint32_t b)
+{
+    const float lo = __uint_as_float(a << 16) + __uint_as_float(b << 16);
+    const float hi = __uint_as_float(a & 0xffff0000u) + __uint_as_float(b & 0xffff0000u);
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    bf16x2 r;
+    r[0] = (__bf16)lo;
+    r[1] = (__bf16)hi;
+    return __builtin_bit_cast(uint32_t, r);
+}
+
+__device__ __forceinline__ uint4 bf16x8_add(uint4 a, uint4 b)
+{
+    return make_uint4(bf16x2_add(a.x, b.x), bf16x2_add(a.y, b.y), bf16x2_add(a.z, b.z), bf16x2_add(a.w, b.w));
+}
+
+template <int CIN, int XB, int NWV>
 struct ConvPlane {
-    static constexpr int LX = XB + 2, LY = 6, CPV = CIN / 8;
+    static constexpr int NTH = 64 * NWV;  // threads of a block, one output row per wave
+    static constexpr int LX = XB + 2, LY = NWV + 2, CPV = CIN / 8;
     static constexpr int CHUNKS = LY * LX * CPV;  // 16-byte chunks of one haloed plane
-    static constexpr int PER = (CHUNKS + 255) / 256;
+    static constexpr int PER = (CHUNKS + NTH - 1) / NTH;
     static constexpr int VPL = 8 / CPV;  // voxels per 128 bytes
 };
 
@@ -102,19 +120,18 @@ __host__ __device__ constexpr int chunk_tap(int kc, int kb)
     return (kc * 32 + kb * 8) / CIN;
 }
 
-template <int CIN, int COUT, int XB, int ACT, int OUTK, int ZB>
-__global__ __launch_bounds__(256) void k_conv_fwd(const bf16_t* __restrict__ in, const bf16_t* __restrict__ w,
-                                                  const float* __restrict__ bias, void* __restrict__ out, int S,
-                                                  int nbx, int nby, int nblocks)
+template <int CIN, int COUT, int XB, int ACT, int OUTK, int ZB, int NWV, bool WREG, bool UP>
+__global__ __launch_bounds__(64 * NWV) void k_conv_fwd(const bf16_t* __restrict__ in, const bf16_t* __restrict__ up,
+                                                       const bf16_t* __restrict__ w, const float* __restrict__ bias,
+                                                       void* __restrict__ out, int S, int nbx, int nby, int nblocks)
 {
-    using CPL = ConvPlane<CIN, XB>;
-    constexpr int CPV = CPL::CPV, LX = CPL::LX, PER = CPL::PER;
+    using CPL = ConvPlane<CIN, XB, NWV>;
+    constexpr int CPV = CPL::CPV, LX = CPL::LX, PER = CPL::PER, NTH = CPL::NTH;
     constexpr int KP = kpad(CIN);
     constexpr int KC = KP / 32;   // chunks of 32 k-values
     constexpr int NT = XB / 16;   // MFMA voxel tiles per wave
     constexpr int NC = COUT / 16; // MFMA channel tiles
     constexpr int PL16 = CPL::CHUNKS;  // 16-byte slots of one haloed plane
-    constexpr bool WREG = KC * NC <= 14;
     constexpr int KPL = KP + 8;   // LDS pitch of a weight row (breaks the bank period)
     extern __shared__ __align__(16) unsigned char smem[];
     uint4* sin = reinterpret_cast<uint4*>(smem);                // [3][PL16], plane p in slot p mod 3
@@ -124,7 +141,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const bf16_t* __restrict__ in,
     // so the y neighbours that share halo rows sit in the same L2
     const int b = xcd_tile(blockIdx.x, nblocks);
     const int bx = b % nbx, byz = b / nbx;
-    const int x0 = bx * XB, y0 = (byz % nby) * 4, zb = (byz / nby) * ZB;
+    const int x0 = bx * XB, y0 = (byz % nby) * NWV, zb = (byz / nby) * ZB;
     const int zend = min(zb + ZB, S);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int row = lane & 15, kb = lane >> 4;
@@ -133,15 +150,18 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const bf16_t* __restrict__ in,
     // staged chunks of this thread: byte offset within an input plane (past
     // any plane outside the grid in x or y, where the buffer load returns
     // zero) and LDS slot
-    int goff[PER], gslot[PER];
+    // (UP: the same for the coarse tensor of side S/2 added on the fly)
+    const int Sc = S / 2;
+    int goff[PER], gslot[PER], coff[UP ? PER : 1];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int c = threadIdx.x + q * 256;
+        const int c = threadIdx.x + q * NTH;
         const int vox = c / CPV, cc = c - vox * CPV;
         const int ly = vox / LX, lx = vox - ly * LX;
         const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
         const bool ok = c < CPL::CHUNKS && gx >= 0 && gx < S && gy >= 0 && gy < S;
         goff[q] = ok ? ((gy * S + gx) * CIN + cc * 8) * 2 : (int)0x80000000u;
+        if (UP) coff[q] = ok ? (((gy >> 1) * Sc + (gx >> 1)) * CIN + cc * 8) * 2 : (int)0x80000000u;
         gslot[q] = c < CPL::CHUNKS ? plane_slot<CPV>(vox, cc) : -1;
     }
     // one input plane as a buffer resource: planes outside the grid get no
@@ -155,11 +175,22 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const bf16_t* __restrict__ in,
 #pragma unroll
         for (int q = 0; q < PER; ++q)
             r[q] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, goff[q], 0, 0));
+        if (UP) {
+            // skip + nearest upsampling of the coarse tensor, rounded to BF16
+            const bf16_t* pc = up + (int64_t)(zin ? gz >> 1 : 0) * ((int64_t)Sc * Sc * CIN);
+            const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<bf16_t*>(pc), (short)0, zin ? plane_bytes / 4 : 0, 0x00020000);
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const uint4 cv = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rc, coff[q], 0, 0));
+                r[q] = bf16x8_add(r[q], cv);
+            }
+        }
     };
     auto store = [&](const uint4 (&r)[PER], int slot) {
 #pragma unroll
         for (int q = 0; q < PER; ++q)
-            if ((q + 1) * 256 <= CPL::CHUNKS || gslot[q] >= 0) sin[slot * PL16 + gslot[q]] = r[q];
+            if ((q + 1) * NTH <= CPL::CHUNKS || gslot[q] >= 0) sin[slot * PL16 + gslot[q]] = r[q];
     };
 
     // weights: registers (A fragments of every chunk) or LDS
@@ -171,7 +202,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const bf16_t* __restrict__ in,
             for (int c = 0; c < NC; ++c)
                 wr[kc * NC + c] = *reinterpret_cast<const uint4*>(w + (c * 16 + row) * KP + kc * 32 + kb * 8);
     } else {
-        for (int e = threadIdx.x; e < COUT * (KP / 8); e += 256) {
+        for (int e = threadIdx.x; e < COUT * (KP / 8); e += NTH) {
             const int co = e / (KP / 8), k8 = e - co * (KP / 8);
             *reinterpret_cast<uint4*>(sw + co * KPL + k8 * 8) = reinterpret_cast<const uint4*>(w)[e];
         }
@@ -801,37 +832,68 @@ static int net_workspace(Net& n, int S)
 }
 
 // forward convolution dispatch
-template <int CIN, int COUT>
-static int conv_fwd_t(const bf16_t* in, const bf16_t* w, const float* bias, void* out, int S, int act, int outk,
-                      hipStream_t s)
+// Launch of the forward convolution with patches of 64 (32 for 32 input
+// channels) x NWV voxels and ZB planes; the weights stay in registers when
+// WREG (a lane's share is at most 14 fragments).
+template <int CIN, int COUT, int ZB, int NWV, bool WREG>
+static int conv_fwd_launch(const bf16_t* in, const bf16_t* up, const bf16_t* w, const float* bias, void* out, int S,
+                           int act, int outk, hipStream_t s)
 {
     constexpr int XB = CIN >= 32 ? 32 : 64;
     constexpr int KP = kpad(CIN);
-    constexpr int ZB = 8;
-    using CPL = ConvPlane<CIN, XB>;
-    constexpr bool WREG = (KP / 32) * (COUT / 16) <= 14;
+    using CPL = ConvPlane<CIN, XB, NWV>;
     const size_t lds = (size_t)3 * CPL::CHUNKS * 16 + (WREG ? 0 : (size_t)COUT * (KP + 8) * 2);
-    const int nbx = (S + XB - 1) / XB, nby = (S + 3) / 4, nbz = (S + ZB - 1) / ZB;
+    const int nbx = (S + XB - 1) / XB, nby = (S + NWV - 1) / NWV, nbz = (S + ZB - 1) / ZB;
     const int nblocks = nbx * nby * nbz;
-    const void* fn;
-    if (outk == 2) fn = (const void*)k_conv_fwd<CIN, COUT, XB, 0, 2, ZB>;
-    else if (outk == 1) fn = (const void*)k_conv_fwd<CIN, COUT, XB, 0, 1, ZB>;
-    else if (act) fn = (const void*)k_conv_fwd<CIN, COUT, XB, 1, 0, ZB>;
-    else fn = (const void*)k_conv_fwd<CIN, COUT, XB, 0, 0, ZB>;
-    if (lds > 64 * 1024) NDL_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    dim3 grid((unsigned)nblocks);
-    if (outk == 2) k_conv_fwd<CIN, COUT, XB, 0, 2, ZB><<<grid, 256, lds, s>>>(in, w, bias, out, S, nbx, nby, nblocks);
-    else if (outk == 1) k_conv_fwd<CIN, COUT, XB, 0, 1, ZB><<<grid, 256, lds, s>>>(in, w, bias, out, S, nbx, nby, nblocks);
-    else if (act) k_conv_fwd<CIN, COUT, XB, 1, 0, ZB><<<grid, 256, lds, s>>>(in, w, bias, out, S, nbx, nby, nblocks);
-    else k_conv_fwd<CIN, COUT, XB, 0, 0, ZB><<<grid, 256, lds, s>>>(in, w, bias, out, S, nbx, nby, nblocks);
+    dim3 grid((unsigned)nblocks), block(CPL::NTH);
+#define NDL_KCF(ACT_, OUTK_, UP_) k_conv_fwd<CIN, COUT, XB, ACT_, OUTK_, ZB, NWV, WREG, UP_>
+#define NDL_KCF_GO(ACT_, OUTK_, UP_)                                                                          \
+    do {                                                                                                     \
+        if (lds > 64 * 1024)                                                                                 \
+            NDL_HIP(hipFuncSetAttribute((const void*)NDL_KCF(ACT_, OUTK_, UP_),                              \
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));              \
+        NDL_KCF(ACT_, OUTK_, UP_)<<<grid, block, lds, s>>>(in, up, w, bias, out, S, nbx, nby, nblocks);       \
+    } while (0)
+    if (up) {
+        // skip additions feed the decoder convolutions (BF16 out, equal channel counts)
+        if constexpr (CIN == COUT) {
+            if (outk != 0 || (S & 1)) { set_error("conv with upsampled input: unsupported form"); return NDL_EINVAL; }
+            if (act) NDL_KCF_GO(1, 0, true);
+            else NDL_KCF_GO(0, 0, true);
+        } else {
+            set_error("conv with upsampled input: channel counts differ");
+            return NDL_EINVAL;
+        }
+    } else if (outk == 2) NDL_KCF_GO(0, 2, false);
+    else if (outk == 1) NDL_KCF_GO(0, 1, false);
+    else if (act) NDL_KCF_GO(1, 0, false);
+    else NDL_KCF_GO(0, 0, false);
+#undef NDL_KCF_GO
+#undef NDL_KCF
     NDL_HIP(hipGetLastError());
     return NDL_OK;
 }
 
-static int conv_fwd(int cin, int cout, const bf16_t* in, const bf16_t* w, const float* bias, void* out, int S, int act,
-                    int outk, hipStream_t s)
+// Patch shape by grid size (measured at 256^3 and its coarser levels): the
+// full-resolution grids take 8-row patches of 16 planes with the weights in
+// LDS (two 8-wave blocks per CU), the middle ones 4-row patches of 8 planes,
+// the coarsest 4 planes so that the launch still spreads over the CUs.
+template <int CIN, int COUT>
+static int conv_fwd_t(const bf16_t* in, const bf16_t* up, const bf16_t* w, const float* bias, void* out, int S,
+                      int act, int outk, hipStream_t s)
 {
-#define NDL_CF(A, B) if (cin == A && cout == B) return conv_fwd_t<A, B>(in, w, bias, out, S, act, outk, s)
+    constexpr bool WR = (kpad(CIN) / 32) * (COUT / 16) <= 14;
+    if (S >= 128) return conv_fwd_launch<CIN, COUT, 16, 8, false>(in, up, w, bias, out, S, act, outk, s);
+    if (S >= 64) return conv_fwd_launch<CIN, COUT, 8, 4, WR>(in, up, w, bias, out, S, act, outk, s);
+    return conv_fwd_launch<CIN, COUT, 4, 4, WR>(in, up, w, bias, out, S, act, outk, s);
+}
+
+// y = conv(x) (up null) or y = conv(x + up2(up)) with the skip sum formed while
+// staging (up: the coarse tensor, side S/2, same channels)
+static int conv_fwd(int cin, int cout, const bf16_t* in, const bf16_t* w, const float* bias, void* out, int S, int act,
+                    int outk, hipStream_t s, const bf16_t* up = nullptr)
+{
+#define NDL_CF(A, B) if (cin == A && cout == B) return conv_fwd_t<A, B>(in, up, w, bias, out, S, act, outk, s)
     NDL_CF(8, 16);
     NDL_CF(16, 16);
     NDL_CF(16, 32);
@@ -963,15 +1025,18 @@ static const bf16_t* layer_input(Net& n, int i)
     }
 }
 
-static int net_forward(Net& n, int S, hipStream_t s, bool linear = false)
+// Inference (fuse_up) forms the decoder's skip sums while staging the next
+// convolution's input instead of storing them; training keeps them for the
+// weight gradients.
+static int net_forward(Net& n, int S, hipStream_t s, bool linear = false, bool fuse_up = false)
 {
     int Sl[4] = {S, S / 2, S / 4, S / 8};
-    auto conv = [&](int i) -> int {
+    auto conv = [&](int i, const bf16_t* in = nullptr, const bf16_t* up = nullptr) -> int {
         Layer& l = n.L[i];
         int lv = level_of_layer(i);
         bool head = i == kNumLayers - 1;
-        return conv_fwd(l.sp.cin, l.sp.cout, layer_input(n, i), l.wbf, linear ? nullptr : l.b32,
-                        head ? (void*)n.head : (void*)n.a[i], Sl[lv], linear ? 0 : l.sp.act, head ? 2 : 0, s);
+        return conv_fwd(l.sp.cin, l.sp.cout, in ? in : layer_input(n, i), l.wbf, linear ? nullptr : l.b32,
+                        head ? (void*)n.head : (void*)n.a[i], Sl[lv], linear ? 0 : l.sp.act, head ? 2 : 0, s, up);
     };
     auto vox = [&](int l) { return (int64_t)Sl[l] * Sl[l] * Sl[l]; };
     NDL_TRY(conv(0));
@@ -985,13 +1050,20 @@ static int net_forward(Net& n, int S, hipStream_t s, bool linear = false)
     k_pool<<<nb(vox(3) * 4), 256, 0, s>>>(n.a[5], n.p[3], Sl[2], 32);
     NDL_TRY(conv(6));
     NDL_TRY(conv(7));
-    k_up_add<<<nb(vox(2) * 4), 256, 0, s>>>(n.a[7], n.a[5], n.u[2], Sl[2], 32);
-    NDL_TRY(conv(8));
-    NDL_TRY(conv(9));
-    k_up_add<<<nb(vox(1) * 2), 256, 0, s>>>(n.a[9], n.a[3], n.u[1], Sl[1], 16);
-    NDL_TRY(conv(10));
-    k_up_add<<<nb(vox(0) * 2), 256, 0, s>>>(n.a[10], n.a[1], n.u[0], Sl[0], 16);
-    NDL_TRY(conv(11));
+    if (fuse_up) {
+        NDL_TRY(conv(8, n.a[5], n.a[7]));
+        NDL_TRY(conv(9));
+        NDL_TRY(conv(10, n.a[3], n.a[9]));
+        NDL_TRY(conv(11, n.a[1], n.a[10]));
+    } else {
+        k_up_add<<<nb(vox(2) * 4), 256, 0, s>>>(n.a[7], n.a[5], n.u[2], Sl[2], 32);
+        NDL_TRY(conv(8));
+        NDL_TRY(conv(9));
+        k_up_add<<<nb(vox(1) * 2), 256, 0, s>>>(n.a[9], n.a[3], n.u[1], Sl[1], 16);
+        NDL_TRY(conv(10));
+        k_up_add<<<nb(vox(0) * 2), 256, 0, s>>>(n.a[10], n.a[1], n.u[0], Sl[0], 16);
+        NDL_TRY(conv(11));
+    }
     NDL_TRY(conv(12));
     NDL_HIP(hipGetLastError());
     return NDL_OK;
@@ -1172,7 +1244,7 @@ static int precond_t(NetState& st, const Plan& p, const T* r, T* z, hipStream_t 
         k_sumsq<float><<<256, 256, 0, s>>>(st.rsc, p.N, n.lpart);
         k_rscale<<<1, 64, 0, s>>>(n.lpart, 256, (double)p.N, n.rscale);
         k_pack_input<float><<<nb(p.N), 256, 0, s>>>(st.rsc, n.rscale, nullptr, nullptr, p.N, S, 0.0, 1.0, n.x_in);
-        NDL_TRY(net_forward(n, S, s, true));
+        NDL_TRY(net_forward(n, S, s, true, true));
         if (z) k_unpack_scaled<T><<<nb(p.N), 256, 0, s>>>(n.head, n.rscale, dinv, p.N, z);
         NDL_HIP(hipGetLastError());
         return NDL_OK;
@@ -1193,7 +1265,7 @@ static int precond_t(NetState& st, const Plan& p, const T* r, T* z, hipStream_t 
     k_rscale<<<1, 64, 0, s>>>(n.lpart, 256, (double)p.N, n.rscale);
     k_pack_input<T><<<nb(p.N), 256, 0, s>>>(r, n.rscale, (const T*)p.prob.delta, (const T*)p.prob.coef, p.N, S,
                                             st.feat_mu, st.feat_isd, n.x_in);
-    NDL_TRY(net_forward(n, S, s));
+    NDL_TRY(net_forward(n, S, s, false, true));
     if (z) k_unpack<T><<<nb(p.N), 256, 0, s>>>(n.head, n.rscale, p.N, z);
     NDL_HIP(hipGetLastError());
     return NDL_OK;

@@ -52,7 +52,7 @@ def test_conv_layer(cin, cout, S):
     assert np.all(gw.cpu().numpy()[:, 27 * cin:] == 0)
 
 
-@pytest.mark.parametrize("cin,cout,S", [(8, 16, 72), (16, 16, 72), (16, 32, 40), (32, 32, 40), (32, 16, 40)])
+@pytest.mark.parametrize("cin,cout,S", [(8, 16, 72), (16, 16, 72), (16, 32, 72), (32, 32, 40), (32, 16, 72)])
 def test_conv_layer_many_patches(cin, cout, S):
     """Forward and data gradient over many (x, y, z) patches with ragged
     edges on every axis (the patch grid is walked in its XCD order)."""
@@ -81,6 +81,32 @@ def test_conv_layer_many_patches(cin, cout, S):
         err = np.abs(dx.cpu().numpy() - dxref).max() / np.abs(dxref).max()
         say("  dgrad", err)
         assert err < 1e-5
+
+
+@pytest.mark.parametrize("cin,cout", [(8, 16), (16, 16)])
+def test_conv_layer_full_resolution_patches(cin, cout):
+    """The full-resolution patch shape (8-row patches of 16 planes, weights
+    in LDS) on a 130^3 grid, ragged on every axis: output planes at both
+    boundaries, at patch seams and inside, against the FP64 reference."""
+    import torch
+    S = 130
+    say(f"case conv {cin}->{cout} S={S} (full-resolution patches)")
+    g = np.random.default_rng(cin * 7 + cout)
+    x = NO.bf16_round(g.standard_normal((S, S, S, cin)))
+    w = g.standard_normal((cout, 27, cin)) / np.sqrt(27 * cin)
+    b = g.standard_normal(cout)
+    wk = NO.pack_weights(w)
+    d = lambda a, t=torch.float32: torch.from_numpy(np.ascontiguousarray(a)).to(t).cuda()
+    xb = torch.from_numpy(NO.bf16_bits(x).view(np.int16)).cuda()
+    y = torch.zeros((S, S, S, cout), device="cuda")
+    ndl.ndl_net_conv_test(cin, cout, S, xb, d(wk), d(b), y=y)
+    torch.cuda.synchronize()
+    zs = [0, 1, 15, 16, 17, 64, 127, 128, 129]
+    yref = NO.conv3d_planes(x, NO.bf16_round(w), b, zs)
+    got = y.cpu().numpy()[zs]
+    err = np.abs(got - yref).max() / np.abs(yref).max()
+    say("  fwd", err)
+    assert err < 1e-5
 
 
 def test_train_step_reduces_loss_and_roundtrips(tmp_path):

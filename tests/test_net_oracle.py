@@ -25,6 +25,21 @@ def test_single_channel_conv_is_scipy_correlate():
     assert np.allclose(y[..., 0], ref, rtol=1e-12, atol=1e-12)
 
 
+def test_conv_planes_is_scipy_correlate_per_channel_pair():
+    """The plane-restricted convolution (used to check single planes of large
+    grids) against scipy's correlation summed over input channels."""
+    g = np.random.default_rng(11)
+    x = g.standard_normal((7, 7, 7, 3))
+    w = g.standard_normal((2, 27, 3))
+    b = g.standard_normal(2)
+    zs = [0, 3, 6]
+    got = NO.conv3d_planes(x, w, b, zs)
+    for o in range(2):
+        ref = sum(ndimage.correlate(x[..., c], w[o, :, c].reshape(3, 3, 3), mode="constant", cval=0.0)
+                  for c in range(3)) + b[o]
+        assert np.allclose(got[..., o], ref[zs], rtol=1e-12, atol=1e-12)
+
+
 def test_dgrad_is_the_adjoint():
     g = np.random.default_rng(2)
     x = g.standard_normal((6, 6, 6, 8))
