@@ -217,10 +217,11 @@ __global__ __launch_bounds__(256) void k_div_items(const Inst* __restrict__ inst
 
 // The same operator for batches of 2D and 3D problems with the discrete
 // normalisation, mapped for gfx950: a block covers a 16 x 64 tile (2D, 4
-// waves of 4 rows) or an 8 x 4 x 64 tile (3D, 8 waves of one plane each), and
-// each lane 4 nodes of one column along axis dim-2, so the uniform per-offset
-// work (offset, |z|^2, |z|^e) is shared by 4 nodes and the partner reads of
-// one offset use immediate LDS offsets from one address.
+// waves of 4 rows) or an 8 x 4 x 64 tile (3D, 16 waves of two rows of one
+// plane), and each lane 4 (2D) or 2 (3D) nodes of one column along axis
+// dim-2, so the uniform per-offset work (offset, |z|^2, |z|^e) is shared by
+// those nodes and the partner reads of one offset use immediate LDS offsets
+// from one address.
 // 2D tiles stage m = delta n/2 in FP64 (exact for FP32 delta, so that
 // m_i + m_j is exactly the (delta_i + delta_j) n/2 of the cutoff rule; FP64
 // data stage delta and form (delta_i + delta_j) n/2 as the rule writes it);
@@ -233,21 +234,29 @@ __global__ __launch_bounds__(256) void k_div_items(const Inst* __restrict__ inst
 // tile (|z|^2 < (2 min m)^2) and the loop ends past the largest
 // (|z|^2 >= (2 max m)^2); a partner outside Omega takes (delta_i, c_i), which
 // only tiles within J of the boundary test for.
+// 3D: 2 nodes per lane, 16 waves per 8 x 4 x 64 tile (the haloed tile leaves
+// room for one block per CU, so the occupancy comes from the block's waves)
+#ifndef NDL_DIV3_PY
+#define NDL_DIV3_PY 2
+#endif
+constexpr int div_py(int dim) { return dim == 3 ? NDL_DIV3_PY : 4; }
+constexpr int div_threads(int dim) { return dim == 3 ? 64 * 32 / NDL_DIV3_PY : 256; }
+
 template <typename T, bool DIAG, int JT, int DIM>
-__global__ __launch_bounds__(DIM == 3 ? 512 : 256) void k_div2_items(const Inst* __restrict__ insts, const int2* __restrict__ items,
+__global__ __launch_bounds__(div_threads(DIM)) void k_div2_items(const Inst* __restrict__ insts, const int2* __restrict__ items,
                                                     int nitems, const T* __restrict__ pvec, T* __restrict__ qvec,
                                                     const int4* __restrict__ full, const double* __restrict__ fw,
                                                     const double* __restrict__ Tinv, const Scal* __restrict__ sc,
                                                     double* __restrict__ part)
 {
     constexpr bool F32 = sizeof(T) == 4;
-    constexpr int PY = 4;
-    constexpr int NWAVES = DIM == 3 ? 8 : 4;
+    constexpr int PY = div_py(DIM);
+    constexpr int NWAVES = div_threads(DIM) / 64;
     // staged horizon: MT values; SC = already scaled by n/2 (2D FP32 only)
     using MT = typename std::conditional<DIM == 3, float, double>::type;
     constexpr bool SC = DIM == 2 && F32;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double red[16];
+    __shared__ double red[2 * NWAVES];
     __shared__ T tinv_s[256];
     __shared__ int s_q[kMaxOffs];
     const int lane = threadIdx.x & 63;
@@ -312,15 +321,15 @@ __global__ __launch_bounds__(DIM == 3 ? 512 : 256) void k_div2_items(const Inst*
         }
         if (lane == 0) {
             red[wv] = mmax;
-            red[8 + wv] = mmin;
+            red[NWAVES + wv] = mmin;
         }
         __syncthreads();
         mmax = red[0];
-        mmin = red[8];
+        mmin = red[NWAVES];
 #pragma unroll
         for (int w = 1; w < NWAVES; ++w) {
             mmax = fmax(mmax, red[w]);
-            mmin = fmin(mmin, red[8 + w]);
+            mmin = fmin(mmin, red[NWAVES + w]);
         }
         const double tmax = 4.0 * mmax * mmax;  // (2 max m)^2 >= every t of the tile
         const double tmin = 4.0 * mmin * mmin;
@@ -329,7 +338,8 @@ __global__ __launch_bounds__(DIM == 3 ? 512 : 256) void k_div2_items(const Inst*
 
         const int x = x0 + lane;
         // 2D: wave wv holds rows 4 wv .. 4 wv + 3; 3D: plane wv, rows 0..3
-        const int wz = DIM == 3 ? wv : 0, wy = DIM == 3 ? 0 : wv * PY;
+        constexpr int WPP = DIM == 3 ? 4 / PY : 1;  // waves per plane (3D)
+        const int wz = DIM == 3 ? wv / WPP : 0, wy = DIM == 3 ? (wv % WPP) * PY : wv * PY;
         const int base = (wz + HZ) * PLANE + (wy + J) * PITCH + lane + J;
         double mi[PY];
         T cci[PY], ui[PY];
@@ -863,7 +873,7 @@ static int launch_div_items(const Batch& B, const Inst* d_insts, const int2* d_i
     bool disc = B.insts[0].norm == NDL_NORM_DISCRETE;
     if (use_div_spec<T>(B)) {
         const int key = B.dim * 16 + B.Jmax;
-        const unsigned nt = B.dim == 3 ? 512u : 256u;
+        const unsigned nt = (unsigned)div_threads(B.dim);
         switch (key) {
 #define NDL_DIV2_CASE(DD, JJ)                                                                                     \
     case DD * 16 + JJ:                                                                                            \
