@@ -239,8 +239,14 @@ __global__ __launch_bounds__(256) void k_div_items(const Inst* __restrict__ inst
 #ifndef NDL_DIV3_PY
 #define NDL_DIV3_PY 2
 #endif
-constexpr int div_py(int dim) { return dim == 3 ? NDL_DIV3_PY : 4; }
-constexpr int div_threads(int dim) { return dim == 3 ? 64 * 32 / NDL_DIV3_PY : 256; }
+#ifndef NDL_DIV2_PY
+#define NDL_DIV2_PY 4
+#endif
+constexpr int div_py(int dim) { return dim == 3 ? NDL_DIV3_PY : NDL_DIV2_PY; }
+// tile rows per plane and planes: 16 x 64 (2D), 8 x 4 x 64 (3D)
+constexpr int div_rows(int dim) { return dim == 3 ? 4 : 16; }
+constexpr int div_planes(int dim) { return dim == 3 ? 8 : 1; }
+constexpr int div_threads(int dim) { return 64 * div_planes(dim) * div_rows(dim) / div_py(dim); }
 
 template <typename T, bool DIAG, int JT, int DIM>
 __global__ __launch_bounds__(div_threads(DIM)) void k_div2_items(const Inst* __restrict__ insts, const int2* __restrict__ items,
@@ -338,8 +344,8 @@ __global__ __launch_bounds__(div_threads(DIM)) void k_div2_items(const Inst* __r
 
         const int x = x0 + lane;
         // 2D: wave wv holds rows 4 wv .. 4 wv + 3; 3D: plane wv, rows 0..3
-        constexpr int WPP = DIM == 3 ? 4 / PY : 1;  // waves per plane (3D)
-        const int wz = DIM == 3 ? wv / WPP : 0, wy = DIM == 3 ? (wv % WPP) * PY : wv * PY;
+        constexpr int WPP = div_rows(DIM) / PY;  // waves per plane
+        const int wz = wv / WPP, wy = (wv % WPP) * PY;
         const int base = (wz + HZ) * PLANE + (wy + J) * PITCH + lane + J;
         double mi[PY];
         T cci[PY], ui[PY];
