@@ -242,22 +242,29 @@ __global__ __launch_bounds__(256) void k_div_items(const Inst* __restrict__ inst
 #ifndef NDL_DIV2_PY
 #define NDL_DIV2_PY 4
 #endif
-constexpr int div_py(int dim) { return dim == 3 ? NDL_DIV3_PY : NDL_DIV2_PY; }
-// tile rows per plane and planes: 16 x 64 (2D), 8 x 4 x 64 (3D)
-constexpr int div_rows(int dim) { return dim == 3 ? 4 : 16; }
-constexpr int div_planes(int dim) { return dim == 3 ? 8 : 1; }
-constexpr int div_threads(int dim) { return 64 * div_planes(dim) * div_rows(dim) / div_py(dim); }
+// Tile of one block: 16 x 64 (2D) or 8 x 4 x 64 (3D) nodes, PY nodes per
+// lane.  FP64 vectors on 3D problems with FP32 fields (the outer residual of
+// the mixed-precision solve) stage 4 planes at a time, in two halves, so that
+// the 8-byte u and c' fit the LDS next to the 4-byte horizon.
+template <typename T, int DIM>
+struct DivShape {
+    static constexpr int PY = DIM == 3 ? NDL_DIV3_PY : NDL_DIV2_PY;
+    static constexpr int TY = DIM == 3 ? 4 : 16;
+    static constexpr int TZ = DIM == 3 ? (sizeof(T) == 8 ? 4 : 8) : 1;
+    static constexpr int SUB = DIM == 3 ? 8 / TZ : 1;  // staged slabs per item
+    static constexpr int THREADS = 64 * TZ * TY / PY;
+};
 
-template <typename T, bool DIAG, int JT, int DIM>
-__global__ __launch_bounds__(div_threads(DIM)) void k_div2_items(const Inst* __restrict__ insts, const int2* __restrict__ items,
-                                                    int nitems, const T* __restrict__ pvec, T* __restrict__ qvec,
-                                                    const int4* __restrict__ full, const double* __restrict__ fw,
-                                                    const double* __restrict__ Tinv, const Scal* __restrict__ sc,
-                                                    double* __restrict__ part)
+template <typename T, typename D, bool DIAG, int JT, int DIM>
+__global__ __launch_bounds__((DivShape<T, DIM>::THREADS)) void k_div2_items(
+    const Inst* __restrict__ insts, const int2* __restrict__ items, int nitems, const T* __restrict__ pvec,
+    T* __restrict__ qvec, const int4* __restrict__ full, const double* __restrict__ fw, const double* __restrict__ Tinv,
+    const Scal* __restrict__ sc, double* __restrict__ part)
 {
+    using SH = DivShape<T, DIM>;
     constexpr bool F32 = sizeof(T) == 4;
-    constexpr int PY = div_py(DIM);
-    constexpr int NWAVES = div_threads(DIM) / 64;
+    constexpr int PY = SH::PY;
+    constexpr int NWAVES = SH::THREADS / 64;
     // staged horizon: MT values; SC = already scaled by n/2 (2D FP32 only)
     using MT = typename std::conditional<DIM == 3, float, double>::type;
     constexpr bool SC = DIM == 2 && F32;
@@ -276,27 +283,29 @@ __global__ __launch_bounds__(div_threads(DIM)) void k_div2_items(const Inst* __r
         }
         int org[3];
         item_geom<T>(I, item.y, org);
+        double dot = 0.0;
+        for (int sub = 0; sub < SH::SUB; ++sub) {
         // every problem of the batch uses the halo JT >= its own J, so the tile
         // pitch is a compile-time constant and the partner reads of the PY
         // nodes of a lane use immediate offsets
         const int n = I.n;
         constexpr int J = JT;
-        constexpr int TZ = DIM == 3 ? 8 : 1, TY = DIM == 3 ? 4 : 16, HZ = DIM == 3 ? J : 0;
+        constexpr int TZ = SH::TZ, TY = SH::TY, HZ = DIM == 3 ? J : 0;
         constexpr int PITCH = 64 + 2 * J, SY = TY + 2 * J, SZ = TZ + 2 * HZ;
         constexpr int PLANE = SY * PITCH, tot = SZ * PLANE;
         MT* tm = reinterpret_cast<MT*>(smem_raw);
         T* tcc = reinterpret_cast<T*>(tm + tot);
         T* tu = tcc + tot;
         const T* p = pvec + I.off;
-        const T* dlt = static_cast<const T*>(I.delta);
-        const T* cf = static_cast<const T*>(I.coef);
+        const D* dlt = static_cast<const D*>(I.delta);
+        const D* cf = static_cast<const D*>(I.coef);
         const double nh = 0.5 * (double)n;
         const double ch = 0.5 * I.n2;
         __syncthreads();  // the previous item's readers are done
         for (int k = threadIdx.x; k <= I.kmax && k < 256; k += blockDim.x) tinv_s[k] = (T)Tinv[k];
         const int nq = I.nq < kMaxOffs ? I.nq : kMaxOffs;
         for (int q = threadIdx.x; q < nq; q += blockDim.x) s_q[q] = full[q].w;
-        const int z0 = org[0], y0 = org[1], x0 = org[2];
+        const int z0 = org[0] + sub * TZ, y0 = org[1], x0 = org[2];
         const int nz = DIM == 3 ? n : 1;
         double mmax = 0.0, mmin = 1e300;
         for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
@@ -344,7 +353,7 @@ __global__ __launch_bounds__(div_threads(DIM)) void k_div2_items(const Inst* __r
 
         const int x = x0 + lane;
         // 2D: wave wv holds rows 4 wv .. 4 wv + 3; 3D: plane wv, rows 0..3
-        constexpr int WPP = div_rows(DIM) / PY;  // waves per plane
+        constexpr int WPP = SH::TY / PY;  // waves per plane
         const int wz = wv / WPP, wy = (wv % WPP) * PY;
         const int base = (wz + HZ) * PLANE + (wy + J) * PITCH + lane + J;
         double mi[PY];
@@ -428,7 +437,6 @@ __global__ __launch_bounds__(div_threads(DIM)) void k_div2_items(const Inst* __r
             run(0, p_in, no{}, no{});
             run(p_in, p_end, no{}, yes{});
         }
-        double dot = 0.0;
         T* qv = qvec + I.off;
 #pragma unroll
         for (int j = 0; j < PY; ++j) {
@@ -442,6 +450,7 @@ __global__ __launch_bounds__(div_threads(DIM)) void k_div2_items(const Inst* __r
                 dot += (double)ui[j] * (double)val;
             }
         }
+        }  // slabs of the item
         if (part) {
             const double s = block_sum(dot, red);
             if (threadIdx.x == 0) part[it] = s;
@@ -817,32 +826,44 @@ static __global__ void k_widen(const T* __restrict__ a, double* __restrict__ b, 
 static unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 // Batches with the discrete normalisation run the specialised kernel: 2D with
-// halo J <= 8, and 3D FP32 with J <= 3 (its 8 x 4 x 64 tile and halo must fit
-// the LDS of one CU).
+// halo J <= 8, and 3D with J <= 3 for FP32 vectors, or FP64 vectors over FP32
+// fields (f32data: the outer residual of the mixed-precision solve); the
+// haloed tile must fit the LDS of one CU.
 template <typename T>
-static bool use_div_spec(const Batch& B)
+static bool use_div_spec(const Batch& B, bool f32data = false)
 {
     if (B.insts[0].norm != NDL_NORM_DISCRETE || B.kmax >= 256 || B.Jmax < 1) return false;
     if (B.dim == 2) return B.Jmax <= 8;
-    if (B.dim == 3) return sizeof(T) == 4 && B.Jmax <= 3;
+    if (B.dim == 3) return (sizeof(T) == 4 || f32data) && B.Jmax <= 3;
     return false;
 }
 
 template <typename T>
-static size_t items_lds(const Batch& B)
+static size_t items_lds(const Batch& B, bool f32data = false)
 {
     const Inst& I0 = B.insts[0];
+    if (use_div_spec<T>(B, f32data)) {
+        const int J = B.Jmax;
+        size_t cells;
+        if (B.dim == 3) cells = (size_t)(DivShape<T, 3>::TZ + 2 * J) * (DivShape<T, 3>::TY + 2 * J) * (64 + 2 * J);
+        else cells = (size_t)(DivShape<T, 2>::TY + 2 * J) * (64 + 2 * J);
+        return cells * ((B.dim == 3 ? sizeof(float) : sizeof(double)) + 2 * sizeof(T));
+    }
     int L[3] = {I0.E[0] + (B.dim >= 3 ? 2 * B.Jmax : 0), I0.E[1] + (B.dim >= 2 ? 2 * B.Jmax : 0),
                 I0.E[2] + 2 * B.Jmax};
     size_t cells = (size_t)L[0] * L[1] * L[2];
-    if (use_div_spec<T>(B)) return cells * ((B.dim == 3 ? sizeof(float) : sizeof(double)) + 2 * sizeof(T));
     return cells * sizeof(T) * (sizeof(T) == 4 ? 3 : 1);
 }
 
+#define NDL_DIV2_KERNELS(T_, D_, DD)                                                                             \
+    (const void*)k_div2_items<T_, D_, false, 1, DD>, (const void*)k_div2_items<T_, D_, true, 1, DD>,            \
+        (const void*)k_div2_items<T_, D_, false, 2, DD>, (const void*)k_div2_items<T_, D_, true, 2, DD>,        \
+        (const void*)k_div2_items<T_, D_, false, 3, DD>, (const void*)k_div2_items<T_, D_, true, 3, DD>
+
 template <typename T>
-static int prepare_lds(const Batch& B)
+static int prepare_lds(const Batch& B, bool f32data = false)
 {
-    size_t lds = items_lds<T>(B);
+    size_t lds = items_lds<T>(B, f32data);
     if (lds + 16 * 1024 > 160 * 1024) {
         set_error("solver tile needs %zu B of LDS (horizon too wide)", lds);
         return NDL_EUNSUPPORTED;
@@ -852,60 +873,81 @@ static int prepare_lds(const Batch& B)
         const void* fns[] = {(const void*)k_div_items<T, false, true>, (const void*)k_div_items<T, true, true>,
                              (const void*)k_div_items<T, false, false>, (const void*)k_div_items<T, true, false>};
         for (const void* f : fns) NDL_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        const void* fns2[] = {(const void*)k_div2_items<T, false, 1, 2>, (const void*)k_div2_items<T, true, 1, 2>,
-                              (const void*)k_div2_items<T, false, 2, 2>, (const void*)k_div2_items<T, true, 2, 2>,
-                              (const void*)k_div2_items<T, false, 3, 2>, (const void*)k_div2_items<T, true, 3, 2>,
-                              (const void*)k_div2_items<T, false, 4, 2>, (const void*)k_div2_items<T, true, 4, 2>,
-                              (const void*)k_div2_items<T, false, 5, 2>, (const void*)k_div2_items<T, true, 5, 2>,
-                              (const void*)k_div2_items<T, false, 6, 2>, (const void*)k_div2_items<T, true, 6, 2>,
-                              (const void*)k_div2_items<T, false, 7, 2>, (const void*)k_div2_items<T, true, 7, 2>,
-                              (const void*)k_div2_items<T, false, 8, 2>, (const void*)k_div2_items<T, true, 8, 2>,
-                              (const void*)k_div2_items<T, false, 1, 3>, (const void*)k_div2_items<T, true, 1, 3>,
-                              (const void*)k_div2_items<T, false, 2, 3>, (const void*)k_div2_items<T, true, 2, 3>,
-                              (const void*)k_div2_items<T, false, 3, 3>, (const void*)k_div2_items<T, true, 3, 3>};
+        const void* fns2[] = {NDL_DIV2_KERNELS(T, T, 2),
+                              (const void*)k_div2_items<T, T, false, 4, 2>, (const void*)k_div2_items<T, T, true, 4, 2>,
+                              (const void*)k_div2_items<T, T, false, 5, 2>, (const void*)k_div2_items<T, T, true, 5, 2>,
+                              (const void*)k_div2_items<T, T, false, 6, 2>, (const void*)k_div2_items<T, T, true, 6, 2>,
+                              (const void*)k_div2_items<T, T, false, 7, 2>, (const void*)k_div2_items<T, T, true, 7, 2>,
+                              (const void*)k_div2_items<T, T, false, 8, 2>, (const void*)k_div2_items<T, T, true, 8, 2>,
+                              NDL_DIV2_KERNELS(T, T, 3)};
         for (const void* f : fns2) NDL_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        if (f32data && sizeof(T) == 8) {
+            const void* fns3[] = {NDL_DIV2_KERNELS(double, float, 3)};
+            for (const void* f : fns3)
+                NDL_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        }
     }
     return NDL_OK;
 }
+#undef NDL_DIV2_KERNELS
 
+// q = -L p over the items.  f32data: the items' fields are FP32 while the
+// vectors are FP64 (3D specialised kernel only; otherwise the caller passes
+// FP64 fields).
 template <typename T>
 static int launch_div_items(const Batch& B, const Inst* d_insts, const int2* d_items, const T* p, T* q,
                             const int4* full, const double* fw, int nfull, const double* Tinv, const Scal* sc,
-                            double* part, bool diag, hipStream_t s)
+                            double* part, bool diag, hipStream_t s, bool f32data = false)
 {
-    size_t lds = items_lds<T>(B);
+    size_t lds = items_lds<T>(B, f32data);
     int nitems = (int)B.items.size();
     unsigned g = (unsigned)std::min(nitems, 256 * 8);
     bool disc = B.insts[0].norm == NDL_NORM_DISCRETE;
-    if (use_div_spec<T>(B)) {
+    if (use_div_spec<T>(B, f32data)) {
         const int key = B.dim * 16 + B.Jmax;
-        const unsigned nt = (unsigned)div_threads(B.dim);
-        switch (key) {
-#define NDL_DIV2_CASE(DD, JJ)                                                                                     \
-    case DD * 16 + JJ:                                                                                            \
+#define NDL_DIV2_CASE(DD, JJ, DT)                                                                                 \
+    case DD * 16 + JJ: {                                                                                          \
+        const unsigned nt = (unsigned)DivShape<T, DD>::THREADS;                                                   \
         if (diag)                                                                                                 \
-            k_div2_items<T, true, JJ, DD><<<g, nt, lds, s>>>(d_insts, d_items, nitems, p, q, full, fw, Tinv, sc,   \
-                                                              part);                                              \
+            k_div2_items<T, DT, true, JJ, DD><<<g, nt, lds, s>>>(d_insts, d_items, nitems, p, q, full, fw, Tinv,  \
+                                                                  sc, part);                                      \
         else                                                                                                      \
-            k_div2_items<T, false, JJ, DD><<<g, nt, lds, s>>>(d_insts, d_items, nitems, p, q, full, fw, Tinv, sc,  \
-                                                               part);                                             \
-        break;
-            NDL_DIV2_CASE(2, 1)
-            NDL_DIV2_CASE(2, 2)
-            NDL_DIV2_CASE(2, 3)
-            NDL_DIV2_CASE(2, 4)
-            NDL_DIV2_CASE(2, 5)
-            NDL_DIV2_CASE(2, 6)
-            NDL_DIV2_CASE(2, 7)
-            NDL_DIV2_CASE(2, 8)
-            NDL_DIV2_CASE(3, 1)
-            NDL_DIV2_CASE(3, 2)
-            NDL_DIV2_CASE(3, 3)
-#undef NDL_DIV2_CASE
-        default: return NDL_EUNSUPPORTED;
+            k_div2_items<T, DT, false, JJ, DD><<<g, nt, lds, s>>>(d_insts, d_items, nitems, p, q, full, fw, Tinv, \
+                                                                   sc, part);                                     \
+        break;                                                                                                    \
+    }
+        if (f32data && sizeof(T) == 8) {
+            if constexpr (sizeof(T) == 8) {
+                switch (key) {
+                    NDL_DIV2_CASE(3, 1, float)
+                    NDL_DIV2_CASE(3, 2, float)
+                    NDL_DIV2_CASE(3, 3, float)
+                default: return NDL_EUNSUPPORTED;
+                }
+            }
+        } else {
+            switch (key) {
+                NDL_DIV2_CASE(2, 1, T)
+                NDL_DIV2_CASE(2, 2, T)
+                NDL_DIV2_CASE(2, 3, T)
+                NDL_DIV2_CASE(2, 4, T)
+                NDL_DIV2_CASE(2, 5, T)
+                NDL_DIV2_CASE(2, 6, T)
+                NDL_DIV2_CASE(2, 7, T)
+                NDL_DIV2_CASE(2, 8, T)
+                NDL_DIV2_CASE(3, 1, T)
+                NDL_DIV2_CASE(3, 2, T)
+                NDL_DIV2_CASE(3, 3, T)
+            default: return NDL_EUNSUPPORTED;
+            }
         }
+#undef NDL_DIV2_CASE
         NDL_HIP(hipGetLastError());
         return NDL_OK;
+    }
+    if (f32data) {
+        set_error("internal: FP32 fields with FP64 vectors need the specialised kernel");
+        return NDL_EINVAL;
     }
     if (diag && disc)
         k_div_items<T, true, true><<<g, 256, lds, s>>>(d_insts, d_items, nitems, p, q, full, fw, nfull, Tinv, sc, part);
@@ -1019,8 +1061,11 @@ static int cg_solve_t(const ndl_plan* plans, int nprob, const double* const* b, 
     const int* down = (const int*)d_owner.p;
     unsigned gi = (unsigned)std::min(nitems, 256 * 8);
     unsigned gp = (unsigned)((nprob + 63) / 64);
+    // the outer FP64 residual of a 3D mixed solve reads the FP32 fields directly
+    const bool res32 = mixed && B.dim == 3 && use_div_spec<double>(B, true);
+    const Inst* dres = res32 ? di : di64;
     NDL_TRY(prepare_lds<T>(B));
-    NDL_TRY(prepare_lds<double>(B));
+    NDL_TRY(prepare_lds<double>(B, res32));
     // Jacobi: dinv = 1 / diag(-L) (in the inner type)
     NDL_TRY(launch_div_items<T>(B, di, dit, (const T*)nullptr, (T*)vq.p, (const int4*)d_full.p,
                                 (const double*)d_fw.p, nfull, (const double*)d_Tinv.p, nullptr, nullptr, true, s));
@@ -1081,9 +1126,9 @@ static int cg_solve_t(const ndl_plan* plans, int nprob, const double* const* b, 
     const int max_outer = mixed ? 20 : 3;
     for (int out_it = 0; out_it < max_outer; ++out_it) {
         // true FP64 residual r = b - A x
-        NDL_TRY(launch_div_items<double>(B, di64, dit, (const double*)vx.p, (double*)vax.p, (const int4*)d_full.p,
+        NDL_TRY(launch_div_items<double>(B, dres, dit, (const double*)vx.p, (double*)vax.p, (const int4*)d_full.p,
                                          (const double*)d_fw.p, nfull, (const double*)d_Tinv.p, nullptr, nullptr,
-                                         false, s));
+                                         false, s, res32));
         k_residual<double><<<gi, 256, 0, s>>>(di, dit, nitems, (const double*)vb.p, (const double*)vax.p,
                                                (double*)vr64.p, (double*)pn2.p);
         k_item_sums<<<nprob, 256, 0, s>>>(nprob, di, (const double*)pn2.p, (double*)sres.p);
@@ -1139,9 +1184,9 @@ static int cg_solve_t(const ndl_plan* plans, int nprob, const double* const* b, 
         NDL_HIP(hipGetLastError());
     }
     // final residual (FP64) and copy-out
-    NDL_TRY(launch_div_items<double>(B, di64, dit, (const double*)vx.p, (double*)vax.p, (const int4*)d_full.p,
+    NDL_TRY(launch_div_items<double>(B, dres, dit, (const double*)vx.p, (double*)vax.p, (const int4*)d_full.p,
                                      (const double*)d_fw.p, nfull, (const double*)d_Tinv.p, nullptr, nullptr, false,
-                                     s));
+                                     s, res32));
     k_residual<double><<<gi, 256, 0, s>>>(di, dit, nitems, (const double*)vb.p, (const double*)vax.p,
                                            (double*)vr64.p, (double*)pn2.p);
     k_item_sums<<<nprob, 256, 0, s>>>(nprob, di, (const double*)pn2.p, (double*)sres.p);
@@ -1386,11 +1431,14 @@ static int pcg_learned_t(const ndl_plan plan, const double* b, double* x, const 
         i64.coef = dc64.p;
     }
     NDL_HIP(hipMemcpy(d_insts64.p, &i64, sizeof(Inst), hipMemcpyHostToDevice));
-    NDL_TRY(prepare_lds<T>(B));
-    NDL_TRY(prepare_lds<double>(B));
     const Inst* di = (const Inst*)d_insts.p;
     const Inst* di64 = (const Inst*)d_insts64.p;
     const int2* dit = (const int2*)d_items.p;
+    // the outer FP64 residual of a 3D mixed solve reads the FP32 fields directly
+    const bool res32 = sizeof(T) == 4 && B.dim == 3 && use_div_spec<double>(B, true);
+    const Inst* dres = res32 ? di : di64;
+    NDL_TRY(prepare_lds<T>(B));
+    NDL_TRY(prepare_lds<double>(B, res32));
     DevBuf vx, vax, vr64, vd, vr, vz, vzo, vp, vq, vdinv, pa, pb, sres;
     NDL_TRY(alloc<double>(vx, N));
     NDL_TRY(alloc<double>(vax, N));
@@ -1443,9 +1491,9 @@ static int pcg_learned_t(const ndl_plan plan, const double* b, double* x, const 
     bool jac = false, conv = false;
     double rel = 1.0;
     for (int o = 0; o < 20; ++o) {
-        NDL_TRY(launch_div_items<double>(B, di64, dit, (const double*)vx.p, (double*)vax.p, (const int4*)d_full.p,
+        NDL_TRY(launch_div_items<double>(B, dres, dit, (const double*)vx.p, (double*)vax.p, (const int4*)d_full.p,
                                          (const double*)d_fw.p, nfull, (const double*)d_Tinv.p, nullptr, nullptr,
-                                         false, s));
+                                         false, s, res32));
         k_residual<double><<<gi, 256, 0, s>>>(di, dit, nitems, b, (const double*)vax.p, (double*)vr64.p,
                                                (double*)pa.p);
         double rn2 = 0.0;
