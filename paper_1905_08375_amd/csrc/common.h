@@ -102,7 +102,10 @@ int fast_prepare(Plan& p, hipStream_t s);
 int launch_fast(Plan& p, const void* u, void* Lu, int batch, hipStream_t s);
 int fast_decomp_host(Plan& p, const int64_t* node, int32_t* out, int cap, int* count);
 int autotune(Plan& p, hipStream_t s);
-int net_precond(void* net, const Plan& p, const void* r, void* z, hipStream_t s, const void* dinv = nullptr);
+bool net_is_linear(void* net);
+// z = M(r); add_jacobi (linear mode): z = r dinv + M(r), the two-level form, in the same pass
+int net_precond(void* net, const Plan& p, const void* r, void* z, hipStream_t s, const void* dinv = nullptr,
+                bool add_jacobi = false);
 // Jacobi diagonal inverse of an FP32 case (b) plan's -L (cached with the plan's operator tables)
 int plan_dinv_f32(const Plan& P, const float** dinv, hipStream_t s);
 int plan_neg_L_f32(const Plan& P, const float* x, float* y, const float** dinv, hipStream_t s);

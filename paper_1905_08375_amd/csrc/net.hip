@@ -602,25 +602,41 @@ __global__ void k_pack_train(const float* __restrict__ r, const float* __restric
 // the smooth corrections of the operator on the unit cube).
 constexpr double kTargetScale = 32.0;
 
-// z = (channel 0 of the fp32 head output) / (rscale * kTargetScale)
-// linear mode: rs = r * sqrt(dinv) (FP32)
-template <typename T>
-__global__ void k_scale_in(const T* __restrict__ r, const T* __restrict__ dinv, int64_t n, float* __restrict__ rs)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) rs[i] = (float)((double)r[i] * sqrt((double)dinv[i]));
-}
-
-// linear mode: z = sqrt(dinv) * y0 / (rscale * target scale)
+// linear mode: z = sqrt(dinv) * y0 / (rscale * target scale), plus the Jacobi
+// term r dinv of the two-level preconditioner when r is given
 template <typename T>
 __global__ void k_unpack_scaled(const float* __restrict__ y, const double* __restrict__ rscale,
-                                const T* __restrict__ dinv, int64_t n, T* __restrict__ z)
+                                const T* __restrict__ dinv, int64_t n, T* __restrict__ z, const T* __restrict__ r)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    z[i] = (T)(sqrt((double)dinv[i]) * (double)y[i] / (*rscale * kTargetScale));
+    const T zn = (T)(sqrt((double)dinv[i]) * (double)y[i] / (*rscale * kTargetScale));
+    z[i] = r ? r[i] * dinv[i] + zn : zn;
 }
 
+// linear mode: rs = r sqrt(dinv) (the network's input before normalisation)
+// and per-block partial sums of rs^2, in one pass
+template <typename T>
+__global__ __launch_bounds__(256) void k_scale_in_sumsq(const T* __restrict__ r, const T* __restrict__ dinv,
+                                                        int64_t n, float* __restrict__ rs, double* __restrict__ part)
+{
+    __shared__ double sh[256];
+    double a = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float v = (float)((double)r[i] * sqrt((double)dinv[i]));
+        rs[i] = v;
+        a += (double)v * (double)v;
+    }
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// z = (channel 0 of the fp32 head output) / (rscale * kTargetScale)
 template <typename T>
 __global__ void k_unpack(const float* __restrict__ y, const double* __restrict__ rscale, int64_t n, T* __restrict__ z)
 {
@@ -1136,12 +1152,20 @@ __global__ void k_sumsq(const T* __restrict__ r, int64_t n, double* __restrict__
 }
 
 // rscale = sqrt(N) / ||r||: the network sees the residual at unit RMS
-__global__ void k_rscale(const double* __restrict__ part, int np, double nvox, double* __restrict__ rs)
+// (one block of 256 threads; fixed summation order)
+__global__ __launch_bounds__(256) void k_rscale(const double* __restrict__ part, int np, double nvox,
+                                                double* __restrict__ rs)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double s = 0.0;
-    for (int i = 0; i < np; ++i) s += part[i];
-    *rs = s > 0.0 ? sqrt(nvox / s) : 1.0;
+    __shared__ double sh[256];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < np; i += 256) a += part[i];
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *rs = sh[0] > 0.0 ? sqrt(nvox / sh[0]) : 1.0;
 }
 
 template <typename T>
@@ -1223,7 +1247,8 @@ __global__ void k_energy_grad(const float* __restrict__ r, const float* __restri
 
 // z = M(r) for a plan's cube (n^3, n % 8 == 0): input (r / ||r||, standardised log c, m / 4)
 template <typename T>
-static int precond_t(NetState& st, const Plan& p, const T* r, T* z, hipStream_t s, const T* dinv = nullptr)
+static int precond_t(NetState& st, const Plan& p, const T* r, T* z, hipStream_t s, const T* dinv = nullptr,
+                     const T* jacobi_r = nullptr)
 {
     Net& n = st.net;
     int S = (int)p.n;
@@ -1240,12 +1265,12 @@ static int precond_t(NetState& st, const Plan& p, const T* r, T* z, hipStream_t 
             NDL_HIP(hipMalloc(&st.rsc, p.N * sizeof(float)));
             st.rsc_n = p.N;
         }
-        k_scale_in<T><<<nb(p.N), 256, 0, s>>>(r, dinv, p.N, st.rsc);
-        k_sumsq<float><<<256, 256, 0, s>>>(st.rsc, p.N, n.lpart);
-        k_rscale<<<1, 64, 0, s>>>(n.lpart, 256, (double)p.N, n.rscale);
+        // the partials of ||rs||^2 fill 2048 blocks (the reduction buffer's size)
+        k_scale_in_sumsq<T><<<2048, 256, 0, s>>>(r, dinv, p.N, st.rsc, n.lpart);
+        k_rscale<<<1, 256, 0, s>>>(n.lpart, 2048, (double)p.N, n.rscale);
         k_pack_input<float><<<nb(p.N), 256, 0, s>>>(st.rsc, n.rscale, nullptr, nullptr, p.N, S, 0.0, 1.0, n.x_in);
         NDL_TRY(net_forward(n, S, s, true, true));
-        if (z) k_unpack_scaled<T><<<nb(p.N), 256, 0, s>>>(n.head, n.rscale, dinv, p.N, z);
+        if (z) k_unpack_scaled<T><<<nb(p.N), 256, 0, s>>>(n.head, n.rscale, dinv, p.N, z, jacobi_r);
         NDL_HIP(hipGetLastError());
         return NDL_OK;
     }
@@ -1261,8 +1286,8 @@ static int precond_t(NetState& st, const Plan& p, const T* r, T* z, hipStream_t 
         st.feat_isd = var > 0 ? 1.0 / std::sqrt(var) : 1.0;
         st.feat_plan = &p;
     }
-    k_sumsq<T><<<256, 256, 0, s>>>(r, p.N, n.lpart);
-    k_rscale<<<1, 64, 0, s>>>(n.lpart, 256, (double)p.N, n.rscale);
+    k_sumsq<T><<<2048, 256, 0, s>>>(r, p.N, n.lpart);
+    k_rscale<<<1, 256, 0, s>>>(n.lpart, 2048, (double)p.N, n.rscale);
     k_pack_input<T><<<nb(p.N), 256, 0, s>>>(r, n.rscale, (const T*)p.prob.delta, (const T*)p.prob.coef, p.N, S,
                                             st.feat_mu, st.feat_isd, n.x_in);
     NDL_TRY(net_forward(n, S, s, false, true));
@@ -1271,7 +1296,9 @@ static int precond_t(NetState& st, const Plan& p, const T* r, T* z, hipStream_t 
     return NDL_OK;
 }
 
-int net_precond(void* net, const Plan& p, const void* r, void* z, hipStream_t s, const void* dinv)
+bool net_is_linear(void* net) { return net && reinterpret_cast<NetState*>(net)->linear; }
+
+int net_precond(void* net, const Plan& p, const void* r, void* z, hipStream_t s, const void* dinv, bool add_jacobi)
 {
     NetState& st = *reinterpret_cast<NetState*>(net);
     if (p.dim != 3 || p.n % 8 != 0) {
@@ -1287,8 +1314,15 @@ int net_precond(void* net, const Plan& p, const void* r, void* z, hipStream_t s,
         NDL_TRY(plan_dinv_f32(p, &d, s));
         dinv = d;
     }
-    return p.prec == NDL_F64 ? precond_t<double>(st, p, (const double*)r, (double*)z, s, (const double*)dinv)
-                             : precond_t<float>(st, p, (const float*)r, (float*)z, s, (const float*)dinv);
+    if (add_jacobi && !st.linear) {
+        set_error("internal: the fused Jacobi term needs the linear preconditioner");
+        return NDL_EINVAL;
+    }
+    return p.prec == NDL_F64
+               ? precond_t<double>(st, p, (const double*)r, (double*)z, s, (const double*)dinv,
+                                   add_jacobi ? (const double*)r : nullptr)
+               : precond_t<float>(st, p, (const float*)r, (float*)z, s, (const float*)dinv,
+                                  add_jacobi ? (const float*)r : nullptr);
 }
 
 }  // namespace ndl

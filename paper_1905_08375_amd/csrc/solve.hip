@@ -1472,7 +1472,10 @@ static int pcg_learned_t(const ndl_plan plan, const double* b, double* x, const 
     };
     // two-level preconditioner: z = D^-1 r + M(r); the network supplies the
     // smooth part of the correction that the Jacobi term misses
+    // (a linear network adds the Jacobi term while unscaling its output)
+    const bool fused_jacobi = net_is_linear(opts->net);
     auto precond = [&](const T* r, T* z, bool jac) -> int {
+        if (!jac && fused_jacobi) return net_precond(opts->net, P, r, z, s, vdinv.p, true);
         if (!jac) NDL_TRY(net_precond(opts->net, P, r, z, s, vdinv.p));
         k_jacobi_add<T><<<grid_for(N), 256, 0, s>>>(N, r, (const T*)vdinv.p, z, jac ? 0 : 1);
         NDL_HIP(hipGetLastError());
