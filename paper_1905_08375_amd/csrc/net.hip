@@ -120,11 +120,18 @@ __host__ __device__ constexpr int chunk_tap(int kc, int kb)
     return (kc * 32 + kb * 8) / CIN;
 }
 
-template <int CIN, int COUT, int XB, int ACT, int OUTK, int ZB, int NWV, bool WREG, bool UP>
+// SRC selects what is staged: 0 the BF16 input, 1 the BF16 input plus the
+// nearest upsampling of the coarse tensor up (side S/2), 2 (CIN = 8) the
+// single FP32 channel in32 times *rscale, rounded to BF16, as channel 0.
+template <int CIN, int COUT, int XB, int ACT, int OUTK, int ZB, int NWV, bool WREG, int SRC>
 __global__ __launch_bounds__(64 * NWV) void k_conv_fwd(const bf16_t* __restrict__ in, const bf16_t* __restrict__ up,
+                                                       const float* __restrict__ in32,
+                                                       const double* __restrict__ rscale,
                                                        const bf16_t* __restrict__ w, const float* __restrict__ bias,
                                                        void* __restrict__ out, int S, int nbx, int nby, int nblocks)
 {
+    constexpr bool UP = SRC == 1;
+    static_assert(SRC != 2 || CIN == 8, "the FP32 single-channel input feeds the 8-channel input layer");
     using CPL = ConvPlane<CIN, XB, NWV>;
     constexpr int CPV = CPL::CPV, LX = CPL::LX, PER = CPL::PER, NTH = CPL::NTH;
     constexpr int KP = kpad(CIN);
@@ -160,15 +167,28 @@ __global__ __launch_bounds__(64 * NWV) void k_conv_fwd(const bf16_t* __restrict_
         const int ly = vox / LX, lx = vox - ly * LX;
         const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
         const bool ok = c < CPL::CHUNKS && gx >= 0 && gx < S && gy >= 0 && gy < S;
-        goff[q] = ok ? ((gy * S + gx) * CIN + cc * 8) * 2 : (int)0x80000000u;
+        goff[q] = ok ? (SRC == 2 ? (gy * S + gx) * 4 : ((gy * S + gx) * CIN + cc * 8) * 2) : (int)0x80000000u;
         if (UP) coff[q] = ok ? (((gy >> 1) * Sc + (gx >> 1)) * CIN + cc * 8) * 2 : (int)0x80000000u;
         gslot[q] = c < CPL::CHUNKS ? plane_slot<CPV>(vox, cc) : -1;
     }
     // one input plane as a buffer resource: planes outside the grid get no
     // records, so every load from them returns zero
     const int plane_bytes = S * S * CIN * 2;
+    const double rsv = SRC == 2 ? *rscale : 1.0;
     auto fetch = [&](uint4 (&r)[PER], int gz) {
         const bool zin = gz >= 0 && gz < S;
+        if (SRC == 2) {
+            const float* pz = in32 + (int64_t)(zin ? gz : 0) * S * S;
+            const __amdgpu_buffer_rsrc_t rs =
+                __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(pz), (short)0, zin ? S * S * 4 : 0, 0x00020000);
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const float v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, goff[q], 0, 0));
+                const __bf16 x = (__bf16)(float)((double)v * rsv);
+                r[q] = make_uint4((uint32_t)__builtin_bit_cast(uint16_t, x), 0u, 0u, 0u);
+            }
+            return;
+        }
         const bf16_t* pz = in + (int64_t)(zin ? gz : 0) * pstride;
         const __amdgpu_buffer_rsrc_t rs =
             __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t*>(pz), (short)0, zin ? plane_bytes : 0, 0x00020000);
@@ -852,8 +872,8 @@ static int net_workspace(Net& n, int S)
 // channels) x NWV voxels and ZB planes; the weights stay in registers when
 // WREG (a lane's share is at most 14 fragments).
 template <int CIN, int COUT, int ZB, int NWV, bool WREG>
-static int conv_fwd_launch(const bf16_t* in, const bf16_t* up, const bf16_t* w, const float* bias, void* out, int S,
-                           int act, int outk, hipStream_t s)
+static int conv_fwd_launch(const bf16_t* in, const bf16_t* up, const float* in32, const double* rscale,
+                           const bf16_t* w, const float* bias, void* out, int S, int act, int outk, hipStream_t s)
 {
     constexpr int XB = CIN >= 32 ? 32 : 64;
     constexpr int KP = kpad(CIN);
@@ -862,28 +882,40 @@ static int conv_fwd_launch(const bf16_t* in, const bf16_t* up, const bf16_t* w, 
     const int nbx = (S + XB - 1) / XB, nby = (S + NWV - 1) / NWV, nbz = (S + ZB - 1) / ZB;
     const int nblocks = nbx * nby * nbz;
     dim3 grid((unsigned)nblocks), block(CPL::NTH);
-#define NDL_KCF(ACT_, OUTK_, UP_) k_conv_fwd<CIN, COUT, XB, ACT_, OUTK_, ZB, NWV, WREG, UP_>
-#define NDL_KCF_GO(ACT_, OUTK_, UP_)                                                                          \
-    do {                                                                                                     \
-        if (lds > 64 * 1024)                                                                                 \
-            NDL_HIP(hipFuncSetAttribute((const void*)NDL_KCF(ACT_, OUTK_, UP_),                              \
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));              \
-        NDL_KCF(ACT_, OUTK_, UP_)<<<grid, block, lds, s>>>(in, up, w, bias, out, S, nbx, nby, nblocks);       \
+#define NDL_KCF(ACT_, OUTK_, SRC_) k_conv_fwd<CIN, COUT, XB, ACT_, OUTK_, ZB, NWV, WREG, SRC_>
+#define NDL_KCF_GO(ACT_, OUTK_, SRC_)                                                                          \
+    do {                                                                                                      \
+        if (lds > 64 * 1024)                                                                                  \
+            NDL_HIP(hipFuncSetAttribute((const void*)NDL_KCF(ACT_, OUTK_, SRC_),                              \
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));               \
+        NDL_KCF(ACT_, OUTK_, SRC_)<<<grid, block, lds, s>>>(in, up, in32, rscale, w, bias, out, S, nbx, nby,   \
+                                                            nblocks);                                        \
     } while (0)
-    if (up) {
-        // skip additions feed the decoder convolutions (BF16 out, equal channel counts)
-        if constexpr (CIN == COUT) {
-            if (outk != 0 || (S & 1)) { set_error("conv with upsampled input: unsupported form"); return NDL_EINVAL; }
-            if (act) NDL_KCF_GO(1, 0, true);
-            else NDL_KCF_GO(0, 0, true);
+    if (up || in32) {
+        // inference-only forms: BF16 out
+        if (outk != 0 || (S & 1)) { set_error("conv with a fused input: unsupported form"); return NDL_EINVAL; }
+        if (up) {
+            // skip additions feed the decoder convolutions (equal channel counts)
+            if constexpr (CIN == COUT) {
+                if (act) NDL_KCF_GO(1, 0, 1);
+                else NDL_KCF_GO(0, 0, 1);
+            } else {
+                set_error("conv with upsampled input: channel counts differ");
+                return NDL_EINVAL;
+            }
         } else {
-            set_error("conv with upsampled input: channel counts differ");
-            return NDL_EINVAL;
+            if constexpr (CIN == 8) {
+                if (act) NDL_KCF_GO(1, 0, 2);
+                else NDL_KCF_GO(0, 0, 2);
+            } else {
+                set_error("conv with an FP32 single-channel input: the input layer only");
+                return NDL_EINVAL;
+            }
         }
-    } else if (outk == 2) NDL_KCF_GO(0, 2, false);
-    else if (outk == 1) NDL_KCF_GO(0, 1, false);
-    else if (act) NDL_KCF_GO(1, 0, false);
-    else NDL_KCF_GO(0, 0, false);
+    } else if (outk == 2) NDL_KCF_GO(0, 2, 0);
+    else if (outk == 1) NDL_KCF_GO(0, 1, 0);
+    else if (act) NDL_KCF_GO(1, 0, 0);
+    else NDL_KCF_GO(0, 0, 0);
 #undef NDL_KCF_GO
 #undef NDL_KCF
     NDL_HIP(hipGetLastError());
@@ -895,21 +927,24 @@ static int conv_fwd_launch(const bf16_t* in, const bf16_t* up, const bf16_t* w, 
 // LDS (two 8-wave blocks per CU), the middle ones 4-row patches of 8 planes,
 // the coarsest 4 planes so that the launch still spreads over the CUs.
 template <int CIN, int COUT>
-static int conv_fwd_t(const bf16_t* in, const bf16_t* up, const bf16_t* w, const float* bias, void* out, int S,
-                      int act, int outk, hipStream_t s)
+static int conv_fwd_t(const bf16_t* in, const bf16_t* up, const float* in32, const double* rscale, const bf16_t* w,
+                      const float* bias, void* out, int S, int act, int outk, hipStream_t s)
 {
     constexpr bool WR = (kpad(CIN) / 32) * (COUT / 16) <= 14;
-    if (S >= 128) return conv_fwd_launch<CIN, COUT, 16, 8, false>(in, up, w, bias, out, S, act, outk, s);
-    if (S >= 64) return conv_fwd_launch<CIN, COUT, 8, 4, WR>(in, up, w, bias, out, S, act, outk, s);
-    return conv_fwd_launch<CIN, COUT, 4, 4, WR>(in, up, w, bias, out, S, act, outk, s);
+    if (S >= 128) return conv_fwd_launch<CIN, COUT, 16, 8, false>(in, up, in32, rscale, w, bias, out, S, act, outk, s);
+    if (S >= 64) return conv_fwd_launch<CIN, COUT, 8, 4, WR>(in, up, in32, rscale, w, bias, out, S, act, outk, s);
+    return conv_fwd_launch<CIN, COUT, 4, 4, WR>(in, up, in32, rscale, w, bias, out, S, act, outk, s);
 }
 
-// y = conv(x) (up null) or y = conv(x + up2(up)) with the skip sum formed while
-// staging (up: the coarse tensor, side S/2, same channels)
+// y = conv(x); fused inputs (inference): up = the coarse tensor (side S/2,
+// same channels) whose nearest upsampling is added to x while staging, or
+// in32 = an FP32 single channel scaled by *rscale in place of x (input layer)
 static int conv_fwd(int cin, int cout, const bf16_t* in, const bf16_t* w, const float* bias, void* out, int S, int act,
-                    int outk, hipStream_t s, const bf16_t* up = nullptr)
+                    int outk, hipStream_t s, const bf16_t* up = nullptr, const float* in32 = nullptr,
+                    const double* rscale = nullptr)
 {
-#define NDL_CF(A, B) if (cin == A && cout == B) return conv_fwd_t<A, B>(in, up, w, bias, out, S, act, outk, s)
+#define NDL_CF(A, B) \
+    if (cin == A && cout == B) return conv_fwd_t<A, B>(in, up, in32, rscale, w, bias, out, S, act, outk, s)
     NDL_CF(8, 16);
     NDL_CF(16, 16);
     NDL_CF(16, 32);
@@ -1042,9 +1077,11 @@ static const bf16_t* layer_input(Net& n, int i)
 }
 
 // Inference (fuse_up) forms the decoder's skip sums while staging the next
-// convolution's input instead of storing them; training keeps them for the
-// weight gradients.
-static int net_forward(Net& n, int S, hipStream_t s, bool linear = false, bool fuse_up = false)
+// convolution's input instead of storing them, and (in32, linear mode) stages
+// the input layer from the scaled FP32 residual; training keeps every layer
+// input for the weight gradients.
+static int net_forward(Net& n, int S, hipStream_t s, bool linear = false, bool fuse_up = false,
+                       const float* in32 = nullptr, const double* rscale = nullptr)
 {
     int Sl[4] = {S, S / 2, S / 4, S / 8};
     auto conv = [&](int i, const bf16_t* in = nullptr, const bf16_t* up = nullptr) -> int {
@@ -1052,7 +1089,8 @@ static int net_forward(Net& n, int S, hipStream_t s, bool linear = false, bool f
         int lv = level_of_layer(i);
         bool head = i == kNumLayers - 1;
         return conv_fwd(l.sp.cin, l.sp.cout, in ? in : layer_input(n, i), l.wbf, linear ? nullptr : l.b32,
-                        head ? (void*)n.head : (void*)n.a[i], Sl[lv], linear ? 0 : l.sp.act, head ? 2 : 0, s, up);
+                        head ? (void*)n.head : (void*)n.a[i], Sl[lv], linear ? 0 : l.sp.act, head ? 2 : 0, s, up,
+                        i == 0 ? in32 : nullptr, rscale);
     };
     auto vox = [&](int l) { return (int64_t)Sl[l] * Sl[l] * Sl[l]; };
     NDL_TRY(conv(0));
@@ -1248,7 +1286,7 @@ __global__ void k_energy_grad(const float* __restrict__ r, const float* __restri
 // z = M(r) for a plan's cube (n^3, n % 8 == 0): input (r / ||r||, standardised log c, m / 4)
 template <typename T>
 static int precond_t(NetState& st, const Plan& p, const T* r, T* z, hipStream_t s, const T* dinv = nullptr,
-                     const T* jacobi_r = nullptr)
+                     const T* jacobi_r = nullptr, bool train = false)
 {
     Net& n = st.net;
     int S = (int)p.n;
@@ -1268,8 +1306,13 @@ static int precond_t(NetState& st, const Plan& p, const T* r, T* z, hipStream_t 
         // the partials of ||rs||^2 fill 2048 blocks (the reduction buffer's size)
         k_scale_in_sumsq<T><<<2048, 256, 0, s>>>(r, dinv, p.N, st.rsc, n.lpart);
         k_rscale<<<1, 256, 0, s>>>(n.lpart, 2048, (double)p.N, n.rscale);
-        k_pack_input<float><<<nb(p.N), 256, 0, s>>>(st.rsc, n.rscale, nullptr, nullptr, p.N, S, 0.0, 1.0, n.x_in);
-        NDL_TRY(net_forward(n, S, s, true, true));
+        if (train) {
+            k_pack_input<float><<<nb(p.N), 256, 0, s>>>(st.rsc, n.rscale, nullptr, nullptr, p.N, S, 0.0, 1.0,
+                                                        n.x_in);
+            NDL_TRY(net_forward(n, S, s, true, false));
+        } else {
+            NDL_TRY(net_forward(n, S, s, true, true, st.rsc, n.rscale));
+        }
         if (z) k_unpack_scaled<T><<<nb(p.N), 256, 0, s>>>(n.head, n.rscale, dinv, p.N, z, jacobi_r);
         NDL_HIP(hipGetLastError());
         return NDL_OK;
@@ -1290,7 +1333,7 @@ static int precond_t(NetState& st, const Plan& p, const T* r, T* z, hipStream_t 
     k_rscale<<<1, 256, 0, s>>>(n.lpart, 2048, (double)p.N, n.rscale);
     k_pack_input<T><<<nb(p.N), 256, 0, s>>>(r, n.rscale, (const T*)p.prob.delta, (const T*)p.prob.coef, p.N, S,
                                             st.feat_mu, st.feat_isd, n.x_in);
-    NDL_TRY(net_forward(n, S, s, false, true));
+    NDL_TRY(net_forward(n, S, s, false, !train));
     if (z) k_unpack<T><<<nb(p.N), 256, 0, s>>>(n.head, n.rscale, p.N, z);
     NDL_HIP(hipGetLastError());
     return NDL_OK;
@@ -1495,7 +1538,7 @@ int ndl_net_train_step_energy(ndl_net net, ndl_plan plan, int batch, const float
     // size the workspace and the features
     const float* dinv = nullptr;
     NDL_TRY(plan_dinv_f32(P, &dinv, hs));
-    NDL_TRY(precond_t<float>(st, P, r, nullptr, hs, dinv));
+    NDL_TRY(precond_t<float>(st, P, r, nullptr, hs, dinv, nullptr, true));
     NDL_TRY(grads_workspace(st, S));
     float *z = nullptr, *az = nullptr;
     NDL_HIP(hipMalloc(&z, N * sizeof(float)));
@@ -1509,7 +1552,7 @@ int ndl_net_train_step_energy(ndl_net net, ndl_plan plan, int batch, const float
     for (int b = 0; b < batch && rc == NDL_OK; ++b) {
         const float* rb = r + (size_t)b * N;
         const float* eb = e + (size_t)b * N;
-        rc = precond_t<float>(st, P, rb, nullptr, hs, dinv);  // head output for rb
+        rc = precond_t<float>(st, P, rb, nullptr, hs, dinv, nullptr, true);  // head output for rb
         if (rc != NDL_OK) break;
         k_z_two_level<<<nb(N), 256, 0, hs>>>(n.head, n.rscale, rb, dinv, N, st.linear ? 1 : 0, z);
         rc = plan_neg_L_f32(P, z, az, nullptr, hs);

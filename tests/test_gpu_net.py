@@ -209,3 +209,83 @@ def test_linear_network_forward_matches_oracle():
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     say("  rel l2", err)
     assert err < 2e-3
+
+
+def _write_layers(net, layers, path):
+    """Save the net, replace its FP32 weights and biases by `layers`, write to path."""
+    import struct
+    ndl.ndl_net_save(net, path)
+    raw = bytearray(open(path, "rb").read())
+    off, i = 16, 0
+    while off < len(raw):
+        cout, kp = struct.unpack_from("<ii", raw, off)
+        w, b = layers[i]
+        raw[off + 8:off + 8 + 4 * cout * kp] = np.asarray(w, np.float32).tobytes()
+        raw[off + 8 + 4 * cout * kp:off + 8 + 4 * (cout * kp + cout)] = np.asarray(b, np.float32).tobytes()
+        off += 8 + 4 * (cout * kp + cout)
+        i += 1
+    open(path, "wb").write(bytes(raw))
+
+
+def test_energy_training_step_follows_the_loss_gradient(tmp_path):
+    """One Adam step of the energy-norm training (linear mode) moves each
+    weight by lr sign(g); the sign of g is checked against central finite
+    differences of the loss the same entry point reports (the loss is
+    quadratic in any one weight, so the difference quotient is exact up to
+    rounding), on weights of the input, encoder, decoder and output layers."""
+    import torch
+    from paper_1905_08375_amd import precond_train as PT
+    say("case energy training gradient signs")
+    n = 16
+    plan, b, feat, w = PT.problem_3d(n, 9)
+    # a smooth error (the part Jacobi-CG leaves, which the network targets)
+    xs = (np.arange(n) + 0.5) / n
+    Z, Y, X = np.meshgrid(xs, xs, xs, indexing="ij")
+    e64 = np.sin(np.pi * X) * np.sin(np.pi * Y) * np.sin(np.pi * Z) + 0.3 * np.sin(2 * np.pi * X) * np.sin(np.pi * Y)
+    e = torch.from_numpy(e64.astype(np.float32)).cuda().reshape(1, n, n, n).contiguous()
+    r = PT.neg_L(plan, e[0], n).reshape(1, n, n, n).contiguous()
+    base = ndl.ndl_net_create(seed=3)
+    ndl.ndl_net_set_linear(base, True)
+    layers = _read_layers(base)
+    path = str(tmp_path / "w.bin")
+
+    def loss_at(lay, lr=0.0):
+        _write_layers(base, lay, path)
+        net = ndl.ndl_net_create(seed=3)
+        ndl.ndl_net_load(net, path)
+        ndl.ndl_net_set_linear(net, True)
+        out = ndl.ndl_net_train_step_energy(net, plan, r, e, lr)
+        torch.cuda.synchronize()
+        return out, net
+
+    lr = 1e-4
+    _, stepped = loss_at(layers, lr)
+    after = _read_layers(stepped)
+    rng = np.random.default_rng(0)
+    cins = [8, 16, 16, 16, 16, 32, 32, 32, 32, 32, 16, 16, 16]
+    checked = 0
+    for li in (0, 1, 8, 10, 11, 12):
+        wl = layers[li][0]
+        cout = wl.shape[0]
+        picks = [(int(rng.integers(cout if li != 12 else 1)), int(rng.integers(27 * (1 if li == 0 else cins[li]))))
+                 for _ in range(6)]
+        for co, k in picks:
+            if li == 0:
+                k = k * 8  # channel 0 of the input layer (the residual)
+            # a perturbation several times the weight: the central difference
+            # of a quadratic is exact for any h, and a large h lifts the change
+            # of the loss above the BF16 rounding of the activations
+            h = 0.5
+            lp = [(a.copy(), bb.copy()) for a, bb in layers]
+            lm = [(a.copy(), bb.copy()) for a, bb in layers]
+            lp[li][0][co, k] += h
+            lm[li][0][co, k] -= h
+            gfd = (loss_at(lp)[0] - loss_at(lm)[0]) / (2 * h)
+            step = wl[co, k] - after[li][0][co, k]
+            say(f"  layer {li} w[{co}][{k}] fd {gfd:.3e} step {step:.3e}")
+            if abs(gfd) < 3e-4:
+                continue
+            assert np.sign(step) == np.sign(gfd), (li, co, k, gfd, step)
+            assert abs(abs(step) - lr) <= 0.05 * lr
+            checked += 1
+    assert checked >= 10
