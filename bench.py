@@ -211,6 +211,34 @@ def bench_pcg_3d(n=256, seed=100, train_steps=0, max_iter=None):
     return res
 
 
+def bench_net(n=256, seed=100, reps=50):
+    """One inference of the shipped preconditioner network (linear mode) on a
+    256^3 residual through ndl_precond_apply: input scaling, 13 BF16 MFMA
+    convolutions, 3 poolings, the output unscaling; ms per inference."""
+    import torch
+    from paper_1905_08375_amd import ndl
+    from paper_1905_08375_amd import precond_train as PT
+    if not os.path.exists(PT.WEIGHTS):
+        return {"skipped": "no trained weights in the tree"}
+    net = PT.load_net(PT.WEIGHTS)
+    plan, b, _, _ = PT.problem_3d(n, seed)
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    r = torch.randn((n, n, n), device="cuda", generator=g)
+    z = torch.empty_like(r)
+    for _ in range(3):
+        ndl.ndl_precond_apply(net, plan, r, z)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ndl.ndl_precond_apply(net, plan, r, z)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    plan.close()
+    return {"ms_per_inference": ms, "voxels": n ** 3, "layers": 13, "precision": "bf16 activations and weights, fp32 accumulation"}
+
+
 def bench_sweep(n=1024, ms=(2, 4, 8, 16, 32, 64), example1=True):
     """Direct sum vs the Section 3 evaluation for the constant profile (p^0 = g
     exactly, so the hierarchical path is pure panel sums) at growing horizon
@@ -321,7 +349,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-rows", action="store_true", help="headline only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", default="", help="run one row only (profiling): cg64, pcg3d, pd, sweep, fast, f64")
+    ap.add_argument("--only", default="", help="run one row only (profiling): cg64, pcg3d, net, pd, sweep, fast, f64")
     ap.add_argument("--cg-iters", type=int, default=0, help="cap the solver iterations (profiling)")
     ap.add_argument("--variant", type=int, default=None,
                     help="fixed tile variant for the headline instead of the autotuner's (profiling runs)")
@@ -337,7 +365,7 @@ def main():
     if args.only:
         fn = {"cg64": lambda: bench_solve(max_iter=args.cg_iters or None),
               "pcg3d": lambda: bench_pcg_3d(max_iter=args.cg_iters or None),
-              "pd": bench_pd, "sweep": bench_sweep, "f64": lambda: bench_apply(ndl.NDL_F64, False, args.steps, args.warmup)["seconds"],
+              "net": bench_net, "pd": bench_pd, "sweep": bench_sweep, "f64": lambda: bench_apply(ndl.NDL_F64, False, args.steps, args.warmup)["seconds"],
               "fast": lambda: bench_apply(ndl.NDL_F32C, True, args.steps, args.warmup)["seconds"]}[args.only]
         print(json.dumps({"only": args.only, "result": fn()}, default=str), flush=True)
         return
@@ -381,6 +409,8 @@ def main():
         rows["cg_64_uneven_to_1e-8"] = bench_solve()
         log("row: 3D 256^3 PCG to 1e-8, plain vs learned")
         rows["pcg_3d_256_to_1e-8"] = bench_pcg_3d()
+        log("row: preconditioner network inference at 256^3")
+        rows["precond_net_3d_256"] = bench_net()
     cpu = None if args.no_cpu else cpu_baseline()
     line = {
         "metric": "Gpoint-applies/s of L_delta (2D var. horizon); PCG time to 1e-8: learned vs plain",

@@ -57,6 +57,7 @@ static inline bf16_t f2bf_host(float f)
 
 constexpr int kpad(int cin) { return ((27 * cin + 31) / 32) * 32; }
 
+
 // ------------------------------------------------------------------ forward conv (MFMA)
 // in  : [S][S][S][CIN] bf16, w : [COUT][KP] bf16, bias : [COUT] fp32 (may be null)
 // out : [S][S][S][COUT] bf16 (OUTK 0, ACT 1 = relu), fp32 (OUTK 1), or only
@@ -139,10 +140,11 @@ __global__ __launch_bounds__(64 * NWV) void k_conv_fwd(const bf16_t* __restrict_
     constexpr int NT = XB / 16;   // MFMA voxel tiles per wave
     constexpr int NC = COUT / 16; // MFMA channel tiles
     constexpr int PL16 = CPL::CHUNKS;  // 16-byte slots of one haloed plane
-    constexpr int KPL = KP + 8;   // LDS pitch of a weight row (breaks the bank period)
     extern __shared__ __align__(16) unsigned char smem[];
     uint4* sin = reinterpret_cast<uint4*>(smem);                // [3][PL16], plane p in slot p mod 3
-    bf16_t* sw = reinterpret_cast<bf16_t*>(sin + 3 * PL16);     // [COUT][KPL] (weights in LDS only)
+    // weights in LDS (when not in registers) in fragment order: fragment
+    // (c, kc) is 1 KB, lane l's 16 bytes at l 16, so every read is linear
+    uint4* swf = sin + 3 * PL16;
 
     // XCD-aware order: each XCD walks a contiguous run of patches, x fastest,
     // so the y neighbours that share halo rows sit in the same L2
@@ -222,9 +224,10 @@ __global__ __launch_bounds__(64 * NWV) void k_conv_fwd(const bf16_t* __restrict_
             for (int c = 0; c < NC; ++c)
                 wr[kc * NC + c] = *reinterpret_cast<const uint4*>(w + (c * 16 + row) * KP + kc * 32 + kb * 8);
     } else {
-        for (int e = threadIdx.x; e < COUT * (KP / 8); e += NTH) {
-            const int co = e / (KP / 8), k8 = e - co * (KP / 8);
-            *reinterpret_cast<uint4*>(sw + co * KPL + k8 * 8) = reinterpret_cast<const uint4*>(w)[e];
+        for (int e = threadIdx.x; e < NC * KC * 64; e += NTH) {
+            const int frag = e >> 6, l = e & 63;
+            const int c = frag / KC, kc = frag - c * KC;
+            swf[e] = *reinterpret_cast<const uint4*>(w + (c * 16 + (l & 15)) * KP + kc * 32 + (l >> 4) * 8);
         }
     }
     float bv[NC][4];
@@ -285,7 +288,7 @@ __global__ __launch_bounds__(64 * NWV) void k_conv_fwd(const bf16_t* __restrict_
             for (int c = 0; c < NC; ++c) {
                 uint4 wa;
                 if (WREG) wa = wr[(WREG ? kc * NC + c : 0)];
-                else wa = *reinterpret_cast<const uint4*>(sw + (c * 16 + row) * KPL + kc * 32 + kb * 8);
+                else wa = swf[(c * KC + kc) * 64 + lane];
                 const bf16x8 afrag = *reinterpret_cast<const bf16x8*>(&wa);
 #pragma unroll
                 for (int t = 0; t < NT; ++t)
@@ -878,7 +881,7 @@ static int conv_fwd_launch(const bf16_t* in, const bf16_t* up, const float* in32
     constexpr int XB = CIN >= 32 ? 32 : 64;
     constexpr int KP = kpad(CIN);
     using CPL = ConvPlane<CIN, XB, NWV>;
-    const size_t lds = (size_t)3 * CPL::CHUNKS * 16 + (WREG ? 0 : (size_t)COUT * (KP + 8) * 2);
+    const size_t lds = (size_t)3 * CPL::CHUNKS * 16 + (WREG ? 0 : (size_t)COUT * KP * 2);
     const int nbx = (S + XB - 1) / XB, nby = (S + NWV - 1) / NWV, nbz = (S + ZB - 1) / ZB;
     const int nblocks = nbx * nby * nbz;
     dim3 grid((unsigned)nblocks), block(CPL::NTH);
