@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <atomic>
 #include <vector>
 
 #include "ndl.h"
@@ -48,7 +49,16 @@ struct Off {
 std::vector<Off> ball_offsets(int dim, int64_t kmax, bool half);
 
 // ------------------------------------------------------------------ plan
+inline uint64_t next_plan_uid()
+{
+    static std::atomic<uint64_t> counter{1};
+    return counter.fetch_add(1, std::memory_order_relaxed);
+}
+
 struct Plan {
+    // identity for caches keyed by plan: never reused within a process (a new
+    // plan can land at a destroyed plan's address)
+    uint64_t uid = next_plan_uid();
     ndl_problem prob{};        // caller's descriptor (poly points at `poly`)
     std::vector<double> poly;  // copied coefficients
     int dim = 0, ncomp = 1, prec = 0, model = 0, form = 0, kernel = 0, norm = 0;

@@ -1025,7 +1025,7 @@ struct NetState {
     Grads g;
     int Sg = 0;
     double feat_mu = 0.0, feat_isd = 1.0;
-    const void* feat_plan = nullptr;
+    uint64_t feat_plan = 0;  // uid of the plan the feature moments belong to
     // linear mode: no activations or biases, the input is the residual alone,
     // scaled by D^-1/2 on the way in and out (M = D^-1/2 N D^-1/2, linear in r)
     bool linear = false;
@@ -1320,7 +1320,7 @@ static int precond_t(NetState& st, const Plan& p, const T* r, T* z, hipStream_t 
         NDL_HIP(hipGetLastError());
         return NDL_OK;
     }
-    if (st.feat_plan != (const void*)&p) {
+    if (st.feat_plan != p.uid) {
         k_logc_moments<T><<<256, 256, 0, s>>>((const T*)p.prob.coef, p.N, n.lpart);
         std::vector<double> h(512);
         NDL_HIP(hipMemcpyAsync(h.data(), n.lpart, 512 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1330,7 +1330,7 @@ static int precond_t(NetState& st, const Plan& p, const T* r, T* z, hipStream_t 
         double mu = a / (double)p.N, var = b / (double)p.N - mu * mu;
         st.feat_mu = mu;
         st.feat_isd = var > 0 ? 1.0 / std::sqrt(var) : 1.0;
-        st.feat_plan = &p;
+        st.feat_plan = p.uid;
     }
     k_sumsq<T><<<2048, 256, 0, s>>>(r, p.N, n.lpart);
     k_rscale<<<1, 256, 0, s>>>(n.lpart, 2048, (double)p.N, n.rscale);

@@ -1228,6 +1228,7 @@ static int cg_solve_t(const ndl_plan* plans, int nprob, const double* const* b, 
 // with device tables built once and kept by the caller.
 struct OpCache {
     const Plan* plan = nullptr;
+    uint64_t plan_uid = 0;
     Batch B;
     DevBuf insts, items, full, fw, Tinv, part, sres, dinv;
     int nfull = 0, nitems = 0;
@@ -1236,7 +1237,7 @@ struct OpCache {
 template <typename T>
 static int op_build(const Plan& P, OpCache& oc, hipStream_t s)
 {
-    if (oc.plan == &P) return NDL_OK;
+    if (oc.plan == &P && oc.plan_uid == P.uid) return NDL_OK;
     oc = OpCache();
     ndl_plan h = reinterpret_cast<ndl_plan>(const_cast<Plan*>(&P));
     std::vector<DevBuf> keep;
@@ -1280,6 +1281,7 @@ static int op_build(const Plan& P, OpCache& oc, hipStream_t s)
     NDL_HIP(hipGetLastError());
     NDL_HIP(hipStreamSynchronize(s));
     oc.plan = &P;
+    oc.plan_uid = P.uid;
     return NDL_OK;
 }
 

@@ -157,9 +157,12 @@ def _read_layers(net):
     return layers
 
 
-def test_linear_network_forward_matches_oracle():
+@pytest.mark.parametrize("n", [16, 64])
+def test_linear_network_forward_matches_oracle(n):
     """The whole preconditioner network in linear mode (the shipped weights) on a
-    16^3 field against the FP64 reference composed from the oracle's layers:
+    16^3 and a 64^3 field (every patch shape below the full-resolution one, the
+    fused input staging and skip sums included) against the FP64 reference
+    composed from the oracle's layers:
     residual scaled by D^-1/2 (D from the oracle's case (b) diagonal) and
     normalised to unit RMS, 13 convolutions without biases or activations,
     3 average poolings, 3 nearest upsamplings with skip additions, BF16 at the
@@ -169,8 +172,7 @@ def test_linear_network_forward_matches_oracle():
     from paper_1905_08375_amd import precond_train as PT
     if not __import__("os").path.exists(PT.WEIGHTS):
         pytest.skip("no trained weights in the tree")
-    say("case linear network forward")
-    n = 16
+    say(f"case linear network forward n={n}")
     plan, b, feat, w = PT.problem_3d(n, 7)
     net = PT.load_net(PT.WEIGHTS)
     g = np.random.default_rng(5)
@@ -206,6 +208,8 @@ def test_linear_network_forward_matches_oracle():
     a11 = bf(conv(11, bf(NO.up2(a10) + a1)))
     head = conv(12, a11)[..., 0]
     ref = sq * head / (rscale * PT.TARGET_SCALE)
+    assert np.isfinite(got).all(), int((~np.isfinite(got)).sum())
+    assert np.isfinite(ref).all(), int((~np.isfinite(ref)).sum())
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     say("  rel l2", err)
     assert err < 2e-3

@@ -211,3 +211,35 @@ def test_trained_preconditioner_gains_over_jacobi(n):
         xr = x.cpu().numpy()
         Ax = -O.apply(P, d64, c64, F.pad(xr, 4))
         assert np.linalg.norm(w["b"] - Ax) / np.linalg.norm(w["b"]) <= 1.05e-8
+
+
+def test_operator_cache_survives_plan_reuse():
+    """The cached operator and Jacobi diagonal of the linear preconditioner
+    belong to one plan: plans of other sizes created and destroyed in between
+    (a new plan can take a destroyed plan's address) leave the result of a
+    later plan unchanged, bit for bit."""
+    import torch
+    from paper_1905_08375_amd import precond_train as PT
+    net = _shipped_net()
+    n = 32
+    g = torch.Generator(device="cuda").manual_seed(1)
+    r = torch.randn((n, n, n), device="cuda", generator=g)
+
+    def apply_fresh():
+        plan, _, _, _ = PT.problem_3d(n, 3)
+        z = torch.empty_like(r)
+        ndl.ndl_precond_apply(net, plan, r, z)
+        torch.cuda.synchronize()
+        plan.close()
+        return z
+
+    ref = apply_fresh()
+    for m in (16, 24, 8, 16):
+        other, _, _, _ = PT.problem_3d(m, 4)
+        zo = torch.empty((m, m, m), device="cuda")
+        ndl.ndl_precond_apply(net, other, torch.randn((m, m, m), device="cuda", generator=g), zo)
+        torch.cuda.synchronize()
+        other.close()
+        z = apply_fresh()
+        assert torch.isfinite(z).all()
+        assert torch.equal(z, ref), m
