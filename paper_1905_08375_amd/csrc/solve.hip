@@ -352,7 +352,8 @@ __global__ __launch_bounds__((DivShape<T, DIM>::THREADS)) void k_div2_items(
                           x0 + 64 + J > n;
 
         const int x = x0 + lane;
-        // 2D: wave wv holds rows 4 wv .. 4 wv + 3; 3D: plane wv, rows 0..3
+        // wave wv holds PY rows of one plane: 2D rows 4 wv .. 4 wv + 3; 3D plane
+        // wv / 2, rows 2 (wv mod 2) .. + 1 (8 planes, or a 4-plane slab for FP64 vectors)
         constexpr int WPP = SH::TY / PY;  // waves per plane
         const int wz = wv / WPP, wy = (wv % WPP) * PY;
         const int base = (wz + HZ) * PLANE + (wy + J) * PITCH + lane + J;
