@@ -5,11 +5,11 @@
 //
 // Activations are BF16 in NDHWC layout (channels innermost, C in {8, 16, 32};
 // the 3 input features are padded to 8 channels).  A convolution is an
-// implicit GEMM: M = voxels (16 per MFMA tile along x), N = output channels
-// (16 per tile), K = 27 taps x C_in, ordered k = tap * C_in + c and padded to a
-// multiple of 32; one MFMA consumes 32 consecutive k.  A block stages the
-// input rows z-1..z+1, y0-1..y0+4, x0-1..x0+XB of its 4 x XB output voxels and
-// the packed weights [C_out][K] in LDS; each wave owns one output row.
+// implicit GEMM: M = output channels (16 per MFMA tile), N = voxels (16 per
+// tile along x), K = 27 taps x C_in, ordered k = tap * C_in + c and padded to
+// a multiple of 32; one MFMA consumes 32 consecutive k.  A block stages a
+// rolling window of three haloed input planes in LDS (the weights in registers
+// or in LDS); each wave owns one output row (details at k_conv_fwd).
 //
 // Network (levels l = 0..3, channels c_l = 16, 16, 32, 32):
 //   enc_l : conv(c_{l-1} -> c_l) relu, conv(c_l -> c_l) relu   (input 8 -> 16 at l = 0)
@@ -28,6 +28,7 @@
 namespace ndl {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint16_t bf16_t;  // storage type
@@ -75,19 +76,21 @@ constexpr int kpad(int cin) { return ((27 * cin + 31) / 32) * 32; }
 // or 16-byte (FP32) store per lane and tile, 16 voxels of a wave contiguous.
 //
 // Everything that does not depend on z is computed once per block: the LDS
-// offset of every (chunk of 32 taps, lane) input fragment, the global offset
-// and LDS slot of every staged 16-byte chunk, and (for the full-resolution
-// layers, at most 14 fragments) the weight fragments, held in registers.
+// offset of every (chunk of 32 taps, lane) input fragment and the global
+// offset and LDS slot of every staged 16-byte chunk.  The weights are held in
+// registers when a lane's share is at most 14 fragments (WREG), otherwise
+// staged once per block in LDS in fragment order (fragment (c, kc): 1 KB,
+// lane l's 16 bytes at l 16, so every read is linear in the lane).
 //
 // LDS plane layout: voxel v of the haloed plane holds CIN/8 chunks of 8
 // channels; chunk h sits at slot v CPV + (h ^ ((v / (8/CPV)) mod CPV)), so
 // that 8 consecutive voxels read at one chunk index cover all 32 banks.
+
 // a + b for 8 BF16 pairs, summed in FP32 and rounded to nearest even
 __device__ __forceinline__ uint32_t bf16x2_add(uint32_t a, uint32_t b)
 {
     const float lo = __uint_as_float(a << 16) + __uint_as_float(b << 16);
     const float hi = __uint_as_float(a & 0xffff0000u) + __uint_as_float(b & 0xffff0000u);
-    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
     bf16x2 r;
     r[0] = (__bf16)lo;
     r[1] = (__bf16)hi;
