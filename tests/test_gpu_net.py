@@ -293,3 +293,40 @@ def test_energy_training_step_follows_the_loss_gradient(tmp_path):
             assert abs(abs(step) - lr) <= 0.05 * lr
             checked += 1
     assert checked >= 10
+
+
+def test_fused_inference_matches_the_training_forward():
+    """At 128^3 (the full-resolution patch shapes) the inference path, which
+    stages the input layer from the scaled FP32 residual and forms the skip
+    sums while staging, against the training forward, which stores every layer
+    input: the energy loss that ndl_net_train_step_energy reports (lr = 0, so
+    the weights stay) equals the same loss formed here from ndl_precond_apply,
+    the Jacobi term from the oracle's diagonal and the operator's apply."""
+    import torch
+    import oracle as O
+    from paper_1905_08375_amd import precond_train as PT
+    if not __import__("os").path.exists(PT.WEIGHTS):
+        pytest.skip("no trained weights in the tree")
+    say("case fused inference vs training forward n=128")
+    n = 128
+    plan, b, feat, w = PT.problem_3d(n, 11)
+    net = PT.load_net(PT.WEIGHTS)
+    xs = (np.arange(n) + 0.5) / n
+    Z, Y, X = np.meshgrid(xs, xs, xs, indexing="ij")
+    g = np.random.default_rng(2)
+    e64 = np.sin(np.pi * X) * np.sin(np.pi * Y) * np.sin(np.pi * Z) + 0.1 * g.standard_normal((n, n, n))
+    e = torch.from_numpy(e64.astype(np.float32)).cuda().contiguous()
+    r = PT.neg_L(plan, e, n).contiguous()
+    loss_train = ndl.ndl_net_train_step_energy(net, plan, r.reshape(1, n, n, n), e.reshape(1, n, n, n), 0.0)
+    zn = torch.empty_like(r)
+    ndl.ndl_precond_apply(net, plan, r, zn)
+    torch.cuda.synchronize()
+    P = O.Problem(dim=3, n=n, R=4, form="div", kernel="frac")
+    diag = np.abs(O.div_diag(P, w["delta"].astype(np.float32), w["coef"].astype(np.float32)))
+    dinv = torch.from_numpy((np.float32(1.0) / diag.astype(np.float32)).astype(np.float32)).cuda()
+    z = r * dinv + zn
+    az = PT.neg_L(plan, z, n)
+    ed, zd, rd, ad = (t.double() for t in (e, z, r, az))
+    loss_inf = float(((ed - zd) * (rd - ad)).sum() / (ed * rd).sum())
+    say("  train", loss_train, "inference", loss_inf)
+    assert abs(loss_inf - loss_train) <= 1e-4 * abs(loss_train)
