@@ -1348,18 +1348,6 @@ __global__ void k_dot2(const Inst* __restrict__ insts, const int2* __restrict__ 
     }
 }
 
-// d += alpha p ; r -= alpha q ; partial r.r
-template <typename T>
-__global__ void k_axpy2(int64_t n, double alpha, T* __restrict__ d, T* __restrict__ r, const T* __restrict__ p,
-                        const T* __restrict__ q)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    T a = (T)alpha;
-    d[i] += a * p[i];
-    r[i] -= a * q[i];
-}
-
 // p = z + beta p ; z_old = z
 template <typename T>
 __global__ void k_dir2(int64_t n, double beta, const T* __restrict__ z, T* __restrict__ p, T* __restrict__ zold)
@@ -1369,6 +1357,72 @@ __global__ void k_dir2(int64_t n, double beta, const T* __restrict__ z, T* __res
     T zv = z[i];
     p[i] = zv + (T)beta * p[i];
     zold[i] = zv;
+}
+
+// alpha = rz / p.q for one problem (items summed in the fixed order); a
+// breakdown (p.q <= 0 or not finite) gives alpha = 0 and flags it.
+// out[0] = alpha, out[1] = p.q, out[2] = breakdown flag.
+__global__ void k_pq_alpha(const Inst* __restrict__ insts, const double* __restrict__ part, double rz,
+                           double* __restrict__ out)
+{
+    __shared__ double sh[256];
+    const Inst I = insts[0];
+    const double pq = problem_sum(I, part, sh);
+    if (threadIdx.x != 0) return;
+    const bool ok = pq > 0.0 && isfinite(pq);
+    out[0] = ok ? rz / pq : 0.0;
+    out[1] = pq;
+    out[2] = ok ? 0.0 : 1.0;
+}
+
+// d += alpha p, r -= alpha q over one problem's items, with the per-item
+// partials of r.r (alpha read from the device)
+template <typename T>
+__global__ __launch_bounds__(256) void k_axpy2_rr(const Inst* __restrict__ insts, const int2* __restrict__ items,
+                                                  int nitems, const double* __restrict__ alpha, T* __restrict__ d,
+                                                  T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ q,
+                                                  double* __restrict__ prr)
+{
+    __shared__ double red[4];
+    const T a = (T)alpha[0];
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        int2 item = items[it];
+        const Inst I = insts[item.x];
+        int org[3];
+        item_geom<T>(I, item.y, org);
+        int ext[3] = {I.dim >= 3 ? I.n : 1, I.dim >= 2 ? I.n : 1, I.n};
+        double s1 = 0.0;
+        int npts = I.E[0] * I.E[1] * I.E[2];
+        for (int pi = threadIdx.x; pi < npts; pi += blockDim.x) {
+            int e2 = pi % I.E[2];
+            int rr_ = pi / I.E[2];
+            int e1 = rr_ % I.E[1];
+            int e0 = rr_ / I.E[1];
+            int x0 = org[0] + e0, x1 = org[1] + e1, x2 = org[2] + e2;
+            if (!(x0 < ext[0] && x1 < ext[1] && x2 < ext[2])) continue;
+            int64_t gi = I.off + ((int64_t)x0 * ext[1] + x1) * ext[2] + x2;
+            d[gi] += a * p[gi];
+            const T rv = r[gi] - a * q[gi];
+            r[gi] = rv;
+            s1 += (double)rv * (double)rv;
+        }
+        double t1 = block_sum(s1, red);
+        if (threadIdx.x == 0) prr[it] = t1;
+    }
+}
+
+// the sums of two item-partial arrays of one problem: out[0], out[1]
+__global__ void k_item_sums2(const Inst* __restrict__ insts, const double* __restrict__ pa,
+                             const double* __restrict__ pb, double* __restrict__ out)
+{
+    __shared__ double sh[256];
+    const Inst I = insts[0];
+    const double a = problem_sum(I, pa, sh);
+    const double b = pb ? problem_sum(I, pb, sh) : 0.0;
+    if (threadIdx.x == 0) {
+        out[0] = a;
+        out[1] = b;
+    }
 }
 
 // z = r / diag (+ z when add)
@@ -1456,6 +1510,8 @@ static int pcg_learned_t(const ndl_plan plan, const double* b, double* x, const 
     NDL_TRY(alloc<double>(pa, nitems));
     NDL_TRY(alloc<double>(pb, nitems));
     NDL_TRY(alloc<double>(sres, 2));
+    DevBuf scal;  // alpha, p.q, breakdown flag, r.r, (spare)
+    NDL_TRY(alloc<double>(scal, 5));
     NDL_HIP(hipMemcpyAsync(vx.p, x, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     NDL_TRY(launch_div_items<T>(B, di, dit, (const T*)nullptr, (T*)vq.p, (const int4*)d_full.p, (const double*)d_fw.p,
                                 nfull, (const double*)d_Tinv.p, nullptr, nullptr, true, s));
@@ -1467,10 +1523,16 @@ static int pcg_learned_t(const ndl_plan plan, const double* b, double* x, const 
         NDL_HIP(hipStreamSynchronize(s));
         return NDL_OK;
     };
+    // r.a (and r.bb) with one read-back
     auto dots = [&](const T* r, const T* a, const T* bb, double* o1, double* o2) -> int {
         k_dot2<T><<<gi, 256, 0, s>>>(di, dit, nitems, r, a, bb, (double*)pa.p, (double*)pb.p);
-        NDL_TRY(sum_items((const double*)pa.p, o1));
-        if (bb) NDL_TRY(sum_items((const double*)pb.p, o2));
+        k_item_sums2<<<1, 256, 0, s>>>(di, (const double*)pa.p, bb ? (const double*)pb.p : nullptr,
+                                       (double*)sres.p);
+        double h[2];
+        NDL_HIP(hipMemcpyAsync(h, sres.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        NDL_HIP(hipStreamSynchronize(s));
+        *o1 = h[0];
+        if (bb) *o2 = h[1];
         return NDL_OK;
     };
     // two-level preconditioner: z = D^-1 r + M(r); the network supplies the
@@ -1543,10 +1605,18 @@ static int pcg_learned_t(const ndl_plan plan, const double* b, double* x, const 
             NDL_TRY(launch_div_items<T>(B, di, dit, (const T*)vp.p, (T*)vq.p, (const int4*)d_full.p,
                                         (const double*)d_fw.p, nfull, (const double*)d_Tinv.p, nullptr, (double*)pa.p,
                                         false, s));
-            double pq = 0.0;
-            NDL_TRY(sum_items((const double*)pa.p, &pq));
+            // alpha on the device; the update and r.r in one pass (alpha = 0 on a
+            // breakdown, which leaves d and r as they were); one read-back
+            k_pq_alpha<<<1, 256, 0, s>>>(di, (const double*)pa.p, rz, (double*)scal.p);
+            k_axpy2_rr<T><<<gi, 256, 0, s>>>(di, dit, nitems, (const double*)scal.p, (T*)vd.p, (T*)vr.p,
+                                             (const T*)vp.p, (const T*)vq.p, (double*)pb.p);
+            k_item_sums2<<<1, 256, 0, s>>>(di, (const double*)pb.p, nullptr, (double*)scal.p + 3);
+            double hs[5];
+            NDL_HIP(hipMemcpyAsync(hs, scal.p, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
+            NDL_HIP(hipStreamSynchronize(s));
+            const double pq = hs[1];
             ++iters;
-            if (!(pq > 0.0) || !std::isfinite(pq)) {
+            if (hs[2] != 0.0) {
                 if (jac) break;  // even Jacobi broke down: stop this inner solve
                 jac = true;      // fall back and restart the inner directions
                 NDL_TRY(precond((const T*)vr.p, (T*)vz.p, true));
@@ -1555,9 +1625,8 @@ static int pcg_learned_t(const ndl_plan plan, const double* b, double* x, const 
                 NDL_HIP(hipMemcpyAsync(vzo.p, vz.p, N * sizeof(T), hipMemcpyDeviceToDevice, s));
                 continue;
             }
-            double alpha = rz / pq;
-            k_axpy2<T><<<grid_for(N), 256, 0, s>>>(N, alpha, (T*)vd.p, (T*)vr.p, (const T*)vp.p, (const T*)vq.p);
-            NDL_TRY(dots((const T*)vr.p, (const T*)vr.p, nullptr, &rr, &dummy));
+            (void)pq;
+            rr = hs[3];
             if (std::sqrt(rr) <= want || !std::isfinite(rr)) break;
             // stagnation of the learned directions (no 0.1% drop of the residual
             // in 200 iterations; CG residuals may plateau for a while): fall
