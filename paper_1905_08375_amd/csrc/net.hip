@@ -125,17 +125,13 @@ __host__ __device__ constexpr int chunk_tap(int kc, int kb)
 }
 
 // SRC selects what is staged: 0 the BF16 input, 1 the BF16 input plus the
-// nearest upsampling of the coarse tensor up (side S/2), 2 (CIN = 8) the
-// single FP32 channel in32 times *rscale, rounded to BF16, as channel 0.
+// nearest upsampling of the coarse tensor up (side S/2).
 template <int CIN, int COUT, int XB, int ACT, int OUTK, int ZB, int NWV, bool WREG, int SRC>
 __global__ __launch_bounds__(64 * NWV) void k_conv_fwd(const bf16_t* __restrict__ in, const bf16_t* __restrict__ up,
-                                                       const float* __restrict__ in32,
-                                                       const double* __restrict__ rscale,
                                                        const bf16_t* __restrict__ w, const float* __restrict__ bias,
                                                        void* __restrict__ out, int S, int nbx, int nby, int nblocks)
 {
     constexpr bool UP = SRC == 1;
-    static_assert(SRC != 2 || CIN == 8, "the FP32 single-channel input feeds the 8-channel input layer");
     using CPL = ConvPlane<CIN, XB, NWV>;
     constexpr int CPV = CPL::CPV, LX = CPL::LX, PER = CPL::PER, NTH = CPL::NTH;
     constexpr int KP = kpad(CIN);
@@ -172,28 +168,15 @@ __global__ __launch_bounds__(64 * NWV) void k_conv_fwd(const bf16_t* __restrict_
         const int ly = vox / LX, lx = vox - ly * LX;
         const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
         const bool ok = c < CPL::CHUNKS && gx >= 0 && gx < S && gy >= 0 && gy < S;
-        goff[q] = ok ? (SRC == 2 ? (gy * S + gx) * 4 : ((gy * S + gx) * CIN + cc * 8) * 2) : (int)0x80000000u;
+        goff[q] = ok ? ((gy * S + gx) * CIN + cc * 8) * 2 : (int)0x80000000u;
         if (UP) coff[q] = ok ? (((gy >> 1) * Sc + (gx >> 1)) * CIN + cc * 8) * 2 : (int)0x80000000u;
         gslot[q] = c < CPL::CHUNKS ? plane_slot<CPV>(vox, cc) : -1;
     }
     // one input plane as a buffer resource: planes outside the grid get no
     // records, so every load from them returns zero
     const int plane_bytes = S * S * CIN * 2;
-    const double rsv = SRC == 2 ? *rscale : 1.0;
     auto fetch = [&](uint4 (&r)[PER], int gz) {
         const bool zin = gz >= 0 && gz < S;
-        if (SRC == 2) {
-            const float* pz = in32 + (int64_t)(zin ? gz : 0) * S * S;
-            const __amdgpu_buffer_rsrc_t rs =
-                __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(pz), (short)0, zin ? S * S * 4 : 0, 0x00020000);
-#pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                const float v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, goff[q], 0, 0));
-                const __bf16 x = (__bf16)(float)((double)v * rsv);
-                r[q] = make_uint4((uint32_t)__builtin_bit_cast(uint16_t, x), 0u, 0u, 0u);
-            }
-            return;
-        }
         const bf16_t* pz = in + (int64_t)(zin ? gz : 0) * pstride;
         const __amdgpu_buffer_rsrc_t rs =
             __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t*>(pz), (short)0, zin ? plane_bytes : 0, 0x00020000);
@@ -335,6 +318,171 @@ __global__ __launch_bounds__(64 * NWV) void k_conv_fwd(const bf16_t* __restrict_
             if (z + 2 < zend) fetch(pre, z + 3);
         }
     }
+}
+
+// ------------------------------------------------------------------ input layer (linear mode)
+// In the linear preconditioner only channel 0 of the 8-channel input layer is
+// non-zero (the scaled residual), so its 3x3x3 convolution has K = 27 taps:
+// one MFMA chunk (taps 27..31 zero) instead of the 7 of the 8-channel layer.
+// The FP32 residual times *rscale is staged as single-channel BF16 planes (2
+// bytes per voxel, rounded as the packed 8-channel input would be), in the
+// rolling three-plane window of the forward convolution; a lane gathers the 8
+// taps of its fragment from them.  Output as the forward convolution's
+// OUTK 0 (BF16, 4 channels per lane).
+template <int NWV, int ZB, int ACT>
+__global__ __launch_bounds__(64 * NWV) void k_conv_in1(const float* __restrict__ in32,
+                                                       const double* __restrict__ rscale,
+                                                       const bf16_t* __restrict__ w, const float* __restrict__ bias,
+                                                       bf16_t* __restrict__ out, int S, int nbx, int nby, int nblocks)
+{
+    constexpr int COUT = 16, XB = 64, LX = XB + 2, LY = NWV + 2, PLANE = LX * LY;  // voxels per plane
+    constexpr int NTH = 64 * NWV, NT = XB / 16;
+    constexpr int KPI = kpad(8);           // row length of the 8-channel layer's packed weights
+    constexpr int PAIRS = PLANE / 2;       // LX is even: a pair never straddles two rows
+    constexpr int PER = (PAIRS + NTH - 1) / NTH;
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t* sp = reinterpret_cast<uint32_t*>(smem);  // [3][PAIRS] BF16 pairs, plane p in slot p mod 3
+    const uint16_t* sp16 = reinterpret_cast<const uint16_t*>(smem);
+
+    const int b = xcd_tile(blockIdx.x, nblocks);
+    const int bx = b % nbx, byz = b / nbx;
+    const int x0 = bx * XB, y0 = (byz % nby) * NWV, zb = (byz / nby) * ZB;
+    const int zend = min(zb + ZB, S);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int row = lane & 15, kb = lane >> 4;
+
+    // staged voxel pairs of this thread: byte offsets in an FP32 plane (past
+    // the plane outside the grid, where the buffer load returns zero)
+    int goa[PER], gob[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int c = threadIdx.x + q * NTH;
+        const int ly = (2 * c) / LX, lx = 2 * c - ly * LX;
+        const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+        const bool rowok = c < PAIRS && gy >= 0 && gy < S;
+        goa[q] = rowok && gx >= 0 && gx < S ? (gy * S + gx) * 4 : (int)0x80000000u;
+        gob[q] = rowok && gx + 1 >= 0 && gx + 1 < S ? (gy * S + gx + 1) * 4 : (int)0x80000000u;
+    }
+    const double rsv = *rscale;
+    auto fetch = [&](uint32_t (&r)[PER], int gz) {
+        const bool zin = gz >= 0 && gz < S;
+        const float* pz = in32 + (int64_t)(zin ? gz : 0) * S * S;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(pz), (short)0, zin ? S * S * 4 : 0, 0x00020000);
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const float fa = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, goa[q], 0, 0));
+            const float fb = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, gob[q], 0, 0));
+            bf16x2 v;
+            v[0] = (__bf16)(float)((double)fa * rsv);
+            v[1] = (__bf16)(float)((double)fb * rsv);
+            r[q] = __builtin_bit_cast(uint32_t, v);
+        }
+    };
+    auto store = [&](const uint32_t (&r)[PER], int slot) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int c = threadIdx.x + q * NTH;
+            if ((q + 1) * NTH <= PAIRS || c < PAIRS) sp[slot * PAIRS + c] = r[q];
+        }
+    };
+
+    // A fragment: channel 0 of taps kb 8 .. kb 8 + 7 for output channel row
+    bf16x8 afrag;
+    {
+        uint16_t wv16[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int tap = kb * 8 + e;
+            wv16[e] = tap < 27 ? w[row * KPI + tap * 8] : (uint16_t)0;
+        }
+        afrag = __builtin_bit_cast(bf16x8, wv16);
+    }
+    float bv[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) bv[e] = bias ? bias[4 * kb + e] : 0.f;
+    // the lane's taps: plane dz and in-plane offset (voxels) of tap kb 8 + e
+    int tdz[8], toff[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int tap = min(kb * 8 + e, 26);
+        tdz[e] = tap / 9;
+        toff[e] = (wv + (tap / 3) % 3) * LX + row + tap % 3;
+    }
+    const bool padlane = kb == 3;  // taps 27..31 of lane group 3 are padding
+
+    uint32_t pre[PER];
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz) {
+        fetch(pre, zb + dz);
+        store(pre, (zb + dz + 3) % 3);
+    }
+    fetch(pre, zb + 2);
+    __syncthreads();
+    const int y = y0 + wv;
+    for (int z = zb; z < zend; ++z) {
+        const int s0 = (z + 2) % 3;
+        const int sb[3] = {s0 * PLANE, (s0 == 2 ? 0 : s0 + 1) * PLANE, (s0 == 0 ? 2 : s0 - 1) * PLANE};
+        int addr[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) addr[e] = (tdz[e] == 0 ? sb[0] : tdz[e] == 1 ? sb[1] : sb[2]) + toff[e];
+        f32x4 acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            uint16_t v16[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const uint16_t v = sp16[addr[e] + t * 16];
+                v16[e] = (padlane && e >= 3) ? (uint16_t)0 : v;
+            }
+            const bf16x8 bfrag = __builtin_bit_cast(bf16x8, v16);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        }
+        if (y < S) {
+            const int64_t vrow = ((int64_t)z * S + y) * S + x0;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int x = x0 + t * 16 + row;
+                if (x >= S) continue;
+                bf16x4 o;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    float v = acc[t][e] + bv[e];
+                    if (ACT == 1) v = v > 0.f ? v : 0.f;
+                    o[e] = (__bf16)v;
+                }
+                *reinterpret_cast<bf16x4*>(out + (vrow + t * 16 + row) * COUT + 4 * kb) = o;
+            }
+        }
+        if (z + 1 < zend) {
+            __syncthreads();
+            store(pre, s0);
+            __syncthreads();
+            if (z + 2 < zend) fetch(pre, z + 3);
+        }
+    }
+}
+
+// launch of the single-channel input layer (patch shape as the forward
+// convolution's by grid size)
+static int conv_in1(const float* in32, const double* rscale, const bf16_t* w, const float* bias, bf16_t* out, int S,
+                    int act, hipStream_t s)
+{
+    auto go = [&](auto nwv_c, auto zb_c) -> int {
+        constexpr int NWV = decltype(nwv_c)::value, ZB = decltype(zb_c)::value;
+        const size_t lds = (size_t)3 * ((66 * (NWV + 2)) / 2) * 4;
+        const int nbx = (S + 63) / 64, nby = (S + NWV - 1) / NWV, nbz = (S + ZB - 1) / ZB;
+        const int nblocks = nbx * nby * nbz;
+        if (act)
+            k_conv_in1<NWV, ZB, 1><<<nblocks, 64 * NWV, lds, s>>>(in32, rscale, w, bias, out, S, nbx, nby, nblocks);
+        else
+            k_conv_in1<NWV, ZB, 0><<<nblocks, 64 * NWV, lds, s>>>(in32, rscale, w, bias, out, S, nbx, nby, nblocks);
+        NDL_HIP(hipGetLastError());
+        return NDL_OK;
+    };
+    if (S >= 128) return go(std::integral_constant<int, 8>{}, std::integral_constant<int, 16>{});
+    if (S >= 64) return go(std::integral_constant<int, 4>{}, std::integral_constant<int, 8>{});
+    return go(std::integral_constant<int, 4>{}, std::integral_constant<int, 4>{});
 }
 
 // ------------------------------------------------------------------ weight gradient (FP32 VALU)
@@ -878,8 +1026,8 @@ static int net_workspace(Net& n, int S)
 // channels) x NWV voxels and ZB planes; the weights stay in registers when
 // WREG (a lane's share is at most 14 fragments).
 template <int CIN, int COUT, int ZB, int NWV, bool WREG>
-static int conv_fwd_launch(const bf16_t* in, const bf16_t* up, const float* in32, const double* rscale,
-                           const bf16_t* w, const float* bias, void* out, int S, int act, int outk, hipStream_t s)
+static int conv_fwd_launch(const bf16_t* in, const bf16_t* up, const bf16_t* w, const float* bias, void* out, int S,
+                           int act, int outk, hipStream_t s)
 {
     constexpr int XB = CIN >= 32 ? 32 : 64;
     constexpr int KP = kpad(CIN);
@@ -894,29 +1042,17 @@ static int conv_fwd_launch(const bf16_t* in, const bf16_t* up, const float* in32
         if (lds > 64 * 1024)                                                                                  \
             NDL_HIP(hipFuncSetAttribute((const void*)NDL_KCF(ACT_, OUTK_, SRC_),                              \
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));               \
-        NDL_KCF(ACT_, OUTK_, SRC_)<<<grid, block, lds, s>>>(in, up, in32, rscale, w, bias, out, S, nbx, nby,   \
-                                                            nblocks);                                        \
+        NDL_KCF(ACT_, OUTK_, SRC_)<<<grid, block, lds, s>>>(in, up, w, bias, out, S, nbx, nby, nblocks);       \
     } while (0)
-    if (up || in32) {
-        // inference-only forms: BF16 out
-        if (outk != 0 || (S & 1)) { set_error("conv with a fused input: unsupported form"); return NDL_EINVAL; }
-        if (up) {
-            // skip additions feed the decoder convolutions (equal channel counts)
-            if constexpr (CIN == COUT) {
-                if (act) NDL_KCF_GO(1, 0, 1);
-                else NDL_KCF_GO(0, 0, 1);
-            } else {
-                set_error("conv with upsampled input: channel counts differ");
-                return NDL_EINVAL;
-            }
+    if (up) {
+        // skip additions feed the decoder convolutions (BF16 out, equal channel counts)
+        if (outk != 0 || (S & 1)) { set_error("conv with upsampled input: unsupported form"); return NDL_EINVAL; }
+        if constexpr (CIN == COUT) {
+            if (act) NDL_KCF_GO(1, 0, 1);
+            else NDL_KCF_GO(0, 0, 1);
         } else {
-            if constexpr (CIN == 8) {
-                if (act) NDL_KCF_GO(1, 0, 2);
-                else NDL_KCF_GO(0, 0, 2);
-            } else {
-                set_error("conv with an FP32 single-channel input: the input layer only");
-                return NDL_EINVAL;
-            }
+            set_error("conv with upsampled input: channel counts differ");
+            return NDL_EINVAL;
         }
     } else if (outk == 2) NDL_KCF_GO(0, 2, 0);
     else if (outk == 1) NDL_KCF_GO(0, 1, 0);
@@ -933,24 +1069,22 @@ static int conv_fwd_launch(const bf16_t* in, const bf16_t* up, const float* in32
 // LDS (two 8-wave blocks per CU), the middle ones 4-row patches of 8 planes,
 // the coarsest 4 planes so that the launch still spreads over the CUs.
 template <int CIN, int COUT>
-static int conv_fwd_t(const bf16_t* in, const bf16_t* up, const float* in32, const double* rscale, const bf16_t* w,
-                      const float* bias, void* out, int S, int act, int outk, hipStream_t s)
+static int conv_fwd_t(const bf16_t* in, const bf16_t* up, const bf16_t* w, const float* bias, void* out, int S,
+                      int act, int outk, hipStream_t s)
 {
     constexpr bool WR = (kpad(CIN) / 32) * (COUT / 16) <= 14;
-    if (S >= 128) return conv_fwd_launch<CIN, COUT, 16, 8, false>(in, up, in32, rscale, w, bias, out, S, act, outk, s);
-    if (S >= 64) return conv_fwd_launch<CIN, COUT, 8, 4, WR>(in, up, in32, rscale, w, bias, out, S, act, outk, s);
-    return conv_fwd_launch<CIN, COUT, 4, 4, WR>(in, up, in32, rscale, w, bias, out, S, act, outk, s);
+    if (S >= 128) return conv_fwd_launch<CIN, COUT, 16, 8, false>(in, up, w, bias, out, S, act, outk, s);
+    if (S >= 64) return conv_fwd_launch<CIN, COUT, 8, 4, WR>(in, up, w, bias, out, S, act, outk, s);
+    return conv_fwd_launch<CIN, COUT, 4, 4, WR>(in, up, w, bias, out, S, act, outk, s);
 }
 
-// y = conv(x); fused inputs (inference): up = the coarse tensor (side S/2,
-// same channels) whose nearest upsampling is added to x while staging, or
-// in32 = an FP32 single channel scaled by *rscale in place of x (input layer)
+// y = conv(x); up (inference): the coarse tensor (side S/2, same channels)
+// whose nearest upsampling is added to x while staging
 static int conv_fwd(int cin, int cout, const bf16_t* in, const bf16_t* w, const float* bias, void* out, int S, int act,
-                    int outk, hipStream_t s, const bf16_t* up = nullptr, const float* in32 = nullptr,
-                    const double* rscale = nullptr)
+                    int outk, hipStream_t s, const bf16_t* up = nullptr)
 {
 #define NDL_CF(A, B) \
-    if (cin == A && cout == B) return conv_fwd_t<A, B>(in, up, in32, rscale, w, bias, out, S, act, outk, s)
+    if (cin == A && cout == B) return conv_fwd_t<A, B>(in, up, w, bias, out, S, act, outk, s)
     NDL_CF(8, 16);
     NDL_CF(16, 16);
     NDL_CF(16, 32);
@@ -1095,11 +1229,16 @@ static int net_forward(Net& n, int S, hipStream_t s, bool linear = false, bool f
         int lv = level_of_layer(i);
         bool head = i == kNumLayers - 1;
         return conv_fwd(l.sp.cin, l.sp.cout, in ? in : layer_input(n, i), l.wbf, linear ? nullptr : l.b32,
-                        head ? (void*)n.head : (void*)n.a[i], Sl[lv], linear ? 0 : l.sp.act, head ? 2 : 0, s, up,
-                        i == 0 ? in32 : nullptr, rscale);
+                        head ? (void*)n.head : (void*)n.a[i], Sl[lv], linear ? 0 : l.sp.act, head ? 2 : 0, s, up);
     };
     auto vox = [&](int l) { return (int64_t)Sl[l] * Sl[l] * Sl[l]; };
-    NDL_TRY(conv(0));
+    if (in32) {
+        // linear mode, inference: the single-channel input layer
+        Layer& l0 = n.L[0];
+        NDL_TRY(conv_in1(in32, rscale, l0.wbf, linear ? nullptr : l0.b32, n.a[0], S, linear ? 0 : l0.sp.act, s));
+    } else {
+        NDL_TRY(conv(0));
+    }
     NDL_TRY(conv(1));
     k_pool<<<nb(vox(1) * 2), 256, 0, s>>>(n.a[1], n.p[1], Sl[0], 16);
     NDL_TRY(conv(2));
