@@ -157,11 +157,12 @@ def _read_layers(net):
     return layers
 
 
-@pytest.mark.parametrize("n", [16, 64])
+@pytest.mark.parametrize("n", [8, 16, 64])
 def test_linear_network_forward_matches_oracle(n):
-    """The whole preconditioner network in linear mode (the shipped weights) on a
-    16^3 and a 64^3 field (every patch shape below the full-resolution one, the
-    fused input staging and skip sums included) against the FP64 reference
+    """The whole preconditioner network in linear mode (the shipped weights) on an
+    8^3 (coarsest level 1^3), a 16^3 and a 64^3 field (every patch shape below
+    the full-resolution one, the single-channel input layer and the skip sums
+    formed while staging included) against the FP64 reference
     composed from the oracle's layers:
     residual scaled by D^-1/2 (D from the oracle's case (b) diagonal) and
     normalised to unit RMS, 13 convolutions without biases or activations,
