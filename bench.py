@@ -316,7 +316,7 @@ def bench_1d(steps=200):
                                                 norm=ndl.NDL_NORM_CONTINUOUS, prec=ndl.NDL_F64), keep=(dd, cc))
     out = torch.empty(n, dtype=torch.float64, device="cuda")
     secs, _ = timed_graph(lambda: ndl.ndl_apply(plan, u, out, 1), steps, 10)
-    return {"us_per_apply": secs / steps * 1e6, "note": "4096 nodes: launch-latency bound"}
+    return {"us_per_apply": secs / steps * 1e6, "note": "4096 nodes, graph replays: launch-latency bound"}
 
 
 def cpu_baseline(budget_s=12.0):
@@ -349,7 +349,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-rows", action="store_true", help="headline only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", default="", help="run one row only (profiling): cg64, pcg3d, net, pd, sweep, fast, f64")
+    ap.add_argument("--only", default="", help="run one row only (profiling): cg64, pcg3d, net, pd, sweep, fast, f64, 1d")
     ap.add_argument("--cg-iters", type=int, default=0, help="cap the solver iterations (profiling)")
     ap.add_argument("--variant", type=int, default=None,
                     help="fixed tile variant for the headline instead of the autotuner's (profiling runs)")
@@ -365,7 +365,7 @@ def main():
     if args.only:
         fn = {"cg64": lambda: bench_solve(max_iter=args.cg_iters or None),
               "pcg3d": lambda: bench_pcg_3d(max_iter=args.cg_iters or None),
-              "net": bench_net, "pd": bench_pd, "sweep": bench_sweep, "f64": lambda: bench_apply(ndl.NDL_F64, False, args.steps, args.warmup)["seconds"],
+              "net": bench_net, "pd": bench_pd, "1d": bench_1d, "sweep": bench_sweep, "f64": lambda: bench_apply(ndl.NDL_F64, False, args.steps, args.warmup)["seconds"],
               "fast": lambda: bench_apply(ndl.NDL_F32C, True, args.steps, args.warmup)["seconds"]}[args.only]
         print(json.dumps({"only": args.only, "result": fn()}, default=str), flush=True)
         return

@@ -212,7 +212,7 @@ __global__ __launch_bounds__(256) void k_direct_nd(const T* __restrict__ u, T* _
                                                    const int32_t* __restrict__ kk, const T* __restrict__ sc,
                                                    const T* __restrict__ invm2, const int4* __restrict__ pairs,
                                                    const T* __restrict__ pw, int npairs, ScaleArgs a, Box B,
-                                                   int64_t N, int64_t NPad)
+                                                   int64_t N, int64_t NPad, int split)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* tile = reinterpret_cast<T*>(smem_raw);
@@ -244,8 +244,12 @@ __global__ __launch_bounds__(256) void k_direct_nd(const T* __restrict__ u, T* _
     for (int c = 0; c < ncomp; c++) stage(tile + c * tot, ub + c * NPad, B, org);
     __syncthreads();
 
+    // `split` lanes (a power of two dividing 64) share one node: lane `sub`
+    // takes every split-th pair and the partial sums meet in a shuffle tree
     int npts = B.E[0] * B.E[1] * B.E[2];
-    for (int pi = threadIdx.x; pi < npts; pi += blockDim.x) {
+    const int sub = threadIdx.x & (split - 1);
+    const int pstep = blockDim.x / split;
+    for (int pi = threadIdx.x / split; pi < npts; pi += pstep) {
         int e2 = pi % B.E[2];
         int r = pi / B.E[2];
         int e1 = r % B.E[1];
@@ -260,7 +264,7 @@ __global__ __launch_bounds__(256) void k_direct_nd(const T* __restrict__ u, T* _
         T v0 = MODEL ? tile[tot + cidx] : T(0);
         T im2 = POLY && valid ? invm2[gi] : T(0);
         Acc<T> A0, A1;
-        for (int p = 0; p < npairs; p++) {
+        for (int p = sub, cnt = 0; p < npairs; p += split, cnt++) {
             int4 o;
             int off, qw;
             T w;
@@ -294,12 +298,17 @@ __global__ __launch_bounds__(256) void k_direct_nd(const T* __restrict__ u, T* _
                     A1.fma_(proj, z1);
                 }
             }
-            if ((p & 7) == 7) { A0.flush(); if (MODEL) A1.flush(); }
+            if ((cnt & 7) == 7) { A0.flush(); if (MODEL) A1.flush(); }
         }
-        if (valid) {
+        T v0s = A0.value(), v1s = MODEL ? A1.value() : T(0);
+        for (int o = split >> 1; o >= 1; o >>= 1) {
+            v0s += __shfl_xor(v0s, o, 64);
+            if (MODEL) v1s += __shfl_xor(v1s, o, 64);
+        }
+        if (valid && sub == 0) {
             T s = sc[gi];
-            ob[gi] = s * A0.value();
-            if (MODEL) ob[N + gi] = s * A1.value();
+            ob[gi] = s * v0s;
+            if (MODEL) ob[N + gi] = s * v1s;
         }
     }
 }
@@ -559,6 +568,14 @@ static int launch_direct_t(Plan& p, const void* u, void* Lu, int batch, hipStrea
 {
     int E[3];
     default_tile(p, E);
+    // 1D: a few nodes per block would leave most of the chip idle and each
+    // thread walking the whole half ball; small tiles with the pair loop split
+    // over 256/E lanes per node fill the waves instead
+    int split = 1;
+    if (p.dim == 1) {
+        if (p.tile_x <= 0) E[2] = 16;
+        if (E[2] <= 256 && 256 % E[2] == 0) split = std::min(64, 256 / E[2]);
+    }
     Box B = make_box(p.dim, p.n, p.R, p.J, E[0], E[1], E[2]);
     int nb = B.tiles[0] * B.tiles[1] * B.tiles[2];
     size_t lds = (size_t)B.L[0] * B.L[1] * B.L[2] * sizeof(T) * p.ncomp;
@@ -574,7 +591,7 @@ static int launch_direct_t(Plan& p, const void* u, void* Lu, int batch, hipStrea
 #define NDL_LAUNCH(M, PL)                                                                          \
     k_direct_nd<T, M, PL><<<grid, dim3(256), lds, s>>>(uu, oo, p.d_k, (const T*)p.d_scale,         \
                                                        (const T*)p.d_invm2, p.d_pairs,             \
-                                                       (const T*)p.d_pairw, p.npairs, a, B, p.N, p.NP)
+                                                       (const T*)p.d_pairw, p.npairs, a, B, p.N, p.NP, split)
     if (p.model == NDL_PERIDYNAMIC) {
         if (poly) NDL_LAUNCH(1, true); else NDL_LAUNCH(1, false);
     } else {

@@ -70,6 +70,20 @@ def test_1d_random(prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_1d_batched_ragged(prec):
+    """1D nodes share their pair loop among lanes; a ragged last tile and a batch."""
+    say(f"case 1d batched prec={prec}")
+    n, R, B = 77, 20, 3
+    delta, c, _ = rand_problem(1, n, R, 2.0, 20.0, seed=13)
+    g = np.random.default_rng(14)
+    u = g.standard_normal((B, n + 2 * R))
+    got, _ = gpu_apply(1, n, R, delta, c, u, prec, batch=B)
+    for b in range(B):
+        ref = oracle_apply(1, n, R, delta, c, u[b], prec)
+        assert rel_l2(got[b], ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_3d_nd(prec):
     say(f"case 3d nd prec={prec}")
     n, R = 21, 4
