@@ -330,7 +330,7 @@ __global__ __launch_bounds__(256) void k_direct_div(const T* __restrict__ u, T* 
                                                     const T* __restrict__ delta, const T* __restrict__ coef,
                                                     const int4* __restrict__ full, const double* __restrict__ fw,
                                                     int nfull, const double* __restrict__ invT, DivArgs a, Box B,
-                                                    int64_t N, int64_t NPad)
+                                                    int64_t N, int64_t NPad, int split)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* tu = reinterpret_cast<T*>(smem_raw);
@@ -347,8 +347,12 @@ __global__ __launch_bounds__(256) void k_direct_div(const T* __restrict__ u, T* 
         __syncthreads();
     }
     double nn = (double)a.n;
+    // `split` lanes share one node as in k_direct_nd; a node's lanes skip or
+    // run together, so the shuffle tree below always sees its whole group
     int npts = B.E[0] * B.E[1] * B.E[2];
-    for (int pi = threadIdx.x; pi < npts; pi += blockDim.x) {
+    const int sub = threadIdx.x & (split - 1);
+    const int pstep = blockDim.x / split;
+    for (int pi = threadIdx.x / split; pi < npts; pi += pstep) {
         int e2 = pi % B.E[2];
         int r = pi / B.E[2];
         int e1 = r % B.E[1];
@@ -362,7 +366,7 @@ __global__ __launch_bounds__(256) void k_direct_div(const T* __restrict__ u, T* 
         T u0 = DIAG ? T(0) : tu[cidx];
         Acc<T> A0;
         double dsum = 0.0;
-        for (int p = 0; p < nfull; p++) {
+        for (int p = sub, cnt = 0; p < nfull; p += split, cnt++) {
             int4 o = full[p];
             if (o.w > a.kmax) break;
             int y0 = x0 + o.x, y1 = x1 + o.y, y2 = x2 + o.z;
@@ -391,11 +395,17 @@ __global__ __launch_bounds__(256) void k_direct_div(const T* __restrict__ u, T* 
             } else {
                 int off = o.x * B.ls0 + o.y * B.ls1 + o.z;
                 A0.fma_((T)w, tu[cidx + off] - u0);
-                if ((p & 7) == 7) A0.flush();
+                if ((cnt & 7) == 7) A0.flush();
             }
         }
+        T v = DIAG ? T(0) : A0.value();
+        for (int o = split >> 1; o >= 1; o >>= 1) {
+            if (DIAG) dsum += __shfl_xor(dsum, o, 64);
+            else v += __shfl_xor(v, o, 64);
+        }
+        if (sub != 0) continue;
         if (DIAG) ob[gi] = (T)dsum;
-        else ob[gi] = A0.value();
+        else ob[gi] = v;
     }
 }
 
@@ -563,19 +573,22 @@ static void default_tile(const Plan& p, int* E)
     else { E[0] = 4; E[1] = 8; E[2] = 32; }
 }
 
+// 1D: a few nodes per block would leave most of the chip idle and each thread
+// walking the whole ball; small tiles with the pair loop split over 256/E
+// lanes per node (a power of two dividing 64) fill the waves instead.
+static int tile_and_split(const Plan& p, int* E)
+{
+    default_tile(p, E);
+    if (p.dim != 1) return 1;
+    if (p.tile_x <= 0) E[2] = 16;
+    return E[2] <= 256 && 256 % E[2] == 0 ? std::min(64, 256 / E[2]) : 1;
+}
+
 template <typename T>
 static int launch_direct_t(Plan& p, const void* u, void* Lu, int batch, hipStream_t s)
 {
     int E[3];
-    default_tile(p, E);
-    // 1D: a few nodes per block would leave most of the chip idle and each
-    // thread walking the whole half ball; small tiles with the pair loop split
-    // over 256/E lanes per node fill the waves instead
-    int split = 1;
-    if (p.dim == 1) {
-        if (p.tile_x <= 0) E[2] = 16;
-        if (E[2] <= 256 && 256 % E[2] == 0) split = std::min(64, 256 / E[2]);
-    }
+    const int split = tile_and_split(p, E);
     Box B = make_box(p.dim, p.n, p.R, p.J, E[0], E[1], E[2]);
     int nb = B.tiles[0] * B.tiles[1] * B.tiles[2];
     size_t lds = (size_t)B.L[0] * B.L[1] * B.L[2] * sizeof(T) * p.ncomp;
@@ -614,7 +627,7 @@ template <typename T, bool DIAG>
 static int launch_div_t(Plan& p, const void* u, void* Lu, int batch, hipStream_t s)
 {
     int E[3];
-    default_tile(p, E);
+    const int split = tile_and_split(p, E);
     Box B = make_box(p.dim, p.n, p.R, p.J, E[0], E[1], E[2]);
     int nb = B.tiles[0] * B.tiles[1] * B.tiles[2];
     size_t lds = DIAG ? 16 : (size_t)B.L[0] * B.L[1] * B.L[2] * sizeof(T);
@@ -632,7 +645,7 @@ static int launch_div_t(Plan& p, const void* u, void* Lu, int batch, hipStream_t
     a.kmax = (int)p.kmax;
     k_direct_div<T, DIAG><<<dim3((unsigned)nb, (unsigned)batch), dim3(256), lds, s>>>(
         static_cast<const T*>(u), static_cast<T*>(Lu), (const T*)p.prob.delta, (const T*)p.prob.coef, p.d_full,
-        (const double*)p.d_fullw, p.nfull, p.d_invT, a, B, p.N, p.NP);
+        (const double*)p.d_fullw, p.nfull, p.d_invT, a, B, p.N, p.NP, split);
     NDL_HIP(hipGetLastError());
     return NDL_OK;
 }

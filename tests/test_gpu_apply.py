@@ -187,6 +187,20 @@ def test_div(prec, dim, n, R):
     assert rel_l2(got, ref) <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_div_1d_batched_ragged(prec):
+    """1D case (b): nodes share their pair loop among lanes; ragged tile, batch."""
+    say(f"case div 1d batched prec={prec}")
+    n, R, B = 333, 12, 2
+    delta, c, _ = rand_problem(1, n, R, 2.0, 12.0, seed=21)
+    g = np.random.default_rng(22)
+    u = g.standard_normal((B, n + 2 * R))
+    got, _ = gpu_apply(1, n, R, delta, c, u, prec, form=ndl.NDL_DIV, batch=B)
+    for b in range(B):
+        ref = oracle_apply(1, n, R, delta, c, u[b], prec, form=ndl.NDL_DIV)
+        assert rel_l2(got[b], ref) <= TOL[prec]
+
+
 def test_div_continuous_and_const():
     n, R = 40, 6
     delta, c, u = rand_problem(2, n, R, 2.0, 6.0, seed=17)
