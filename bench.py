@@ -316,7 +316,12 @@ def bench_1d(steps=200):
                                                 norm=ndl.NDL_NORM_CONTINUOUS, prec=ndl.NDL_F64), keep=(dd, cc))
     out = torch.empty(n, dtype=torch.float64, device="cuda")
     secs, _ = timed_graph(lambda: ndl.ndl_apply(plan, u, out, 1), steps, 10)
-    return {"us_per_apply": secs / steps * 1e6, "note": "4096 nodes, graph replays: launch-latency bound"}
+    # the same field through case (b) (per-pair cutoff and coefficient)
+    plan_b = ndl.ndl_plan_create(ndl.make_problem(1, n, R, dd, cc, form=ndl.NDL_DIV, kernel=ndl.NDL_G_CONST,
+                                                  norm=ndl.NDL_NORM_CONTINUOUS, prec=ndl.NDL_F64), keep=(dd, cc))
+    secs_b, _ = timed_graph(lambda: ndl.ndl_apply(plan_b, u, out, 1), steps, 10)
+    return {"us_per_apply": secs / steps * 1e6, "case_b_us_per_apply": secs_b / steps * 1e6,
+            "note": "4096 nodes, graph replays: launch-latency bound"}
 
 
 def cpu_baseline(budget_s=12.0):
