@@ -107,7 +107,6 @@ struct Plan {
 int plan_fields(Plan& p, hipStream_t s);                   // k_i, scales, tables
 int launch_direct(Plan& p, const void* u, void* Lu, int batch, hipStream_t s);
 int launch_div(Plan& p, const void* u, void* Lu, int batch, hipStream_t s);
-int launch_div_diag(Plan& p, void* diag, hipStream_t s);
 int fast_prepare(Plan& p, hipStream_t s);
 int launch_fast(Plan& p, const void* u, void* Lu, int batch, hipStream_t s);
 int fast_decomp_host(Plan& p, const int64_t* node, int32_t* out, int cap, int* count);

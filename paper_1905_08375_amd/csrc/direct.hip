@@ -316,8 +316,7 @@ __global__ __launch_bounds__(256) void k_direct_nd(const T* __restrict__ u, T* _
 // ------------------------------------------------------------------ case (b)
 // Symmetric form: each neighbour j uses delta_ij = (delta_i+delta_j)/2 and
 // C_ij = (c_i+c_j)/2; k_ij is evaluated in FP64 exactly as in case (a); a
-// partner in the collar takes (delta_i, c_i).  DIAG computes the diagonal of
-// -L instead (the Jacobi preconditioner).
+// partner in the collar takes (delta_i, c_i).
 struct DivArgs {
     int64_t n;
     int norm, dim;
@@ -325,7 +324,7 @@ struct DivArgs {
     int kmax;
 };
 
-template <typename T, bool DIAG>
+template <typename T>
 __global__ __launch_bounds__(256) void k_direct_div(const T* __restrict__ u, T* __restrict__ out,
                                                     const T* __restrict__ delta, const T* __restrict__ coef,
                                                     const int4* __restrict__ full, const double* __restrict__ fw,
@@ -340,12 +339,10 @@ __global__ __launch_bounds__(256) void k_direct_div(const T* __restrict__ u, T* 
     int t1 = (t / B.tiles[2]) % B.tiles[1];
     int t0i = t / (B.tiles[2] * B.tiles[1]);
     int org[3] = {t0i * B.E[0], t1 * B.E[1], t2 * B.E[2]};
-    const T* ub = DIAG ? u : u + (int64_t)blockIdx.y * NPad;
+    const T* ub = u + (int64_t)blockIdx.y * NPad;
     T* ob = out + (int64_t)blockIdx.y * N;
-    if (!DIAG) {
-        stage(tu, ub, B, org);
-        __syncthreads();
-    }
+    stage(tu, ub, B, org);
+    __syncthreads();
     double nn = (double)a.n;
     // `split` lanes share one node as in k_direct_nd; a node's lanes skip or
     // run together, so the shuffle tree below always sees its whole group
@@ -363,9 +360,8 @@ __global__ __launch_bounds__(256) void k_direct_div(const T* __restrict__ u, T* 
         int64_t gi = ((int64_t)x0 * B.ext[1] + x1) * B.ext[2] + x2;
         int cidx = (e0 + B.halo[0]) * B.ls0 + (e1 + B.halo[1]) * B.ls1 + (e2 + B.halo[2]);
         double di = (double)delta[gi], ci = (double)coef[gi];
-        T u0 = DIAG ? T(0) : tu[cidx];
+        T u0 = tu[cidx];
         Acc<T> A0;
-        double dsum = 0.0;
         for (int p = sub, cnt = 0; p < nfull; p += split, cnt++) {
             int4 o = full[p];
             if (o.w > a.kmax) break;
@@ -390,22 +386,13 @@ __global__ __launch_bounds__(256) void k_direct_div(const T* __restrict__ u, T* 
                 double base = C * pow(am, -a.expo) * a.hd / dd2 * fw[p];
                 w = a.norm == NDL_NORM_CONTINUOUS ? base * a.m2 / a.contc : base;
             }
-            if (DIAG) {
-                dsum += w;
-            } else {
-                int off = o.x * B.ls0 + o.y * B.ls1 + o.z;
-                A0.fma_((T)w, tu[cidx + off] - u0);
-                if ((cnt & 7) == 7) A0.flush();
-            }
+            int off = o.x * B.ls0 + o.y * B.ls1 + o.z;
+            A0.fma_((T)w, tu[cidx + off] - u0);
+            if ((cnt & 7) == 7) A0.flush();
         }
-        T v = DIAG ? T(0) : A0.value();
-        for (int o = split >> 1; o >= 1; o >>= 1) {
-            if (DIAG) dsum += __shfl_xor(dsum, o, 64);
-            else v += __shfl_xor(v, o, 64);
-        }
-        if (sub != 0) continue;
-        if (DIAG) ob[gi] = (T)dsum;
-        else ob[gi] = v;
+        T v = A0.value();
+        for (int o = split >> 1; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (sub == 0) ob[gi] = v;
     }
 }
 
@@ -623,15 +610,15 @@ int launch_direct(Plan& p, const void* u, void* Lu, int batch, hipStream_t s)
                              : launch_direct_t<float>(p, u, Lu, batch, s);
 }
 
-template <typename T, bool DIAG>
+template <typename T>
 static int launch_div_t(Plan& p, const void* u, void* Lu, int batch, hipStream_t s)
 {
     int E[3];
     const int split = tile_and_split(p, E);
     Box B = make_box(p.dim, p.n, p.R, p.J, E[0], E[1], E[2]);
     int nb = B.tiles[0] * B.tiles[1] * B.tiles[2];
-    size_t lds = DIAG ? 16 : (size_t)B.L[0] * B.L[1] * B.L[2] * sizeof(T);
-    NDL_TRY(lds_check((const void*)k_direct_div<T, DIAG>, lds));
+    size_t lds = (size_t)B.L[0] * B.L[1] * B.L[2] * sizeof(T);
+    NDL_TRY(lds_check((const void*)k_direct_div<T>, lds));
     DivArgs a{};
     a.n = p.n;
     a.norm = p.norm;
@@ -643,7 +630,7 @@ static int launch_div_t(Plan& p, const void* u, void* Lu, int batch, hipStream_t
     for (int q = 0; q < p.dim; q++) hd /= (double)p.n;
     a.hd = hd;
     a.kmax = (int)p.kmax;
-    k_direct_div<T, DIAG><<<dim3((unsigned)nb, (unsigned)batch), dim3(256), lds, s>>>(
+    k_direct_div<T><<<dim3((unsigned)nb, (unsigned)batch), dim3(256), lds, s>>>(
         static_cast<const T*>(u), static_cast<T*>(Lu), (const T*)p.prob.delta, (const T*)p.prob.coef, p.d_full,
         (const double*)p.d_fullw, p.nfull, p.d_invT, a, B, p.N, p.NP, split);
     NDL_HIP(hipGetLastError());
@@ -652,14 +639,8 @@ static int launch_div_t(Plan& p, const void* u, void* Lu, int batch, hipStream_t
 
 int launch_div(Plan& p, const void* u, void* Lu, int batch, hipStream_t s)
 {
-    return p.prec == NDL_F64 ? launch_div_t<double, false>(p, u, Lu, batch, s)
-                             : launch_div_t<float, false>(p, u, Lu, batch, s);
-}
-
-int launch_div_diag(Plan& p, void* diag, hipStream_t s)
-{
-    return p.prec == NDL_F64 ? launch_div_t<double, true>(p, nullptr, diag, 1, s)
-                             : launch_div_t<float, true>(p, nullptr, diag, 1, s);
+    return p.prec == NDL_F64 ? launch_div_t<double>(p, u, Lu, batch, s)
+                             : launch_div_t<float>(p, u, Lu, batch, s);
 }
 
 }  // namespace ndl
