@@ -223,6 +223,20 @@ def test_single_node_and_zero_horizon():
         assert np.allclose(got, ref, rtol=1e-12, atol=1e-300)
 
 
+@pytest.mark.parametrize("form", [ndl.NDL_ND, ndl.NDL_DIV])
+def test_1d_grids_smaller_than_a_tile(form):
+    """1D grids of 1, 3 and 17 nodes (below one 16-node tile, and one past it),
+    partners reaching into the collar on both sides."""
+    for n, m in [(1, 0.5), (1, 2.5), (3, 2.0), (17, 4.0)]:
+        R = 4
+        delta, c, _ = rand_problem(1, n, R, 0.5 * m, m, seed=30 + n)
+        u = np.random.default_rng(31 + n).standard_normal(n + 2 * R)
+        kw = dict(form=form, kernel=ndl.NDL_G_CONST, norm=ndl.NDL_NORM_NONE)
+        got, _ = gpu_apply(1, n, R, delta, c, u, ndl.NDL_F64, **kw)
+        ref = oracle_apply(1, n, R, delta, c, u, ndl.NDL_F64, **kw)
+        assert np.allclose(got, ref, rtol=1e-12, atol=1e-300), (n, m)
+
+
 def test_collar_too_small_is_an_error():
     import torch
     n = 16
