@@ -386,6 +386,11 @@ __global__ __launch_bounds__((DivShape<T, DIM>::THREADS)) void k_div2_items(
         };
         const int p_in = first_at_least(tmin);
         const int p_end = first_at_least(tmax);
+        // per-lane bases of the three staged fields: a partner read is the
+        // base plus the uniform offset (one add per field and offset)
+        const MT* tmb = tm + base;
+        const T* tcb = tcc + base;
+        const T* tub = tu + base;
         // one range of offsets; the table entries are uniform (scalar loads)
         auto run = [&](int pb, int pe, auto edge_c, auto mask_c) {
             constexpr bool EDGE = decltype(edge_c)::value;
@@ -403,9 +408,9 @@ __global__ __launch_bounds__((DivShape<T, DIM>::THREADS)) void k_div2_items(
                 fwq = fw[q + 1];
 #pragma unroll
                 for (int j = 0; j < PY; ++j) {
-                    const int jj = base + j * PITCH + off;
-                    double mj = (double)tm[jj];
-                    T ccj = tcc[jj];
+                    const int jo = j * PITCH + off;
+                    double mj = (double)tmb[jo];
+                    T ccj = tcb[jo];
                     if (EDGE) {
                         const bool out = mj < 0.0;
                         mj = out ? mi[j] : mj;
@@ -420,7 +425,7 @@ __global__ __launch_bounds__((DivShape<T, DIM>::THREADS)) void k_div2_items(
                     if (DIAG) {
                         dsum[j] += (double)w;
                     } else {
-                        acc[j].fma_(w, tu[jj] - ui[j]);
+                        acc[j].fma_(w, tub[jo] - ui[j]);
                     }
                 }
                 if (!DIAG && F32 && (q & 7) == 7) {
