@@ -402,7 +402,7 @@ __global__ __launch_bounds__((DivShape<T, DIM>::THREADS)) void k_div2_items(
             double fwq = fw[pb];
             for (int q = pb; q < pe; ++q) {
                 const int off = (DIM == 3 ? o.x * PLANE : 0) + o.y * PITCH + o.z;
-                const double qd = (double)o.w;
+                const int qi = o.w;  // |z|^2 >= 1: the table holds no zero offset
                 const T fq = (T)fwq;
                 o = full[q + 1];
                 fwq = fw[q + 1];
@@ -419,9 +419,11 @@ __global__ __launch_bounds__((DivShape<T, DIM>::THREADS)) void k_div2_items(
                     const double a = SC ? mi[j] + mj : (mi[j] + mj) * nh;
                     const double t = a * a;
                     int kij = (int)ceil(t) - 1;
+                    // |z|^2 < t  <=>  |z|^2 <= ceil(t) - 1 = k_ij for an integer |z|^2
+                    const bool inside = qi <= kij;
                     if (MASK) kij = max(kij, 0);
                     T w = (cci[j] + ccj) * tinv_s[kij] * fq;
-                    if (MASK) w = qd < t ? w : T(0);
+                    if (MASK) w = inside ? w : T(0);
                     if (DIAG) {
                         dsum[j] += (double)w;
                     } else {
