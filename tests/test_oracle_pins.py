@@ -140,7 +140,7 @@ def test_nd_not_symmetric():
 
 
 # --------------------------------------------------------------- P4
-@pytest.mark.parametrize("kname,kw", KERNELS[:3])
+@pytest.mark.parametrize("kname,kw", KERNELS)
 def test_constant_coefficients_are_a_convolution(kname, kw):
     """Constant delta and C: L u = w * u - (sum w) u, a zero-padded linear convolution
     computed with scipy's FFT convolution (the translation-invariant case)."""
@@ -161,6 +161,11 @@ def test_constant_coefficients_are_a_convolution(kname, kw):
         prof = np.ones_like(r)
     elif kname == "inv_r":
         prof = 1 / r
+    elif kname == "poly":
+        # even polynomial sum_j a_j r^(2j) (the p^{2K} of Section 3), Horner in r^2
+        prof = np.zeros_like(r)
+        for a in reversed(kw["poly"]):
+            prof = prof * r * r + a
     else:
         prof = r ** (-(2 + 2 * kw["s"]))
     prof = np.where(inside, prof, 0.0)
@@ -171,6 +176,59 @@ def test_constant_coefficients_are_a_convolution(kname, kw):
     ref = conv - w.sum() * u
     got = O.apply(P, delta, c, F.pad(u, R))
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+# --------------------------------------------------------------- case (b) normalisation
+@pytest.mark.parametrize("dim", [1, 2, 3])
+@pytest.mark.parametrize("kname,kw", KERNELS[:4])
+def test_div_with_constant_fields_is_case_a(dim, kname, kw):
+    """Case (b) with constant delta and C: delta_ij = delta and C_ij = C, so the
+    symmetric operator is case (a) itself and reproduces the local limit, L |x|^2 =
+    2d c exactly (Section 2, cases (a) and (b)).  The case (b) side takes its
+    normalisation per cutoff from moment sums memoised by k, the case (a) side
+    enumerates the ball per node: two independent routes to A(k, m)."""
+    n = {1: 40, 2: 13, 3: 6}[dim]
+    R = 5
+    m = {1: 4.7, 2: 3.3, 3: 2.6}[dim]
+    delta = np.full((n,) * dim, m / n)
+    c = np.full((n,) * dim, 1.37)
+    g = np.random.default_rng(40 + dim)
+    u = g.standard_normal((n + 2 * R,) * dim)
+    Pa = O.Problem(dim=dim, n=n, R=R, form="nd", kernel=kname, **kw)
+    Pb = O.Problem(dim=dim, n=n, R=R, form="div", kernel=kname, **kw)
+    La, Lb = O.apply(Pa, delta, c, u), O.apply(Pb, delta, c, u)
+    assert np.abs(La - Lb).max() <= 1e-13 * np.abs(La).max()
+    X = F.padded_coords(n, dim, R)
+    r2 = sum(x * x for x in X)
+    assert np.allclose(O.apply(Pb, delta, c, r2), 2 * dim * 1.37, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("dim,n", [(1, 30), (2, 8), (3, 5)])
+@pytest.mark.parametrize("kname,kw", [("frac", {"s": 0.5}), ("inv_r", {}), ("const", {})])
+def test_div_pair_weight_is_case_a_at_the_mean_horizon(dim, n, kname, kw):
+    """Every entry of the assembled case (b) matrix, A_ij for j != i, is the case
+    (a) entry of the constant-field problem with delta = (delta_i + delta_j)/2 and
+    C = (c_i + c_j)/2 (Section 2, case (b) with the symmetric C and delta): the
+    pair weight is the full normalised kernel evaluated at the pair's mean
+    horizon, including its cutoff k_ij."""
+    R = 4
+    g = np.random.default_rng(50 + dim)
+    delta = g.uniform(1.3, 4.0, (n,) * dim) / n
+    c = np.exp(g.normal(0.0, 0.5, (n,) * dim))
+    Pb = O.Problem(dim=dim, n=n, R=R, form="div", kernel=kname, **kw)
+    A = assemble(Pb, delta, c)
+    N = n ** dim
+    Pa = O.Problem(dim=dim, n=n, R=R, form="nd", kernel=kname, **kw)
+    for i in g.choice(N, size=4, replace=False):
+        row = A[i]
+        js = [j for j in range(N) if j != i]
+        for j in g.choice(js, size=min(8, len(js)), replace=False):
+            dm = 0.5 * (delta.flat[i] + delta.flat[j])
+            cm = 0.5 * (c.flat[i] + c.flat[j])
+            e = np.zeros((n,) * dim)
+            e.flat[j] = 1.0
+            ref = O.apply(Pa, np.full((n,) * dim, dm), np.full((n,) * dim, cm), F.pad(e, R)).flat[i]
+            assert abs(row[j] - ref) <= 1e-13 * max(abs(ref), abs(A[i, i])), (i, j, row[j], ref)
 
 
 # --------------------------------------------------------------- P5
