@@ -209,6 +209,15 @@ int ndl_net_train_step_energy(ndl_net net, ndl_plan plan, int batch, const float
  * ndl_cg_solve(precond = 1). */
 int ndl_precond_apply(ndl_net net, ndl_plan plan, const void* r, void* z, void* stream);
 
+/* Test hook: copy one FP32 tensor of network layer `layer` (0..12, in the
+ * order input layer, encoder, bottom, decoder, output layer) to the host
+ * buffer `out` of `count` values, which must equal the tensor's size.
+ * which: 0 weights [cout][KP] (KP = 27 cin rounded up to 32, k = tap cin + c),
+ * 1 biases [cout], 2 / 3 their gradients from the last training step,
+ * 4 / 5 Adam's first and second moments of the weights, 6 / 7 those of the
+ * biases.  Synchronises the device. */
+int ndl_net_layer_tensor(ndl_net net, int layer, int which, float* out, int64_t count);
+
 /* Test hook: one 3x3x3 convolution layer of the network (zero padding) with
  * the network's kernels.  x [S^3][cin] BF16 bit patterns (NDHWC), w
  * [cout][K] FP32 with K = 27 cin rounded up to 32 and k = tap cin + c,

@@ -1728,6 +1728,27 @@ int ndl_net_train_step_energy(ndl_net net, ndl_plan plan, int batch, const float
     return std::isfinite(h) ? NDL_OK : NDL_EBREAKDOWN;
 }
 
+// Test hook: copy one of a layer's FP32 tensors to host memory.
+int ndl_net_layer_tensor(ndl_net net, int layer, int which, float* out, int64_t count)
+{
+    if (!net || !out || layer < 0 || layer >= kNumLayers || which < 0 || which > 7) {
+        set_error("ndl_net_layer_tensor: bad argument");
+        return NDL_EINVAL;
+    }
+    Layer& l = reinterpret_cast<NetState*>(net)->net.L[layer];
+    const float* src[8] = {l.w32, l.b32, l.gw, l.gb, l.mw, l.vw, l.mb, l.vb};
+    const bool per_channel = which == 1 || which == 3 || which == 6 || which == 7;
+    const int64_t size = per_channel ? (int64_t)l.sp.cout : (int64_t)l.nw;
+    if (count != size) {
+        set_error("ndl_net_layer_tensor: layer %d tensor %d holds %lld values, not %lld", layer, which,
+                  (long long)size, (long long)count);
+        return NDL_EINVAL;
+    }
+    NDL_HIP(hipDeviceSynchronize());
+    NDL_HIP(hipMemcpy(out, src[which], (size_t)size * sizeof(float), hipMemcpyDeviceToHost));
+    return NDL_OK;
+}
+
 int ndl_precond_apply(ndl_net net, ndl_plan plan, const void* r, void* z, void* stream)
 {
     if (!net || !plan || !r || !z) { set_error("null argument"); return NDL_EINVAL; }

@@ -364,10 +364,11 @@ __global__ __launch_bounds__((DivShape<T, DIM>::THREADS)) void k_div2_items(
         double dsum[PY];
 #pragma unroll
         for (int j = 0; j < PY; ++j) {
-            // nodes past the grid edge (ragged tiles) compute with m = c = 0,
-            // which keeps every k_ij within the table; they are not stored
+            // nodes past the grid edge (ragged tiles) compute with c = 0 and the
+            // tile's largest horizon, so that every pair they form has m_ij > 0
+            // and 0 <= k_ij <= k_max (within the table); they are not stored
             valid[j] = x < n && y0 + wy + j < n && z0 + wz < nz;
-            mi[j] = valid[j] ? (double)tm[base + j * PITCH] : 0.0;
+            mi[j] = valid[j] ? (double)tm[base + j * PITCH] : (SC ? mmax : mmax / nh);
             cci[j] = valid[j] ? tcc[base + j * PITCH] : T(0);
             ui[j] = tu[base + j * PITCH];
             dsum[j] = 0.0;
@@ -421,7 +422,6 @@ __global__ __launch_bounds__((DivShape<T, DIM>::THREADS)) void k_div2_items(
                     int kij = (int)ceil(t) - 1;
                     // |z|^2 < t  <=>  |z|^2 <= ceil(t) - 1 = k_ij for an integer |z|^2
                     const bool inside = qi <= kij;
-                    if (MASK) kij = max(kij, 0);
                     T w = (cci[j] + ccj) * tinv_s[kij] * fq;
                     if (MASK) w = inside ? w : T(0);
                     if (DIAG) {

@@ -27,7 +27,7 @@ EXPORTS = [
     "ndl_fast_decomposition", "ndl_decompose_node", "ndl_cg_solve", "ndl_net_create", "ndl_net_destroy", "ndl_net_set_linear",
     "ndl_net_save", "ndl_net_load", "ndl_net_num_params", "ndl_net_train_step", "ndl_precond_apply",
     "ndl_autotune", "ndl_last_error", "ndl_version", "ndl_plan_set_variant", "ndl_plan_num_variants",
-    "ndl_net_conv_test", "ndl_net_train_step_energy",
+    "ndl_net_conv_test", "ndl_net_train_step_energy", "ndl_net_layer_tensor",
 ]
 
 
@@ -98,6 +98,7 @@ def lib():
             "ndl_plan_num_variants": [vp, C.POINTER(C.c_int)],
             "ndl_net_train_step_energy": [vp, vp, C.c_int, vp, vp, C.c_float, C.POINTER(C.c_float), vp],
             "ndl_net_conv_test": [C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp, vp, vp],
+            "ndl_net_layer_tensor": [vp, C.c_int, C.c_int, C.POINTER(C.c_float), i64],
         }
         for name, args in sig.items():
             if hasattr(L, name):
@@ -314,3 +315,23 @@ def ndl_net_train_step_energy(net: Net, plan: Plan, r, e, lr: float, stream=None
     _check(lib().ndl_net_train_step_energy(net.handle, plan.handle, int(r.shape[0]), _ptr(r), _ptr(e), C.c_float(lr),
                                            C.byref(loss), _stream(stream)), "ndl_net_train_step_energy")
     return loss.value
+
+
+# which tensor ndl_net_layer_tensor reads
+NET_W, NET_B, NET_GW, NET_GB, NET_MW, NET_VW, NET_MB, NET_VB = range(8)
+_NET_COUT = (16, 16, 16, 16, 32, 32, 32, 32, 32, 16, 16, 16, 16)
+_NET_CIN = (8, 16, 16, 16, 16, 32, 32, 32, 32, 32, 16, 16, 16)
+
+
+def ndl_net_layer_tensor(net: Net, layer: int, which: int):
+    """A layer's FP32 tensor as a numpy array: [cout][KP] for weights and
+    their gradient and moments, [cout] for biases and theirs."""
+    import numpy as np
+    cout = _NET_COUT[layer]
+    kp = ((27 * _NET_CIN[layer] + 31) // 32) * 32
+    shape = (cout,) if which in (NET_B, NET_GB, NET_MB, NET_VB) else (cout, kp)
+    out = np.zeros(shape, dtype=np.float32)
+    _check(lib().ndl_net_layer_tensor(net.handle, int(layer), int(which),
+                                      out.ctypes.data_as(C.POINTER(C.c_float)), int(out.size)),
+           "ndl_net_layer_tensor")
+    return out

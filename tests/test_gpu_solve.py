@@ -244,3 +244,33 @@ def test_operator_cache_survives_plan_reuse():
         z = apply_fresh()
         assert torch.isfinite(z).all()
         assert torch.equal(z, ref), m
+
+
+def test_batched_cg_on_the_workload_size_mix():
+    """The first 16 instances of the 64-instance workload (sizes drawn from
+    256^2..1024^2, m in [2, 8], lognormal c, FP32 compensated inner apply)
+    in one call: the persistent item loop runs over far more tiles than the
+    grid holds, problems of every size share the launch, and each instance's
+    FP64 residual is recomputed over every node by the oracle."""
+    import torch
+    sizes = F.solve_sizes(64)[:16]
+    say(f"case cg workload mix sizes={sizes}")
+    assert len(set(sizes)) >= 4
+    R = 8
+    plans, bs, xs, ws = [], [], [], []
+    for i, n in enumerate(sizes):
+        w = F.solve_instance_2d(n, i)
+        d_d, d_c = dev(w["delta"], ndl.NDL_F32C), dev(w["coef"], ndl.NDL_F32C)
+        plans.append(ndl.ndl_plan_create(ndl.make_problem(2, n, R, d_d, d_c, form=ndl.NDL_DIV, prec=ndl.NDL_F32C),
+                                         keep=(d_d, d_c)))
+        bs.append(torch.from_numpy(w["b"]).cuda())
+        xs.append(torch.zeros((n, n), dtype=torch.float64, device="cuda"))
+        ws.append(w)
+    rc, reps = ndl.ndl_cg_solve(plans, bs, xs, rtol=1e-8)
+    torch.cuda.synchronize()
+    assert rc == ndl.NDL_OK, ndl.ndl_last_error()
+    for i, (n, w, rep, x) in enumerate(zip(sizes, ws, reps, xs)):
+        rr, _, _ = oracle_relres(n, w["delta"], w["coef"], w["b"], x.cpu().numpy(), ndl.NDL_F32C, R=R)
+        say(f"  inst {i} n={n} iters={rep.iters} outer={rep.outer} gpu_res={rep.rel_res_fp64:.2e} oracle_res={rr:.2e}")
+        assert rep.converged == 1
+        assert rr <= 1.05e-8
