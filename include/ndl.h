@@ -93,8 +93,9 @@ typedef struct ndl_plan_s* ndl_plan;
 /* Plan: validates the problem, computes per node the integer cutoff k_i and
  * the scale of the operator from (delta, coef) in FP64, checks the collar, and
  * picks the kernel variant (the autotuner's cached tile, see
- * ndl_autotune).  With want_fast != 0 it also prepares the workspace of the
- * hierarchical evaluation (Section 3: the dyadic tree of panels; the per-node
+ * ndl_autotune).  With want_fast != 0 it also prepares the hierarchical
+ * evaluation (want_fast = 1 with its pyramid workspace; 2 without it, for
+ * ndl_apply_fast_noalloc) (Section 3: the dyadic tree of panels; the per-node
  * decomposition of Step 1 is evaluated in closed form per panel row, so
  * nothing per node is stored).  This is the amortised set-up that the
  * paper's timings exclude. */
@@ -128,6 +129,20 @@ int ndl_apply(ndl_plan plan, const void* u, void* Lu, int batch, void* stream);
  * directly in the same pass.  Same inputs and result as ndl_apply up to
  * rounding.  Needs a plan made with want_fast != 0; case (a), diffusion. */
 int ndl_apply_fast(ndl_plan plan, const void* u, void* Lu, int batch, void* stream);
+
+/* ndl_apply_fast for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and result, with the pyramid of partial sums in a static
+ * device workspace of 64 MiB that the library holds on each GPU it runs on
+ * until the process ends, instead of the plan's own buffer.  The call itself
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine);
+ * the plan may be created with want_fast = 2, which skips the plan's pyramid
+ * buffer.  Returns NDL_EINVAL when the plan's pyramid needs more than the
+ * workspace holds (about n^dim / (2^dim - 1) doubles).  Every call on one GPU
+ * shares that GPU's workspace and overwrites it before reading it, so calls
+ * that overlap on one GPU (different streams, or threads without ordering)
+ * race; calls ordered on one stream do not. */
+int ndl_apply_fast_noalloc(ndl_plan plan, const void* u, void* Lu, int batch, void* stream);
 
 /* Step 1 as used by ndl_apply_fast, for one node (test hook): writes up to cap
  * panels as (s, j_1..j_dim) int32 records, s = log2 of the panel side in

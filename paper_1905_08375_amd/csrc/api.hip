@@ -115,7 +115,7 @@ int ndl_plan_create(const ndl_problem* prob, int want_fast, ndl_plan* out, void*
             set_error("the hierarchical path is implemented for case (a) diffusion");
             rc = NDL_EUNSUPPORTED;
         } else {
-            rc = fast_prepare(*p, s);
+            rc = fast_prepare(*p, s, want_fast != 2);
         }
     }
     if (rc != NDL_OK) { free_plan(p); return rc; }
@@ -168,8 +168,29 @@ int ndl_apply_fast(ndl_plan plan, const void* u, void* Lu, int batch, void* stre
     if (!plan || !u || !Lu || batch < 0) { set_error("ndl_apply_fast: null argument"); return NDL_EINVAL; }
     Plan* p = reinterpret_cast<Plan*>(plan);
     if (!p->fast) { set_error("plan was created without want_fast"); return NDL_EINVAL; }
+    if (!p->d_pyr) {
+        set_error("plan was created without its pyramid workspace (want_fast = 2): use ndl_apply_fast_noalloc");
+        return NDL_EINVAL;
+    }
     if (batch == 0) return NDL_OK;
     return launch_fast(*p, u, Lu, batch, (hipStream_t)stream);
+}
+
+int ndl_apply_fast_noalloc(ndl_plan plan, const void* u, void* Lu, int batch, void* stream)
+{
+    if (!plan || !u || !Lu || batch < 0) { set_error("ndl_apply_fast_noalloc: null argument"); return NDL_EINVAL; }
+    Plan* p = reinterpret_cast<Plan*>(plan);
+    if (!p->fast) { set_error("plan was created without want_fast"); return NDL_EINVAL; }
+    double* ws = nullptr;
+    int64_t cap = 0;
+    NDL_TRY(fast_static_workspace(&ws, &cap));
+    if (p->pyr_elems > cap) {
+        set_error("ndl_apply_fast_noalloc: the pyramid needs %lld bytes, the static workspace holds %lld",
+                  (long long)(p->pyr_elems * (int64_t)sizeof(double)), (long long)(cap * (int64_t)sizeof(double)));
+        return NDL_EINVAL;
+    }
+    if (batch == 0) return NDL_OK;
+    return launch_fast(*p, u, Lu, batch, (hipStream_t)stream, ws);
 }
 
 int ndl_fast_decomposition(ndl_plan plan, const int64_t* node, int32_t* panels, int32_t cap, int32_t* count)

@@ -107,8 +107,13 @@ struct Plan {
 int plan_fields(Plan& p, hipStream_t s);                   // k_i, scales, tables
 int launch_direct(Plan& p, const void* u, void* Lu, int batch, hipStream_t s);
 int launch_div(Plan& p, const void* u, void* Lu, int batch, hipStream_t s);
-int fast_prepare(Plan& p, hipStream_t s);
-int launch_fast(Plan& p, const void* u, void* Lu, int batch, hipStream_t s);
+// with_workspace: allocate the plan's own pyramid buffer (ndl_apply_fast);
+// without it only ndl_apply_fast_noalloc can run the plan
+int fast_prepare(Plan& p, hipStream_t s, bool with_workspace);
+// pyr: the pyramid buffer of pyr_elems doubles (nullptr = the plan's own)
+int launch_fast(Plan& p, const void* u, void* Lu, int batch, hipStream_t s, double* pyr = nullptr);
+// the static pyramid workspace of the calling thread's current device
+int fast_static_workspace(double** ptr, int64_t* capacity_elems);
 int fast_decomp_host(Plan& p, const int64_t* node, int32_t* out, int cap, int* count);
 int autotune(Plan& p, hipStream_t s);
 bool net_is_linear(void* net);

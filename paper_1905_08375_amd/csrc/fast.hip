@@ -23,10 +23,13 @@
 // __host__ __device__ routine drives the device gather and the host test hook.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "common.h"
 
 namespace ndl {
+
+constexpr int kMaxDevices = 64;
 
 __host__ __device__ inline int64_t isqrt64(int64_t v)
 {
@@ -295,7 +298,7 @@ __global__ void k_split(const T* __restrict__ delta, int64_t N, int64_t n, doubl
     out[i] = (T)(a0 * pow(m, expo));
 }
 
-int fast_prepare(Plan& p, hipStream_t s)
+int fast_prepare(Plan& p, hipStream_t s, bool with_workspace)
 {
     if (p.kernel == NDL_G_POLY && p.poly.size() > 1) {
         set_error("hierarchical path: polynomial profiles of degree > 0 need panel moments (not built)");
@@ -316,7 +319,7 @@ int fast_prepare(Plan& p, hipStream_t s)
     }
     if (p.fast_S > 23) { set_error("tree too deep"); return NDL_EUNSUPPORTED; }
     p.pyr_elems = tot;
-    NDL_HIP(hipMalloc(&p.d_pyr, std::max<int64_t>(1, tot) * sizeof(double)));
+    if (with_workspace) NDL_HIP(hipMalloc(&p.d_pyr, std::max<int64_t>(1, tot) * sizeof(double)));
     // weight of the polynomial part per node: g(1) in units of the scale, m^e
     NDL_HIP(hipMalloc(&p.d_split, p.N * elem_size(p.prec)));
     double a0 = p.kernel == NDL_G_POLY ? p.poly[0] : 1.0;
@@ -343,7 +346,7 @@ int fast_prepare(Plan& p, hipStream_t s)
 }
 
 template <typename T>
-static int launch_fast_t(Plan& p, const void* u, void* Lu, int batch, hipStream_t s)
+static int launch_fast_t(Plan& p, const void* u, void* Lu, int batch, hipStream_t s, double* pyr)
 {
     FastArgs a{};
     a.dim = p.dim;
@@ -363,19 +366,19 @@ static int launch_fast_t(Plan& p, const void* u, void* Lu, int batch, hipStream_
             if (c == 0) continue;
             unsigned nb = (unsigned)((c + 255) / 256);
             if (sc == 1)
-                k_pyr_first<T><<<dim3(nb), dim3(256), 0, s>>>(ub, p.d_pyr + p.lev_off[1], p.dim, p.n, p.R, E, c);
+                k_pyr_first<T><<<dim3(nb), dim3(256), 0, s>>>(ub, pyr + p.lev_off[1], p.dim, p.n, p.R, E, c);
             else
-                k_pyr_next<<<dim3(nb), dim3(256), 0, s>>>(p.d_pyr + p.lev_off[sc - 1], p.d_pyr + p.lev_off[sc],
+                k_pyr_next<<<dim3(nb), dim3(256), 0, s>>>(pyr + p.lev_off[sc - 1], pyr + p.lev_off[sc],
                                                           p.dim, p.lev_ext[sc - 1], E, c);
             NDL_HIP(hipGetLastError());
         }
         unsigned nb = (unsigned)((p.N + 255) / 256);
         if (kappa)
-            k_fast_gather<T, true><<<dim3(nb), dim3(256), 0, s>>>(ub, ob, p.d_pyr, p.d_k, (const T*)p.d_scale,
+            k_fast_gather<T, true><<<dim3(nb), dim3(256), 0, s>>>(ub, ob, pyr, p.d_k, (const T*)p.d_scale,
                                                                  (const T*)p.d_split, p.d_cntM,
                                                                  p.d_pairs, (const T*)p.d_pairw, p.npairs, a, p.N);
         else
-            k_fast_gather<T, false><<<dim3(nb), dim3(256), 0, s>>>(ub, ob, p.d_pyr, p.d_k, (const T*)p.d_scale,
+            k_fast_gather<T, false><<<dim3(nb), dim3(256), 0, s>>>(ub, ob, pyr, p.d_k, (const T*)p.d_scale,
                                                                   (const T*)p.d_split, p.d_cntM,
                                                                   p.d_pairs, (const T*)p.d_pairw, p.npairs, a, p.N);
         NDL_HIP(hipGetLastError());
@@ -383,9 +386,42 @@ static int launch_fast_t(Plan& p, const void* u, void* Lu, int batch, hipStream_
     return NDL_OK;
 }
 
-int launch_fast(Plan& p, const void* u, void* Lu, int batch, hipStream_t s)
+int launch_fast(Plan& p, const void* u, void* Lu, int batch, hipStream_t s, double* pyr)
 {
-    return p.prec == NDL_F64 ? launch_fast_t<double>(p, u, Lu, batch, s) : launch_fast_t<float>(p, u, Lu, batch, s);
+    if (!pyr) pyr = p.d_pyr;
+    return p.prec == NDL_F64 ? launch_fast_t<double>(p, u, Lu, batch, s, pyr)
+                             : launch_fast_t<float>(p, u, Lu, batch, s, pyr);
+}
+
+// ------------------------------------------------------------------ static workspace
+// The pyramid of ndl_apply_fast_noalloc lives in this file-scope device array
+// (each GPU that runs the library holds its own copy until the process ends).
+// In host code its name is only a host-side stand-in: the device address of
+// each GPU's copy comes from hipGetSymbolAddress, taken once per device with
+// that device current and kept here; kernels receive that address.
+constexpr int64_t kStaticWorkspaceBytes = int64_t(64) << 20;
+static __device__ __align__(256) double scratch[kStaticWorkspaceBytes / sizeof(double)];
+static std::mutex g_scratch_mu;
+static void* g_scratch_addr[kMaxDevices] = {};
+
+int fast_static_workspace(double** ptr, int64_t* capacity_elems)
+{
+    int dev = 0;
+    NDL_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device ordinal %d beyond the static workspace table (%d devices)", dev, kMaxDevices);
+        return NDL_EUNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* a = nullptr;
+        NDL_HIP(hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)));
+        if (!a) { set_error("no device address for the static workspace"); return NDL_EHIP; }
+        g_scratch_addr[dev] = a;
+    }
+    *ptr = static_cast<double*>(g_scratch_addr[dev]);
+    *capacity_elems = kStaticWorkspaceBytes / (int64_t)sizeof(double);
+    return NDL_OK;
 }
 
 // Device-side record of one node's decomposition, for the parity test.

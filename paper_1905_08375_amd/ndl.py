@@ -27,7 +27,7 @@ EXPORTS = [
     "ndl_fast_decomposition", "ndl_decompose_node", "ndl_cg_solve", "ndl_net_create", "ndl_net_destroy", "ndl_net_set_linear",
     "ndl_net_save", "ndl_net_load", "ndl_net_num_params", "ndl_net_train_step", "ndl_precond_apply",
     "ndl_autotune", "ndl_last_error", "ndl_version", "ndl_plan_set_variant", "ndl_plan_num_variants",
-    "ndl_net_conv_test", "ndl_net_train_step_energy", "ndl_net_layer_tensor",
+    "ndl_net_conv_test", "ndl_net_train_step_energy", "ndl_net_layer_tensor", "ndl_apply_fast_noalloc",
 ]
 
 
@@ -81,6 +81,7 @@ def lib():
             "ndl_plan_get_info": [vp, C.POINTER(ndl_plan_info)],
             "ndl_apply": [vp, vp, vp, C.c_int, vp],
             "ndl_apply_fast": [vp, vp, vp, C.c_int, vp],
+            "ndl_apply_fast_noalloc": [vp, vp, vp, C.c_int, vp],
             "ndl_fast_decomposition": [vp, C.POINTER(i64), C.POINTER(i32), i32, C.POINTER(i32)],
             "ndl_decompose_node": [i32, i64, C.POINTER(i64), i64, C.POINTER(i32), i32, C.POINTER(i32)],
             "ndl_cg_solve": [C.POINTER(vp), C.c_int, C.POINTER(vp), C.POINTER(vp), C.POINTER(ndl_cg_opts),
@@ -165,9 +166,11 @@ def make_problem(dim, n, collar, delta, coef, *, model=NDL_DIFFUSION, form=NDL_N
     return p
 
 
-def ndl_plan_create(prob: ndl_problem, want_fast: bool = False, stream=None, keep=()) -> Plan:
+def ndl_plan_create(prob: ndl_problem, want_fast: int = 0, stream=None, keep=()) -> Plan:
+    """want_fast: 0 direct only, 1 (or True) with the hierarchical path and its
+    pyramid workspace, 2 hierarchical path without it (ndl_apply_fast_noalloc)."""
     h = C.c_void_p()
-    _check(lib().ndl_plan_create(C.byref(prob), int(bool(want_fast)), C.byref(h), _stream(stream)),
+    _check(lib().ndl_plan_create(C.byref(prob), int(want_fast), C.byref(h), _stream(stream)),
            "ndl_plan_create")
     return Plan(h, prob, keep)
 
@@ -182,6 +185,11 @@ def ndl_apply(plan: Plan, u, Lu, batch: int = 1, stream=None):
 
 def ndl_apply_fast(plan: Plan, u, Lu, batch: int = 1, stream=None):
     _check(lib().ndl_apply_fast(plan.handle, _ptr(u), _ptr(Lu), int(batch), _stream(stream)), "ndl_apply_fast")
+
+
+def ndl_apply_fast_noalloc(plan: Plan, u, Lu, batch: int = 1, stream=None):
+    _check(lib().ndl_apply_fast_noalloc(plan.handle, _ptr(u), _ptr(Lu), int(batch), _stream(stream)),
+           "ndl_apply_fast_noalloc")
 
 
 def _records(buf, cnt, dim):
