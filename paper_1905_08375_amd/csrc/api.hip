@@ -29,7 +29,7 @@ static void free_plan(Plan* p)
 {
     if (!p) return;
     void* bufs[] = {p->d_k, p->d_scale, p->d_invm2, p->d_split, p->d_invT, p->d_pairs, p->d_pairw, p->d_wq,
-                    p->d_full, p->d_fullw, p->d_pyr, p->d_cntM};
+                    p->d_full, p->d_fullw, p->d_pyr, p->d_wtab};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -111,12 +111,7 @@ int ndl_plan_create(const ndl_problem* prob, int want_fast, ndl_plan* out, void*
     hipStream_t s = (hipStream_t)stream;
     int rc = plan_fields(*p, s);
     if (rc == NDL_OK && want_fast) {
-        if (p->form != NDL_ND || p->model != NDL_DIFFUSION) {
-            set_error("the hierarchical path is implemented for case (a) diffusion");
-            rc = NDL_EUNSUPPORTED;
-        } else {
-            rc = fast_prepare(*p, s, want_fast != 2);
-        }
+        rc = fast_prepare(*p, s, want_fast != 2);
     }
     if (rc != NDL_OK) { free_plan(p); return rc; }
     *out = reinterpret_cast<ndl_plan>(p);

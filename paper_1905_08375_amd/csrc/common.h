@@ -98,9 +98,10 @@ struct Plan {
     int64_t fast_origin = 0;   // tree node index of the first padded node (per axis)
     std::vector<int64_t> lev_off;   // offsets of each level in d_pyr (elements)
     std::vector<int64_t> lev_ext;   // panels per axis on each level
-    double* d_pyr = nullptr;   // partial sums, FP64, all levels
+    int fast_deg = 0;          // moment degree of the panels (0: partial sums)
+    double* d_pyr = nullptr;   // panel moments, FP64, all levels
     int64_t pyr_elems = 0;
-    int32_t* d_cntM = nullptr; // lattice count of the full ball (centre included) per k
+    double* d_wtab = nullptr;  // full-ball sums of the polynomial part per cutoff k
 };
 
 // host helpers implemented in the .hip files

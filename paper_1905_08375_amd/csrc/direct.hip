@@ -75,6 +75,14 @@ __global__ __launch_bounds__(256) void k_cutoffs(const T* __restrict__ delta, in
     }
 }
 
+// histogram of the integer cutoffs (for the average ball size)
+__global__ __launch_bounds__(256) void k_khist(const int32_t* __restrict__ kk, int64_t N,
+                                               unsigned long long* __restrict__ hist)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&hist[kk[i]], 1ull);
+}
+
 struct ScaleArgs {
     int dim, kernel, norm, K;
     int64_t n;
@@ -524,12 +532,23 @@ static int plan_fields_t(Plan& p, hipStream_t s)
     NDL_TRY(upload((void**)&p.d_invT, invT));
     double* d_T = nullptr;
     NDL_TRY(upload((void**)&d_T, Ttab));
-    // average ball size, for reports
+    // average ball size (neighbours per node) from the histogram of the cutoffs
     {
         std::vector<int64_t> cnt(p.kmax + 1, 0);
         for (auto& o : full) cnt[o.q]++;
         for (int64_t k = 1; k <= p.kmax; k++) cnt[k] += cnt[k - 1];
-        p.avg_ball = (double)cnt[p.kmax];  // refined below from the k histogram when cheap
+        unsigned long long* d_hist = nullptr;
+        NDL_HIP(hipMalloc(&d_hist, (p.kmax + 1) * sizeof(unsigned long long)));
+        NDL_HIP(hipMemsetAsync(d_hist, 0, (p.kmax + 1) * sizeof(unsigned long long), s));
+        k_khist<<<dim3(ncut), dim3(256), 0, s>>>(p.d_k, p.N, d_hist);
+        NDL_HIP(hipGetLastError());
+        std::vector<unsigned long long> hist(p.kmax + 1);
+        NDL_HIP(hipMemcpyAsync(hist.data(), d_hist, hist.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        NDL_HIP(hipStreamSynchronize(s));
+        NDL_HIP(hipFree(d_hist));
+        double tot = 0.0;
+        for (int64_t k = 0; k <= p.kmax; k++) tot += (double)hist[k] * (double)cnt[k];
+        p.avg_ball = p.N > 0 ? tot / (double)p.N : 0.0;
     }
     if (p.form == NDL_ND) {
         NDL_HIP(hipMalloc(&p.d_scale, p.N * elem_size(p.prec)));

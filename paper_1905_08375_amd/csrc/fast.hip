@@ -1,19 +1,29 @@
-// Hierarchical evaluation of Section 3 for case (a) diffusion on the zero
-// volume constraint (problem "nonlocal:polynomial"):
+// Hierarchical evaluation of Section 3 for case (a): nonlocal diffusion and
+// linear bond-based peridynamics.
 //
-//   Step 1  the ball of node x cut by Omega is split into maximal dyadic panels
-//           of the tree over Omega (Algorithm "recur" with the cube/ball test
-//           on node boxes);
-//   Step 2  partial sums of u over every panel, bottom-up (one pass per level,
-//           FP64 for every precision);
-//   Step 3  S_x = sum of the partial sums over the panels of x, and
-//           L^P u(x) = s_x w_P (S_x - M_x u(x)) as in eq. "nonlocalP", with
-//           M_x the lattice count of the full ball (centre included).
+//   Step 1  the ball of node x is split into maximal dyadic panels of a tree
+//           (Algorithm "recur" with the cube/ball test on node boxes);
+//   Step 2  per panel, moments of u about the panel centre, bottom-up (one
+//           pass per level, FP64 for every precision): sum_w w^alpha u for the
+//           monomials |alpha| <= DEG (DEG = 0 is the paper's partial sum of
+//           u; DEG > 0 gives the "sum x^m u" moments that Section 3 asks for
+//           polynomials p^{2K} with K > 0, and the peridynamic bond tensor);
+//   Step 3  per node, the polynomial part of the kernel summed over the
+//           panels of its decomposition from those moments, combined as in
+//           eq. "nonlocalP" with the full-ball sum of the same polynomial.
 //
-// The profile is split as g = kappa + g(1) (the K = 0 splitting): the
-// polynomial part is the constant g(1), evaluated hierarchically; the
-// remainder kappa(z) = |z|^e - m^e (zero for the constant profile) is summed
-// directly in the same kernel.
+// Kernel splitting (the K of Section 3):
+//   diffusion, polynomial profile p(r) = sum_j a_j r^2j: exact, no remainder;
+//   diffusion, power profile |z|^e: the constant m^e (the value at |z| = m)
+//     hierarchically, the remainder kappa(z) = |z|^e - m^e summed directly;
+//   peridynamics, pair tensor |z|^(e-2) z z^T: the constant m^(e-2) times
+//     z z^T hierarchically (second moments of the displacement per
+//     component), the remainder (|z|^(e-2) - m^(e-2)) z z^T summed directly.
+// The direct remainder is summed from an LDS tile of u in the same pass.
+//
+// The tree covers the padded box (grid plus collar), so the decomposition is
+// of the whole ball and the collar's volume-constraint data enter exactly as
+// in the direct sum; with a zero collar this is the paper's ball cut by Omega.
 //
 // Step 1 is not stored per node.  On panel rows it has a closed form: on a
 // row of scale s (side 2^s nodes) the panels inside the ball are one run
@@ -24,53 +34,50 @@
 #include <algorithm>
 #include <cmath>
 #include <mutex>
+#include <type_traits>
 
 #include "common.h"
 
 namespace ndl {
 
 constexpr int kMaxDevices = 64;
+constexpr int kMaxLevels = 24;
 
-__host__ __device__ inline int64_t isqrt64(int64_t v)
+// ------------------------------------------------------------------ integer helpers
+template <typename I>
+__host__ __device__ inline I isqrt_i(I v)
 {
     if (v < 0) return -1;
-    int64_t r = (int64_t)sqrt((double)v);
+    I r = (I)sqrt((double)v);
     while (r * r > v) --r;
     while ((r + 1) * (r + 1) <= v) ++r;
     return r;
 }
 
-__host__ __device__ inline int64_t fdiv(int64_t a, int64_t b)  // floor(a / b), b > 0
-{
-    int64_t q = a / b;
-    return (a % b != 0 && a < 0) ? q - 1 : q;
-}
-
-__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b)  // ceil(a / b), b > 0
-{
-    return -fdiv(-a, b);
-}
-
-// floor and ceiling of v / 2^s (panel sides are powers of two: shifts, not
-// 64-bit divisions; the arithmetic right shift rounds toward minus infinity)
-__host__ __device__ inline int64_t fshr(int64_t v, int s) { return v >> s; }
-__host__ __device__ inline int64_t cshr(int64_t v, int s) { return -((-v) >> s); }
+// floor and ceiling of v / 2^s (panel sides are powers of two: shifts; the
+// arithmetic right shift rounds toward minus infinity)
+template <typename I>
+__host__ __device__ inline I fshr(I v, int s) { return v >> s; }
+template <typename I>
+__host__ __device__ inline I cshr(I v, int s) { return -((-v) >> s); }
 
 // farthest squared offset from x to the panel [j a, j a + a - 1] on one axis
-__host__ __device__ inline int64_t far2(int64_t x, int64_t j, int64_t a)
+template <typename I>
+__host__ __device__ inline I far2(I x, I j, I a)
 {
-    int64_t lo = j * a - x, hi = j * a + a - 1 - x;
+    I lo = j * a - x, hi = j * a + a - 1 - x;
     return lo * lo > hi * hi ? lo * lo : hi * hi;
 }
 
-// panels of side 2^s on the last axis lying inside {|d| <= isqrt(A)} and inside Omega
-__host__ __device__ inline void inside_run(int64_t x, int64_t A, int s, int64_t E, int64_t& lo, int64_t& hi)
+// panels of side 2^s on the last axis lying inside {|d| <= isqrt(A)} and inside the domain
+template <typename I>
+__host__ __device__ inline void inside_run(I x, I A, int s, I E, I& lo, I& hi)
 {
     if (A < 0 || E <= 0) { lo = 0; hi = -1; return; }
-    int64_t r = isqrt64(A);
-    lo = cshr(x - r, s);
+    I r = isqrt_i<I>(A);
+    lo = cshr<I>(x - r, s);
     if (lo < 0) lo = 0;
-    hi = fshr(x + r + 1, s) - 1;
+    hi = fshr<I>(x + r + 1, s) - 1;
     if (hi > E - 1) hi = E - 1;
 }
 
@@ -96,47 +103,46 @@ __host__ __device__ inline int tree_height(int64_t n)
     return L;
 }
 
-// Step 1 for node x (dim coordinates), cutoff k.  Calls
-// emit(s, j_rows..., lo, hi) for every run of included panels of scale s on
-// the last axis: f(s, r0, r1, lo, hi), where r0/r1 are the row indices on the
-// leading axes (unused axes pass 0).
-template <class Emit>
-__host__ __device__ inline void decompose_runs(int dim, int64_t n, const int64_t* x, int64_t k, Emit& emit)
+// Step 1 for node x (dim coordinates) in the domain [0, n)^dim, cutoff k:
+// calls emit(s, r0, r1, lo, hi) for every run of included panels of scale s
+// on the last axis, r0/r1 the row indices on the leading axes (unused axes
+// pass 0).  Runs come in increasing s.
+template <typename I, class Emit>
+__host__ __device__ inline void decompose_runs(int dim, I n, const I* x, I k, Emit& emit)
 {
     if (k < 0) return;
-    int L = tree_height(n);
-    int S = top_scale(dim, k, L);
-    int64_t J = isqrt64(k);
-    int64_t xl = x[dim - 1];
+    int L = tree_height((int64_t)n);
+    int S = top_scale(dim, (int64_t)k, L);
+    I J = isqrt_i<I>(k);
+    I xl = x[dim - 1];
     for (int s = 0; s <= S; ++s) {
-        int64_t a = (int64_t)1 << s;
-        int64_t E = n >> s;
-        int64_t Ep = n >> (s + 1);
-        // row ranges on leading axes
-        int64_t rlo[2] = {0, 0}, rhi[2] = {0, 0};
+        I a = (I)1 << s;
+        I E = n >> s;
+        I Ep = n >> (s + 1);
+        I rlo[2] = {0, 0}, rhi[2] = {0, 0};
         for (int ax = 0; ax < dim - 1; ++ax) {
-            rlo[ax] = cshr(x[ax] - J, s);
+            rlo[ax] = cshr<I>(x[ax] - J, s);
             if (rlo[ax] < 0) rlo[ax] = 0;
-            rhi[ax] = fshr(x[ax] + J + 1, s) - 1;
+            rhi[ax] = fshr<I>(x[ax] + J + 1, s) - 1;
             if (rhi[ax] > E - 1) rhi[ax] = E - 1;
         }
-        for (int64_t r0 = rlo[0]; r0 <= rhi[0]; ++r0) {
-            for (int64_t r1 = rlo[1]; r1 <= rhi[1]; ++r1) {
-                int64_t A = k, Ap = k;
+        for (I r0 = rlo[0]; r0 <= rhi[0]; ++r0) {
+            for (I r1 = rlo[1]; r1 <= rhi[1]; ++r1) {
+                I A = k, Ap = k;
                 bool prow = s < S;
                 if (dim >= 2) {
-                    A -= far2(x[0], r0, a);
-                    if (prow) { if ((r0 >> 1) > Ep - 1) prow = false; else Ap -= far2(x[0], r0 >> 1, 2 * a); }
+                    A -= far2<I>(x[0], r0, a);
+                    if (prow) { if ((r0 >> 1) > Ep - 1) prow = false; else Ap -= far2<I>(x[0], r0 >> 1, 2 * a); }
                 }
                 if (dim >= 3) {
-                    A -= far2(x[1], r1, a);
-                    if (prow) { if ((r1 >> 1) > Ep - 1) prow = false; else Ap -= far2(x[1], r1 >> 1, 2 * a); }
+                    A -= far2<I>(x[1], r1, a);
+                    if (prow) { if ((r1 >> 1) > Ep - 1) prow = false; else Ap -= far2<I>(x[1], r1 >> 1, 2 * a); }
                 }
-                int64_t lo, hi;
-                inside_run(xl, A, s, E, lo, hi);
+                I lo, hi;
+                inside_run<I>(xl, A, s, E, lo, hi);
                 if (lo > hi) continue;
-                int64_t plo = 0, phi = -1;
-                if (prow) inside_run(xl, Ap, s + 1, Ep, plo, phi);
+                I plo = 0, phi = -1;
+                if (prow) inside_run<I>(xl, Ap, s + 1, Ep, plo, phi);
                 if (plo > phi) {
                     emit(s, r0, r1, lo, hi);
                 } else {
@@ -148,113 +154,479 @@ __host__ __device__ inline void decompose_runs(int dim, int64_t n, const int64_t
     }
 }
 
-// ------------------------------------------------------------------ Step 2
-// Level 1 from the padded state (level 0 is u itself), in FP64.
-template <typename T>
-__global__ void k_pyr_first(const T* __restrict__ u, double* __restrict__ S1, int dim, int64_t n, int R, int64_t E1,
-                            int64_t cnt)
+// ------------------------------------------------------------------ monomials
+// Moments are stored per panel as [component][monomial], the monomials
+// w0^a0 w1^a1 w2^a2 with a0 + a1 + a2 <= DEG in the order a0, then a1, then a2.
+__host__ __device__ constexpr int nmono(int dim, int deg)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= cnt) return;
-    int64_t P = n + 2 * R;
-    int64_t j[3] = {0, 0, 0}, r = t;
-    for (int a = dim - 1; a >= 0; --a) { j[a] = r % E1; r /= E1; }
-    double acc = 0.0;
-    for (int m = 0; m < (1 << dim); ++m) {
-        int64_t off = 0;
-        for (int a = 0; a < dim; ++a) off = off * P + (2 * j[a] + ((m >> a) & 1) + R);
-        acc += (double)u[off];
-    }
-    S1[t] = acc;
+    return dim == 1 ? deg + 1 : (dim == 2 ? (deg + 1) * (deg + 2) / 2 : (deg + 1) * (deg + 2) * (deg + 3) / 6);
 }
 
-__global__ void k_pyr_next(const double* __restrict__ Sp, double* __restrict__ S, int dim, int64_t Ep, int64_t E,
-                           int64_t cnt)
+template <int DIM, int DEG>
+__host__ __device__ constexpr int midx(int a0, int a1, int a2)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (DIM == 1) return a0;
+    if (DIM == 2) return a0 * (DEG + 1) - a0 * (a0 - 1) / 2 + a1;
+    int base = 0;
+    for (int t = 0; t < a0; ++t) base += nmono(2, DEG - t);
+    const int D = DEG - a0;
+    return base + a1 * (D + 1) - a1 * (a1 - 1) / 2 + a2;
+}
+
+// exponent of axis `ax` of monomial m
+template <int DIM, int DEG>
+__host__ __device__ constexpr int mexp(int m, int ax)
+{
+    for (int a0 = 0; a0 <= DEG; ++a0)
+        for (int a1 = 0; a1 <= (DIM >= 2 ? DEG - a0 : 0); ++a1)
+            for (int a2 = 0; a2 <= (DIM >= 3 ? DEG - a0 - a1 : 0); ++a2)
+                if (midx<DIM, DEG>(a0, a1, a2) == m) return ax == 0 ? a0 : (ax == 1 ? a1 : a2);
+    return -1;
+}
+
+__host__ __device__ constexpr double binom(int n, int k)
+{
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (double)(n - k + i) / (double)i;
+    return r;
+}
+
+// Moments shifted to a new centre: src holds sum w^b u about centre c, dst
+// receives sum (w + d)^alpha u (the same sums about c - d), axis by axis.
+template <int DIM, int DEG>
+__device__ inline void shift_moments(const double* src, double* dst, const double* d)
+{
+    constexpr int NM = nmono(DIM, DEG);
+    double t[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) t[m] = src[m];
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) {
+        double pw[DEG + 1];
+        pw[0] = 1.0;
+#pragma unroll
+        for (int q = 1; q <= DEG; ++q) pw[q] = pw[q - 1] * d[ax];
+        double o[NM];
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            const int e0 = mexp<DIM, DEG>(m, 0), e1 = mexp<DIM, DEG>(m, 1), e2 = mexp<DIM, DEG>(m, 2);
+            const int ea = ax == 0 ? e0 : (ax == 1 ? e1 : e2);
+            double acc = 0.0;
+#pragma unroll
+            for (int b = 0; b <= DEG; ++b) {
+                if (b > ea) break;
+                const int src_m = midx<DIM, DEG>(ax == 0 ? b : e0, ax == 1 ? b : e1, ax == 2 ? b : e2);
+                acc += binom(ea, b) * pw[ea - b] * t[src_m];
+            }
+            o[m] = acc;
+        }
+#pragma unroll
+        for (int m = 0; m < NM; ++m) t[m] = o[m];
+    }
+#pragma unroll
+    for (int m = 0; m < NM; ++m) dst[m] += t[m];
+}
+
+// ------------------------------------------------------------------ Step 2
+// Level 1 from the padded state (level 0 is u itself): every node of a panel
+// sits at +-1/2 from its centre on each axis.
+template <typename T, int DIM, int DEG, int NC>
+__global__ __launch_bounds__(256) void k_mom_first(const T* __restrict__ u, int64_t npad, double* __restrict__ lev,
+                                                   int64_t P, int64_t E1, int64_t cnt)
+{
+    constexpr int NM = nmono(DIM, DEG);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= cnt) return;
     int64_t j[3] = {0, 0, 0}, r = t;
-    for (int a = dim - 1; a >= 0; --a) { j[a] = r % E; r /= E; }
-    double acc = 0.0;
-    for (int m = 0; m < (1 << dim); ++m) {
+    for (int a = DIM - 1; a >= 0; --a) { j[a] = r % E1; r /= E1; }
+    double acc[NC * NM];
+#pragma unroll
+    for (int q = 0; q < NC * NM; ++q) acc[q] = 0.0;
+#pragma unroll
+    for (int c = 0; c < (1 << DIM); ++c) {
         int64_t off = 0;
-        for (int a = 0; a < dim; ++a) off = off * Ep + (2 * j[a] + ((m >> a) & 1));
-        acc += Sp[off];
+        double d[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            const int bit = (c >> (DIM - 1 - a)) & 1;
+            off = off * P + (2 * j[a] + bit);
+            d[a] = bit ? 0.5 : -0.5;
+        }
+#pragma unroll
+        for (int comp = 0; comp < NC; ++comp) {
+            const double v = (double)u[comp * npad + off];
+#pragma unroll
+            for (int m = 0; m < NM; ++m) {
+                double w = v;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+#pragma unroll
+                    for (int q = 0; q < DEG; ++q)
+                        if (q < mexp<DIM, DEG>(m, a)) w *= d[a];
+                }
+                acc[comp * NM + m] += w;
+            }
+        }
     }
-    S[t] = acc;
+    double* o = lev + t * (NC * NM);
+#pragma unroll
+    for (int q = 0; q < NC * NM; ++q) o[q] = acc[q];
+}
+
+// Level s from level s-1: the children's moments shifted from their centres to
+// the parent's (children sit at +-h, h = a quarter of the parent's side).
+template <int DIM, int DEG, int NC>
+__global__ __launch_bounds__(256) void k_mom_next(const double* __restrict__ prev, double* __restrict__ lev,
+                                                  int64_t Ep, int64_t E, double h, int64_t cnt)
+{
+    constexpr int NM = nmono(DIM, DEG);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cnt) return;
+    int64_t j[3] = {0, 0, 0}, r = t;
+    for (int a = DIM - 1; a >= 0; --a) { j[a] = r % E; r /= E; }
+    double acc[NC * NM];
+#pragma unroll
+    for (int q = 0; q < NC * NM; ++q) acc[q] = 0.0;
+#pragma unroll
+    for (int c = 0; c < (1 << DIM); ++c) {
+        int64_t off = 0;
+        double d[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            const int bit = (c >> (DIM - 1 - a)) & 1;
+            off = off * Ep + (2 * j[a] + bit);
+            // the child's centre relative to the parent's: w_parent = w_child + d
+            d[a] = bit ? h : -h;
+        }
+        const double* ch = prev + off * (NC * NM);
+#pragma unroll
+        for (int comp = 0; comp < NC; ++comp) {
+            if (DEG == 0) {
+                acc[comp] += ch[comp];
+            } else {
+                double src[NM];
+#pragma unroll
+                for (int m = 0; m < NM; ++m) src[m] = ch[comp * NM + m];
+                shift_moments<DIM, DEG>(src, acc + comp * NM, d);
+            }
+        }
+    }
+    double* o = lev + t * (NC * NM);
+#pragma unroll
+    for (int q = 0; q < NC * NM; ++q) o[q] = acc[q];
 }
 
 // ------------------------------------------------------------------ Step 3
 struct FastArgs {
-    int dim, R, S;
-    int64_t n, P;
-    int64_t off[24];  // level offsets into the pyramid (levels 1..S)
+    int R, S;
+    int poly_mode;              // 1: polynomial profile (weights b_j = a_j / m^2j, no per-node split)
+    int P;                      // padded extent per used axis
+    int E[3], H, L[3];          // tile extent, LDS halo, LDS extent per box axis
+    int tiles[3];
+    int ls0, ls1;               // LDS strides of box axes 0, 1
+    int ext[3];                 // grid extent per box axis (1 for unused)
+    int kmax1;                  // kmax + 1 (row length of the full-ball tables)
+    int64_t N, NP;
+    int64_t lev[kMaxLevels];    // offsets (doubles) of levels 1..S in the pyramid
+    double poly[8];             // a_j of the polynomial profile
 };
 
-template <typename T>
-struct GatherSum {
-    const T* u;
-    const double* pyr;
-    const FastArgs* a;
-    double acc;
-    __device__ inline void operator()(int s, int64_t r0, int64_t r1, int64_t lo, int64_t hi)
-    {
-        int dim = a->dim;
-        if (s == 0) {
-            int64_t base;
-            if (dim == 1) base = a->R;
-            else if (dim == 2) base = (r0 + a->R) * a->P + a->R;
-            else base = ((r0 + a->R) * a->P + (r1 + a->R)) * a->P + a->R;
-            for (int64_t j = lo; j <= hi; ++j) acc += (double)u[base + j];
-        } else {
-            int64_t E = a->n >> s;
-            int64_t base = a->off[s];
-            if (dim == 2) base += r0 * E;
-            else if (dim == 3) base += (r0 * E + r1) * E;
-            for (int64_t j = lo; j <= hi; ++j) acc += pyr[base + j];
-        }
-    }
-};
-
-template <typename T, bool KAPPA>
-__global__ __launch_bounds__(256) void k_fast_gather(const T* __restrict__ u, T* __restrict__ out,
-                                                     const double* __restrict__ pyr, const int32_t* __restrict__ kk,
-                                                     const T* __restrict__ sc, const T* __restrict__ split,
-                                                     const int32_t* __restrict__ cntM, const int4* __restrict__ pairs,
-                                                     const T* __restrict__ pw, int npairs, FastArgs a, int64_t N)
+// Polynomial part of one panel for diffusion with p(z) = sum_j b_j |z|^2j:
+// sum_{w in Q} p(D + w) u_w from the moments mu of Q (D = panel centre - x).
+// The coefficients of p(D + w) in w are built by Horner's rule in
+// |D + w|^2 = sum_a (D_a^2 + 2 D_a w_a + w_a^2).
+template <int DIM, int DEG>
+__device__ inline double panel_poly(const double* mu, const double* D, const double* b)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    int64_t x[3] = {0, 0, 0}, r = i;
-    for (int ax = a.dim - 1; ax >= 0; --ax) { x[ax] = r % a.n; r /= a.n; }
-    int64_t pc = 0;
-    for (int ax = 0; ax < a.dim; ++ax) pc = pc * a.P + (x[ax] + a.R);
-    int k = kk[i];
-    GatherSum<T> g{u, pyr, &a, 0.0};
-    decompose_runs(a.dim, a.n, x, (int64_t)k, g);
-    T u0 = u[pc];
-    double wP = (double)split[i];
-    double poly = wP * (g.acc - (double)cntM[k] * (double)u0);
-    double kap = 0.0;
-    if (KAPPA) {
-        // remainder kappa(z) = |z|^e - m^e over the ball, paired {z, -z}
-        T mp = split[i];
-        T sum = 0, comp = 0;
-        int64_t s1 = a.dim >= 2 ? a.P : 1;
-        int64_t s0 = a.dim >= 3 ? a.P * a.P : 0;
-        for (int p = 0; p < npairs; ++p) {
-            int4 o = pairs[p];
-            if (o.w > k) break;
-            int64_t off = (int64_t)o.x * s0 + (int64_t)o.y * s1 + o.z;
-            T d = (u[pc + off] - u0) + (u[pc - off] - u0);
-            T y = (pw[p] - mp) * d - comp;
-            T t = sum + y;
-            comp = (t - sum) - y;
-            sum = t;
+    constexpr int NM = nmono(DIM, DEG);
+    constexpr int K = DEG / 2;
+    if (K == 0) return b[0] * mu[0];
+    double c[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) c[m] = 0.0;
+    c[0] = b[K];
+#pragma unroll
+    for (int j = K - 1; j >= 0; --j) {
+        double o[NM];
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            const int e[3] = {mexp<DIM, DEG>(m, 0), mexp<DIM, DEG>(m, 1), mexp<DIM, DEG>(m, 2)};
+            double acc = m == 0 ? b[j] : 0.0;
+#pragma unroll
+            for (int ax = 0; ax < DIM; ++ax) {
+                acc += D[ax] * D[ax] * c[m];
+                if (e[ax] >= 1) {
+                    const int q = midx<DIM, DEG>(e[0] - (ax == 0), e[1] - (ax == 1), e[2] - (ax == 2));
+                    acc += 2.0 * D[ax] * c[q];
+                }
+                if (e[ax] >= 2) {
+                    const int q = midx<DIM, DEG>(e[0] - 2 * (ax == 0), e[1] - 2 * (ax == 1), e[2] - 2 * (ax == 2));
+                    acc += c[q];
+                }
+            }
+            o[m] = acc;
         }
-        kap = (double)sum - (double)comp;
+#pragma unroll
+        for (int m = 0; m < NM; ++m) c[m] = o[m];
     }
-    out[i] = (T)((double)sc[i] * (poly + kap));
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < NM; ++m) s += c[m] * mu[m];
+    return s;
+}
+
+// Bond tensor of one panel for peridynamics: F_a += sum_{w in Q} z_a (z . u_w),
+// z = D + w, from the moments (|alpha| <= 2) of each displacement component.
+template <int DIM>
+__device__ inline void panel_pd(const double* mu, const double* D, double* F)
+{
+    constexpr int NM = nmono(DIM, 2);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        double f = 0.0;
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) {
+            const double* m = mu + b * NM;
+            const int eb = midx<DIM, 2>(b == 0, b == 1, b == 2);
+            const int ea = midx<DIM, 2>(a == 0, a == 1, a == 2);
+            const int eab = midx<DIM, 2>((a == 0) + (b == 0), (a == 1) + (b == 1), (a == 2) + (b == 2));
+            f += D[a] * D[b] * m[0] + D[a] * m[eb] + D[b] * m[ea] + m[eab];
+        }
+        F[a] += f;
+    }
+}
+
+// MODEL 0 diffusion (NC = 1), 1 peridynamics (NC = DIM).  DEG: moment degree.
+// KAPPA: a direct remainder (power profiles).  STAGE: u of the tile plus a halo
+// of the ball's reach in LDS (remainder and single-node panels read there).
+template <typename T, int DIM, int MODEL, int DEG, bool KAPPA, bool STAGE>
+__global__ __launch_bounds__(256) void k_fast_step3(const T* __restrict__ u, T* __restrict__ out,
+                                                    const double* __restrict__ pyr, FastArgs a,
+                                                    const int32_t* __restrict__ kk, const T* __restrict__ sc,
+                                                    const T* __restrict__ pwn, const double* __restrict__ wtab,
+                                                    const int4* __restrict__ pairs, const T* __restrict__ pairw,
+                                                    int npairs)
+{
+    constexpr int NC = MODEL ? DIM : 1;
+    constexpr int NM = nmono(DIM, DEG);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* tile = reinterpret_cast<T*>(smem_raw);
+    __shared__ int64_t s_lev[kMaxLevels];
+    constexpr int kStage = 512;
+    __shared__ int s_off[KAPPA ? kStage : 1], s_q[KAPPA ? kStage : 1];
+    __shared__ T s_w[KAPPA ? kStage : 1];
+    __shared__ signed char s_z[KAPPA && MODEL ? 3 * kStage : 1];
+    for (int q = threadIdx.x; q < kMaxLevels; q += blockDim.x) s_lev[q] = a.lev[q];
+    const bool staged_pairs = KAPPA && STAGE && npairs <= kStage;
+    if (staged_pairs)
+        for (int p = threadIdx.x; p < npairs; p += blockDim.x) {
+            const int4 o = pairs[p];
+            s_off[p] = o.x * a.ls0 + o.y * a.ls1 + o.z;
+            s_q[p] = o.w;
+            s_w[p] = pairw[p];
+            if (MODEL) {
+                s_z[3 * p] = (signed char)o.x;
+                s_z[3 * p + 1] = (signed char)o.y;
+                s_z[3 * p + 2] = (signed char)o.z;
+            }
+        }
+    const int nb = a.tiles[0] * a.tiles[1] * a.tiles[2];
+    const int t = xcd_tile(blockIdx.x, nb);
+    const int t2 = t % a.tiles[2];
+    const int t1 = (t / a.tiles[2]) % a.tiles[1];
+    const int t0 = t / (a.tiles[2] * a.tiles[1]);
+    const int org[3] = {t0 * a.E[0], t1 * a.E[1], t2 * a.E[2]};
+    constexpr bool U0 = DIM >= 3, U1 = DIM >= 2;  // box axes in use
+    const int64_t P = a.P;
+    const int64_t P0 = U0 ? P : 1, P1 = U1 ? P : 1;
+    const T* ub = u + (int64_t)blockIdx.y * NC * a.NP;
+    T* ob = out + (int64_t)blockIdx.y * NC * a.N;
+    const int tot = a.L[0] * a.L[1] * a.L[2];
+    if (STAGE) {
+        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+            const int l2 = idx % a.L[2];
+            const int rr = idx / a.L[2];
+            const int l1 = rr % a.L[1];
+            const int l0 = rr / a.L[1];
+            // padded coordinates of the staged node
+            const int g0 = U0 ? org[0] + a.R - a.H + l0 : 0;
+            const int g1 = U1 ? org[1] + a.R - a.H + l1 : 0;
+            const int g2 = org[2] + a.R - a.H + l2;
+            const bool in = g0 >= 0 && g0 < P0 && g1 >= 0 && g1 < P1 && g2 >= 0 && g2 < P;
+            const int64_t gg = ((int64_t)g0 * P1 + g1) * P + g2;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) tile[c * tot + idx] = in ? ub[c * a.NP + gg] : T(0);
+        }
+    }
+    __syncthreads();
+
+    const int e2 = threadIdx.x % a.E[2];
+    const int e1 = (threadIdx.x / a.E[2]) % a.E[1];
+    const int e0 = threadIdx.x / (a.E[2] * a.E[1]);
+    const int x[3] = {org[0] + e0, org[1] + e1, org[2] + e2};
+    const bool valid = e0 < a.E[0] && x[0] < a.ext[0] && x[1] < a.ext[1] && x[2] < a.ext[2];
+    if (!valid) return;
+    const int64_t gi = ((int64_t)x[0] * a.ext[1] + x[1]) * a.ext[2] + x[2];
+    // this node in the padded box, in the dim coordinates of the tree
+    using I = typename std::conditional<DIM == 1, int64_t, int>::type;
+    I xp[3] = {0, 0, 0};
+    if (DIM == 1) xp[0] = (I)(x[2] + a.R);
+    if (DIM == 2) { xp[0] = (I)(x[1] + a.R); xp[1] = (I)(x[2] + a.R); }
+    if (DIM == 3) { xp[0] = (I)(x[0] + a.R); xp[1] = (I)(x[1] + a.R); xp[2] = (I)(x[2] + a.R); }
+    int64_t pc = 0;
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) pc = pc * P + (int64_t)xp[ax];
+    const int cidx = STAGE ? (e0 + (U0 ? a.H : 0)) * a.ls0 + (e1 + (U1 ? a.H : 0)) * a.ls1 + (e2 + a.H) : 0;
+    auto uval = [&](int c, int64_t gpad, int lidx) -> double {
+        return STAGE ? (double)tile[c * tot + lidx] : (double)ub[c * a.NP + gpad];
+    };
+    double u0[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) u0[c] = uval(c, pc, cidx);
+    const int k = kk[gi];
+    // coefficients b_j of the polynomial part in |z|^2j
+    double b[DEG / 2 + 1];
+    if (MODEL == 0 && a.poly_mode) {
+        const double im2 = (double)pwn[gi];
+        double pw = 1.0;
+#pragma unroll
+        for (int j = 0; j <= DEG / 2; ++j) { b[j] = a.poly[j] * pw; pw *= im2; }
+    } else {
+#pragma unroll
+        for (int j = 0; j <= DEG / 2; ++j) b[j] = j == 0 ? 1.0 : 0.0;
+    }
+    double G[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) G[c] = 0.0;
+    // Steps 1 and 3: walk the decomposition, gather the panels
+    auto emit = [&](int s, I r0, I r1, I lo, I hi) {
+        if (s == 0) {
+            // single nodes: the polynomial at the node's own offset
+            for (I j = lo; j <= hi; ++j) {
+                I y[3] = {0, 0, 0};
+                if (DIM == 1) y[0] = j;
+                if (DIM == 2) { y[0] = r0; y[1] = j; }
+                if (DIM == 3) { y[0] = r0; y[1] = r1; y[2] = j; }
+                double z[3] = {0.0, 0.0, 0.0};
+                int64_t gpad = 0;
+#pragma unroll
+                for (int ax = 0; ax < DIM; ++ax) {
+                    z[ax] = (double)(y[ax] - xp[ax]);
+                    gpad = gpad * P + (int64_t)y[ax];
+                }
+                int lidx = 0;
+                if (STAGE) {
+                    const int d0 = DIM == 3 ? (int)(y[0] - xp[0]) : 0;
+                    const int d1 = DIM >= 2 ? (int)(y[DIM - 2] - xp[DIM - 2]) : 0;
+                    const int d2 = (int)(y[DIM - 1] - xp[DIM - 1]);
+                    lidx = cidx + d0 * a.ls0 + d1 * a.ls1 + d2;
+                }
+                if (MODEL == 0) {
+                    double w = b[0];
+                    if (DEG > 0) {
+                        double q2 = 0.0;
+#pragma unroll
+                        for (int ax = 0; ax < DIM; ++ax) q2 += z[ax] * z[ax];
+                        double pw = q2;
+#pragma unroll
+                        for (int jj = 1; jj <= DEG / 2; ++jj) { w += b[jj] * pw; pw *= q2; }
+                    }
+                    G[0] += w * uval(0, gpad, lidx);
+                } else {
+                    double zu = 0.0;
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) zu += z[c] * uval(c, gpad, lidx);
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) G[c] += z[c] * zu;
+                }
+            }
+        } else {
+            const I side = (I)1 << s;
+            const I E = (I)(P >> s);
+            const double half = 0.5 * (double)(side - 1);
+            double D[3] = {0.0, 0.0, 0.0};
+            int64_t row = 0;
+            if (DIM == 2) { D[0] = (double)(r0 * side - xp[0]) + half; row = (int64_t)r0 * E; }
+            if (DIM == 3) {
+                D[0] = (double)(r0 * side - xp[0]) + half;
+                D[1] = (double)(r1 * side - xp[1]) + half;
+                row = ((int64_t)r0 * E + r1) * E;
+            }
+            const double* base = pyr + s_lev[s] + row * (NC * NM);
+            for (I j = lo; j <= hi; ++j) {
+                D[DIM - 1] = (double)(j * side - xp[DIM - 1]) + half;
+                const double* mu = base + (int64_t)j * (NC * NM);
+                double m[NC * NM];
+#pragma unroll
+                for (int q = 0; q < NC * NM; ++q) m[q] = mu[q];
+                if (MODEL == 0) G[0] += panel_poly<DIM, DEG>(m, D, b);
+                else panel_pd<DIM>(m, D, G);
+            }
+        }
+    };
+    decompose_runs<I>(DIM, (I)P, xp, (I)k, emit);
+    // eq. "nonlocalP": minus the polynomial summed over the full ball times u(x)
+    double res[NC];
+    const double pw0 = (MODEL == 0 && a.poly_mode) ? 1.0 : (double)pwn[gi];
+    if (MODEL == 0) {
+        double W = 0.0;
+#pragma unroll
+        for (int j = 0; j <= DEG / 2; ++j) W += b[j] * wtab[j * a.kmax1 + k];
+        res[0] = pw0 * (G[0] - W * u0[0]);
+    } else {
+        const double W = wtab[k] / (double)DIM;  // sum of z z^T over the ball = T2[k]/dim I
+#pragma unroll
+        for (int c = 0; c < NC; ++c) res[c] = pw0 * (G[c] - W * u0[c]);
+    }
+    if (KAPPA) {
+        // remainder kappa = w(z) - w(m) over the half ball, pairs {z, -z}
+        double kap[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) kap[c] = 0.0;
+        for (int p = 0; p < npairs; ++p) {
+            int off = 0, q;
+            double w;
+            int z[3];
+            if (staged_pairs) {
+                off = s_off[p];
+                q = s_q[p];
+                w = (double)s_w[p];
+                if (MODEL) { z[0] = s_z[3 * p]; z[1] = s_z[3 * p + 1]; z[2] = s_z[3 * p + 2]; }
+            } else {
+                const int4 o = pairs[p];
+                q = o.w;
+                w = (double)pairw[p];
+                z[0] = o.x; z[1] = o.y; z[2] = o.z;
+                off = o.x * a.ls0 + o.y * a.ls1 + o.z;
+            }
+            if (q > k) break;
+            int64_t goff = 0;
+            if (!STAGE) goff = ((int64_t)z[0] * P1 + z[1]) * P + z[2];
+            const double kw = w - pw0;
+            if (MODEL == 0) {
+                const double d = (uval(0, pc + goff, cidx + off) - u0[0]) + (uval(0, pc - goff, cidx - off) - u0[0]);
+                kap[0] += kw * d;
+            } else {
+                // box axes 3 - DIM .. 2 carry the components 0 .. DIM - 1
+                double zc[3] = {0.0, 0.0, 0.0}, proj = 0.0;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    zc[c] = (double)z[3 - DIM + c];
+                    const double d =
+                        (uval(c, pc + goff, cidx + off) - u0[c]) + (uval(c, pc - goff, cidx - off) - u0[c]);
+                    proj += zc[c] * d;
+                }
+                proj *= kw;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) kap[c] += proj * zc[c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) res[c] += kap[c];
+    }
+    const double s = (double)sc[gi];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) ob[c * a.N + gi] = (T)(s * res[c]);
 }
 
 // Records Step 1 panels for one node on the device (test hook).
@@ -263,9 +635,10 @@ struct RecordPanels {
     int32_t* out;
     int cap;
     int count;
-    __host__ __device__ inline void operator()(int s, int64_t r0, int64_t r1, int64_t lo, int64_t hi)
+    template <typename I>
+    __host__ __device__ inline void operator()(int s, I r0, I r1, I lo, I hi)
     {
-        for (int64_t j = lo; j <= hi; ++j) {
+        for (I j = lo; j <= hi; ++j) {
             if (count < cap) {
                 int32_t* rec = out + (size_t)count * (dim + 1);
                 rec[0] = s;
@@ -284,106 +657,231 @@ __global__ void k_record(int dim, int64_t n, int64_t x0, int64_t x1, int64_t x2,
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     int64_t x[3] = {x0, x1, x2};
     RecordPanels rp{dim, out, cap, 0};
-    decompose_runs(dim, n, x, k, rp);
+    decompose_runs<int64_t>(dim, n, x, k, rp);
     *count = rp.count;
 }
 
 // ------------------------------------------------------------------ host side
+// weight of the polynomial part per node: diffusion m^e, peridynamics m^(e-2)
 template <typename T>
-__global__ void k_split(const T* __restrict__ delta, int64_t N, int64_t n, double expo, double a0, T* __restrict__ out)
+__global__ void k_split(const T* __restrict__ delta, int64_t N, int64_t n, double expo, T* __restrict__ out)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     double m = (double)delta[i] * (double)n;
-    out[i] = (T)(a0 * pow(m, expo));
+    out[i] = (T)pow(m, expo);
 }
+
+// moment degree of a plan's hierarchical path (-1: not supported)
+static int fast_degree(const Plan& p)
+{
+    if (p.model == NDL_PERIDYNAMIC) return p.kernel == NDL_G_POLY ? -1 : 2;
+    if (p.kernel != NDL_G_POLY) return 0;
+    const int K = (int)p.poly.size() - 1;
+    const int kmax_dim[4] = {0, 3, 2, 1};
+    return K <= kmax_dim[p.dim] ? 2 * K : -1;
+}
+
+static int fast_ncomp(const Plan& p) { return p.model == NDL_PERIDYNAMIC ? p.dim : 1; }
 
 int fast_prepare(Plan& p, hipStream_t s, bool with_workspace)
 {
-    if (p.kernel == NDL_G_POLY && p.poly.size() > 1) {
-        set_error("hierarchical path: polynomial profiles of degree > 0 need panel moments (not built)");
+    if (p.form != NDL_ND) {
+        set_error("the hierarchical path is implemented for case (a)");
         return NDL_EUNSUPPORTED;
     }
-    int L = tree_height(p.n);
+    const int deg = fast_degree(p);
+    if (deg < 0) {
+        set_error(p.model == NDL_PERIDYNAMIC
+                      ? "hierarchical peridynamics needs a power profile"
+                      : "hierarchical path: polynomial profiles up to K = 3 (1D), 2 (2D), 1 (3D)");
+        return NDL_EUNSUPPORTED;
+    }
+    if (p.dim >= 2 && p.P > 32767) {
+        set_error("hierarchical path: padded extent above 32767");
+        return NDL_EUNSUPPORTED;
+    }
+    p.fast_deg = deg;
+    const int nm = nmono(p.dim, deg) * fast_ncomp(p);
+    int L = tree_height(p.P);
     p.fast_S = top_scale(p.dim, p.kmax, L);
+    if (p.fast_S >= kMaxLevels) { set_error("tree too deep"); return NDL_EUNSUPPORTED; }
     p.lev_off.assign(p.fast_S + 1, 0);
     p.lev_ext.assign(p.fast_S + 1, 0);
     int64_t tot = 0;
     for (int sc = 1; sc <= p.fast_S; ++sc) {
-        int64_t E = p.n >> sc;
+        int64_t E = p.P >> sc;
         int64_t c = 1;
         for (int a = 0; a < p.dim; ++a) c *= E;
         p.lev_off[sc] = tot;
         p.lev_ext[sc] = E;
-        tot += c;
+        tot += c * nm;
     }
-    if (p.fast_S > 23) { set_error("tree too deep"); return NDL_EUNSUPPORTED; }
     p.pyr_elems = tot;
     if (with_workspace) NDL_HIP(hipMalloc(&p.d_pyr, std::max<int64_t>(1, tot) * sizeof(double)));
-    // weight of the polynomial part per node: g(1) in units of the scale, m^e
-    NDL_HIP(hipMalloc(&p.d_split, p.N * elem_size(p.prec)));
-    double a0 = p.kernel == NDL_G_POLY ? p.poly[0] : 1.0;
-    double e = p.kernel == NDL_G_POLY ? 0.0 : p.expo;
-    int64_t nb = (p.N + 255) / 256;
-    if (p.prec == NDL_F64)
-        k_split<double><<<dim3((unsigned)nb), dim3(256), 0, s>>>((const double*)p.prob.delta, p.N, p.n, e, a0,
-                                                                (double*)p.d_split);
-    else
-        k_split<float><<<dim3((unsigned)nb), dim3(256), 0, s>>>((const float*)p.prob.delta, p.N, p.n, e, a0,
-                                                               (float*)p.d_split);
-    NDL_HIP(hipGetLastError());
-    // M(k) = number of lattice points with |z|^2 <= k, centre included
+    // per-node weight of the polynomial part (power profiles)
+    if (p.kernel != NDL_G_POLY) {
+        NDL_HIP(hipMalloc(&p.d_split, p.N * elem_size(p.prec)));
+        const double e = p.model == NDL_PERIDYNAMIC ? p.expo - 2.0 : p.expo;
+        int64_t nb = (p.N + 255) / 256;
+        if (p.prec == NDL_F64)
+            k_split<double><<<dim3((unsigned)nb), dim3(256), 0, s>>>((const double*)p.prob.delta, p.N, p.n, e,
+                                                                    (double*)p.d_split);
+        else
+            k_split<float><<<dim3((unsigned)nb), dim3(256), 0, s>>>((const float*)p.prob.delta, p.N, p.n, e,
+                                                                   (float*)p.d_split);
+        NDL_HIP(hipGetLastError());
+    }
+    // full-ball tables: row j holds sum_{|z|^2 <= k} |z|^2j (centre included)
+    // for j = 0..K (diffusion), or the single row sum |z|^2 (peridynamics)
     std::vector<Off> full = ball_offsets(p.dim, p.kmax, false);
-    std::vector<int32_t> cnt(p.kmax + 1, 0);
-    for (auto& o : full) cnt[o.q]++;
-    cnt[0] += 1;
-    for (int64_t k = 1; k <= p.kmax; ++k) cnt[k] += cnt[k - 1];
-    NDL_HIP(hipMalloc(&p.d_cntM, cnt.size() * sizeof(int32_t)));
-    NDL_HIP(hipMemcpy(p.d_cntM, cnt.data(), cnt.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    const int rows = p.model == NDL_PERIDYNAMIC ? 1 : deg / 2 + 1;
+    std::vector<double> tab((size_t)rows * (p.kmax + 1), 0.0);
+    for (int j = 0; j < rows; ++j) {
+        const int pw = p.model == NDL_PERIDYNAMIC ? 1 : j;
+        std::vector<double> shell(p.kmax + 1, 0.0);
+        if (pw == 0) shell[0] = 1.0;
+        for (auto& o : full) shell[o.q] += std::pow((double)o.q, pw);
+        double acc = 0.0;
+        for (int64_t k = 0; k <= p.kmax; ++k) {
+            acc += shell[k];
+            tab[(size_t)j * (p.kmax + 1) + k] = acc;
+        }
+    }
+    NDL_HIP(hipMalloc(&p.d_wtab, tab.size() * sizeof(double)));
+    NDL_HIP(hipMemcpy(p.d_wtab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
     NDL_HIP(hipStreamSynchronize(s));
     p.fast = true;
+    return NDL_OK;
+}
+
+static bool fast_has_kappa(const Plan& p)
+{
+    return !(p.kernel == NDL_G_POLY || (p.kernel == NDL_G_CONST && p.model == NDL_DIFFUSION));
+}
+
+// tile of Step 3 (256 nodes) and its LDS halo
+static void fast_geometry(const Plan& p, FastArgs& a, bool stage)
+{
+    int E[3];
+    if (p.dim == 1) { E[0] = 1; E[1] = 1; E[2] = 256; }
+    else if (p.dim == 2) { E[0] = 1; E[1] = 4; E[2] = 64; }
+    else { E[0] = 2; E[1] = 2; E[2] = 64; }
+    const int used[3] = {p.dim >= 3, p.dim >= 2, 1};
+    a.H = stage ? p.J : 0;
+    for (int ax = 0; ax < 3; ++ax) {
+        a.E[ax] = E[ax];
+        a.ext[ax] = used[ax] ? (int)p.n : 1;
+        a.L[ax] = used[ax] ? E[ax] + 2 * a.H : 1;
+        a.tiles[ax] = (a.ext[ax] + E[ax] - 1) / E[ax];
+    }
+    a.ls1 = a.L[2];
+    a.ls0 = a.L[1] * a.L[2];
+}
+
+static size_t fast_lds(const Plan& p, const FastArgs& a)
+{
+    return (size_t)a.L[0] * a.L[1] * a.L[2] * fast_ncomp(p) * elem_size(p.prec);
+}
+
+// the remainder is staged with the tile when its halo fits the LDS
+static bool fast_stage(const Plan& p)
+{
+    if (!fast_has_kappa(p)) return false;
+    FastArgs a{};
+    fast_geometry(p, a, true);
+    return fast_lds(p, a) <= 96 * 1024;
+}
+
+template <typename T, int DIM, int MODEL, int DEG, bool KAPPA, bool STAGE>
+static int step3_launch(Plan& p, const FastArgs& a, const T* ub, T* ob, const double* pyr, hipStream_t s)
+{
+    auto fn = k_fast_step3<T, DIM, MODEL, DEG, KAPPA, STAGE>;
+    const size_t lds = STAGE ? fast_lds(p, a) : 0;
+    if (lds > 48 * 1024)
+        NDL_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const int nb = a.tiles[0] * a.tiles[1] * a.tiles[2];
+    const T* pw = p.kernel == NDL_G_POLY ? (const T*)p.d_invm2 : (const T*)p.d_split;
+    fn<<<dim3((unsigned)nb), dim3(256), lds, s>>>(ub, ob, pyr, a, p.d_k, (const T*)p.d_scale, pw, p.d_wtab,
+                                                  p.d_pairs, (const T*)p.d_pairw, p.npairs);
+    NDL_HIP(hipGetLastError());
+    return NDL_OK;
+}
+
+template <typename T, int DIM, int MODEL, int DEG>
+static int step3_dispatch(Plan& p, const FastArgs& a, const T* ub, T* ob, const double* pyr, hipStream_t s)
+{
+    if (!fast_has_kappa(p)) return step3_launch<T, DIM, MODEL, DEG, false, false>(p, a, ub, ob, pyr, s);
+    if (a.H > 0) return step3_launch<T, DIM, MODEL, DEG, true, true>(p, a, ub, ob, pyr, s);
+    return step3_launch<T, DIM, MODEL, DEG, true, false>(p, a, ub, ob, pyr, s);
+}
+
+template <typename T, int DIM, int DEG, int NC>
+static int step2_launch(Plan& p, const T* ub, double* pyr, hipStream_t s)
+{
+    for (int sc = 1; sc <= p.fast_S; ++sc) {
+        const int64_t E = p.lev_ext[sc];
+        int64_t c = 1;
+        for (int q = 0; q < DIM; ++q) c *= E;
+        if (c == 0) continue;
+        const unsigned nb = (unsigned)((c + 255) / 256);
+        if (sc == 1)
+            k_mom_first<T, DIM, DEG, NC><<<dim3(nb), dim3(256), 0, s>>>(ub, p.NP, pyr + p.lev_off[1], p.P, E, c);
+        else
+            k_mom_next<DIM, DEG, NC><<<dim3(nb), dim3(256), 0, s>>>(pyr + p.lev_off[sc - 1], pyr + p.lev_off[sc],
+                                                                    p.lev_ext[sc - 1], E,
+                                                                    0.25 * (double)((int64_t)1 << sc), c);
+        NDL_HIP(hipGetLastError());
+    }
+    return NDL_OK;
+}
+
+template <typename T, int DIM, int MODEL, int DEG>
+static int launch_fast_k(Plan& p, const void* u, void* Lu, int batch, hipStream_t s, double* pyr)
+{
+    constexpr int NC = MODEL ? DIM : 1;
+    FastArgs a{};
+    fast_geometry(p, a, fast_stage(p));
+    a.R = p.R;
+    a.S = p.fast_S;
+    a.poly_mode = p.kernel == NDL_G_POLY ? 1 : 0;
+    a.P = (int)std::min<int64_t>(p.P, 0x7fffffff);
+    a.kmax1 = (int)p.kmax + 1;
+    a.N = p.N;
+    a.NP = p.NP;
+    for (int sc = 1; sc <= p.fast_S; ++sc) a.lev[sc] = p.lev_off[sc];
+    for (size_t j = 0; j < p.poly.size() && j < 8; ++j) a.poly[j] = p.poly[j];
+    for (int b = 0; b < batch; ++b) {
+        const T* ub = static_cast<const T*>(u) + (int64_t)b * NC * p.NP;
+        T* ob = static_cast<T*>(Lu) + (int64_t)b * NC * p.N;
+        NDL_TRY((step2_launch<T, DIM, DEG, NC>(p, ub, pyr, s)));
+        NDL_TRY((step3_dispatch<T, DIM, MODEL, DEG>(p, a, ub, ob, pyr, s)));
+    }
     return NDL_OK;
 }
 
 template <typename T>
 static int launch_fast_t(Plan& p, const void* u, void* Lu, int batch, hipStream_t s, double* pyr)
 {
-    FastArgs a{};
-    a.dim = p.dim;
-    a.R = p.R;
-    a.S = p.fast_S;
-    a.n = p.n;
-    a.P = p.P;
-    for (int sc = 1; sc <= p.fast_S; ++sc) a.off[sc] = p.lev_off[sc];
-    bool kappa = !(p.kernel == NDL_G_CONST || p.kernel == NDL_G_POLY);
-    for (int b = 0; b < batch; ++b) {
-        const T* ub = static_cast<const T*>(u) + (int64_t)b * p.NP;
-        T* ob = static_cast<T*>(Lu) + (int64_t)b * p.N;
-        for (int sc = 1; sc <= p.fast_S; ++sc) {
-            int64_t E = p.lev_ext[sc];
-            int64_t c = 1;
-            for (int q = 0; q < p.dim; ++q) c *= E;
-            if (c == 0) continue;
-            unsigned nb = (unsigned)((c + 255) / 256);
-            if (sc == 1)
-                k_pyr_first<T><<<dim3(nb), dim3(256), 0, s>>>(ub, pyr + p.lev_off[1], p.dim, p.n, p.R, E, c);
-            else
-                k_pyr_next<<<dim3(nb), dim3(256), 0, s>>>(pyr + p.lev_off[sc - 1], pyr + p.lev_off[sc],
-                                                          p.dim, p.lev_ext[sc - 1], E, c);
-            NDL_HIP(hipGetLastError());
-        }
-        unsigned nb = (unsigned)((p.N + 255) / 256);
-        if (kappa)
-            k_fast_gather<T, true><<<dim3(nb), dim3(256), 0, s>>>(ub, ob, pyr, p.d_k, (const T*)p.d_scale,
-                                                                 (const T*)p.d_split, p.d_cntM,
-                                                                 p.d_pairs, (const T*)p.d_pairw, p.npairs, a, p.N);
-        else
-            k_fast_gather<T, false><<<dim3(nb), dim3(256), 0, s>>>(ub, ob, pyr, p.d_k, (const T*)p.d_scale,
-                                                                  (const T*)p.d_split, p.d_cntM,
-                                                                  p.d_pairs, (const T*)p.d_pairw, p.npairs, a, p.N);
-        NDL_HIP(hipGetLastError());
+    const int d = p.fast_deg;
+    if (p.model == NDL_PERIDYNAMIC) {
+        if (p.dim == 2) return launch_fast_k<T, 2, 1, 2>(p, u, Lu, batch, s, pyr);
+        if (p.dim == 3) return launch_fast_k<T, 3, 1, 2>(p, u, Lu, batch, s, pyr);
+    } else if (p.dim == 1) {
+        if (d == 0) return launch_fast_k<T, 1, 0, 0>(p, u, Lu, batch, s, pyr);
+        if (d == 2) return launch_fast_k<T, 1, 0, 2>(p, u, Lu, batch, s, pyr);
+        if (d == 4) return launch_fast_k<T, 1, 0, 4>(p, u, Lu, batch, s, pyr);
+        if (d == 6) return launch_fast_k<T, 1, 0, 6>(p, u, Lu, batch, s, pyr);
+    } else if (p.dim == 2) {
+        if (d == 0) return launch_fast_k<T, 2, 0, 0>(p, u, Lu, batch, s, pyr);
+        if (d == 2) return launch_fast_k<T, 2, 0, 2>(p, u, Lu, batch, s, pyr);
+        if (d == 4) return launch_fast_k<T, 2, 0, 4>(p, u, Lu, batch, s, pyr);
+    } else {
+        if (d == 0) return launch_fast_k<T, 3, 0, 0>(p, u, Lu, batch, s, pyr);
+        if (d == 2) return launch_fast_k<T, 3, 0, 2>(p, u, Lu, batch, s, pyr);
     }
-    return NDL_OK;
+    set_error("internal: no hierarchical kernel for this plan");
+    return NDL_EUNSUPPORTED;
 }
 
 int launch_fast(Plan& p, const void* u, void* Lu, int batch, hipStream_t s, double* pyr)
@@ -424,16 +922,17 @@ int fast_static_workspace(double** ptr, int64_t* capacity_elems)
     return NDL_OK;
 }
 
-// Device-side record of one node's decomposition, for the parity test.
+// Device-side record of one node's decomposition (in the tree over the padded
+// box: node coordinates shifted by the collar), for the parity test.
 int fast_decomp_host(Plan& p, const int64_t* node, int32_t* out, int cap, int* count)
 {
     int64_t x[3] = {0, 0, 0};
     for (int a = 0; a < p.dim; ++a) {
         if (node[a] < 0 || node[a] >= p.n) { set_error("node outside the grid"); return NDL_EINVAL; }
-        x[a] = node[a];
+        x[a] = node[a] + p.R;
     }
     int64_t gi = 0;
-    for (int a = 0; a < p.dim; ++a) gi = gi * p.n + x[a];
+    for (int a = 0; a < p.dim; ++a) gi = gi * p.n + node[a];
     int32_t k = 0;
     NDL_HIP(hipMemcpy(&k, p.d_k + gi, sizeof(int32_t), hipMemcpyDeviceToHost));
     int32_t* d_out = nullptr;
@@ -441,12 +940,13 @@ int fast_decomp_host(Plan& p, const int64_t* node, int32_t* out, int cap, int* c
     size_t bytes = (size_t)std::max(cap, 1) * (p.dim + 1) * sizeof(int32_t);
     NDL_HIP(hipMalloc(&d_out, bytes));
     NDL_HIP(hipMalloc(&d_cnt, sizeof(int32_t)));
-    k_record<<<1, 64>>>(p.dim, p.n, x[0], x[1], x[2], k, d_out, cap, d_cnt);
+    k_record<<<1, 64>>>(p.dim, p.P, x[0], x[1], x[2], k, d_out, cap, d_cnt);
     NDL_HIP(hipGetLastError());
     int32_t c = 0;
     NDL_HIP(hipMemcpy(&c, d_cnt, sizeof(int32_t), hipMemcpyDeviceToHost));
-    if (cap > 0) NDL_HIP(hipMemcpy(out, d_out, (size_t)std::min(c, cap) * (p.dim + 1) * sizeof(int32_t),
-                                  hipMemcpyDeviceToHost));
+    if (cap > 0)
+        NDL_HIP(hipMemcpy(out, d_out, (size_t)std::min(c, cap) * (p.dim + 1) * sizeof(int32_t),
+                          hipMemcpyDeviceToHost));
     NDL_HIP(hipFree(d_out));
     NDL_HIP(hipFree(d_cnt));
     *count = c;
@@ -470,7 +970,7 @@ extern "C" int ndl_decompose_node(int32_t dim, int64_t n, const int64_t* node, i
         x[a] = node[a];
     }
     RecordPanels rp{dim, panels, cap, 0};
-    decompose_runs(dim, n, x, k, rp);
+    decompose_runs<int64_t>(dim, n, x, k, rp);
     *count = rp.count;
     return NDL_OK;
 }

@@ -342,11 +342,14 @@ def test_device_decomposition_matches_oracle():
     c = torch.ones((n, n), dtype=torch.float64, device="cuda")
     plan = ndl.ndl_plan_create(ndl.make_problem(2, n, 21, d, c, prec=ndl.NDL_F64, kernel=ndl.NDL_G_CONST),
                                want_fast=True, keep=(d, c))
-    L = O.tree_levels(n)
+    # the tree covers the padded box: the node sits at node + R in a domain of n + 2R
+    R = 21
+    P = n + 2 * R
+    L = O.tree_levels(P)
     for node in [(0, 0), (47, 47), (10, 30), (24, 24), (3, 44)]:
         k = O.cutoff(m[node] / n, n)
         got = sorted((L - s, j) for s, j in ndl.ndl_fast_decomposition(plan, node))
-        assert got == sorted(O.decompose(2, n, node, k))
+        assert got == sorted(O.decompose(2, P, (node[0] + R, node[1] + R), k))
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -394,8 +397,6 @@ def test_graph_replay_matches_eager(fast):
     n, R = 130, 6
     prec = ndl.NDL_F32K if not fast else ndl.NDL_F32C
     delta, c, u = rand_problem(2, n, R, 2.0, 6.0, seed=77, smooth=True)
-    if fast:
-        u = zero_collar(u, R, 2)  # the hierarchical path is the zero-collar (Dirichlet) operator
     d_d, d_c, d_u = dev(delta, prec), dev(c, prec), dev(u, prec)
     plan = ndl.ndl_plan_create(ndl.make_problem(2, n, R, d_d, d_c, prec=prec), want_fast=int(fast), keep=(d_d, d_c))
     out = torch.zeros((n, n), dtype=d_u.dtype, device="cuda")

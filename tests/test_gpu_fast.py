@@ -1,0 +1,144 @@
+"""The hierarchical evaluation of Section 3 (ndl_apply_fast) against the FP64
+direct-sum oracle: volume-constraint data in the collar, peridynamics through
+panel moments of degree 2, polynomial profiles with K > 0 through moments of
+degree 2K (1D up to K = 3, the paper's second example; 2D up to K = 2; 3D
+K = 1), and the 2D workload at full size."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1905_08375_amd import fields as F
+from paper_1905_08375_amd import ndl
+from gpuhelp import TOL, gpu_apply, oracle_apply, rand_problem, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+PRECS = [ndl.NDL_F64, ndl.NDL_F32C, ndl.NDL_F32K]
+# p^6 matching 1/s to third order at s = 1, and lower-degree even polynomials
+P6 = (35 / 16, -35 / 16, 21 / 16, -5 / 16)
+P4 = (15 / 8, -5 / 4, 3 / 8)
+P2 = (1.5, -0.5)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("dim,n,R,mlo,mhi,kernel", [
+    (2, 90, 7, 2.0, 6.0, ndl.NDL_G_FRAC),
+    (2, 70, 12, 4.0, 12.0, ndl.NDL_G_CONST),
+    (1, 300, 30, 5.0, 30.0, ndl.NDL_G_INV_R),
+    (3, 21, 4, 2.0, 4.0, ndl.NDL_G_FRAC),
+])
+def test_fast_with_collar_data_equals_direct(prec, dim, n, R, mlo, mhi, kernel):
+    """Non-zero volume-constraint data in the collar (the tree covers the
+    padded box, so the collar enters as in the direct sum), ragged grids."""
+    say(f"case fast collar dim={dim} n={n} kernel={kernel} prec={prec}")
+    delta, c, u = rand_problem(dim, n, R, mlo, mhi, seed=310 + n, smooth=True)
+    kw = dict(kernel=kernel)
+    got, info = gpu_apply(dim, n, R, delta, c, u, prec, fast=True, **kw)
+    ref = oracle_apply(dim, n, R, delta, c, u, prec, **kw)
+    err = rel_l2(got, ref)
+    say("  rel l2", err, "levels", info.fast_levels)
+    assert err <= TOL[prec]
+
+
+def _pd_fields(n, R, B, seed):
+    g = np.random.default_rng(seed)
+    X = F.mesh(n, 2)
+    delta = (7.5 + 4.5 * np.sin(2 * np.pi * X[0]) * np.cos(2 * np.pi * X[1])) / n
+    c = g.uniform(0.5, 2.0, (n, n))
+    Xp = F.padded_coords(n, 2, R)
+    u = []
+    for b in range(B):
+        th = 1e-3 * g.standard_normal()
+        rot = np.stack([-th * (Xp[1] - 0.5), th * (Xp[0] - 0.5)])
+        u.append(np.stack([F.pad(F.grf(n, 2, 1e-3, 0.1, 9, 7 * b + q), R) for q in range(2)]) + rot)
+    u = np.stack(u)
+    return delta, c, u
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("kernel", [ndl.NDL_G_INV_R, ndl.NDL_G_CONST])
+def test_fast_peridynamics_equals_direct(prec, kernel):
+    """Peridynamics through Step 2 moments of degree 2 of both displacement
+    components (sum w^alpha u_c, |alpha| <= 2) and the lattice constant
+    sum z z^T = T2[k]/d I, the remainder summed directly; horizons of 3 to 12
+    nodes, rigid rotation plus a random field, collar data, batch of 2."""
+    say(f"case fast pd kernel={kernel} prec={prec}")
+    n, R, B = 77, 12, 2
+    delta, c, u = _pd_fields(n, R, B, 41)
+    kw = dict(model=ndl.NDL_PERIDYNAMIC, kernel=kernel)
+    got, info = gpu_apply(2, n, R, delta, c, u, prec, batch=B, fast=True, **kw)
+    for b in range(B):
+        ref = oracle_apply(2, n, R, delta, c, u[b], prec, **kw)
+        err = rel_l2(got[b], ref)
+        say("  field", b, "rel l2", err, "levels", info.fast_levels)
+        assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("dim,n,R,mlo,mhi,poly,norm", [
+    (1, 400, 40, 8.0, 40.0, P2, ndl.NDL_NORM_NONE),
+    (1, 400, 40, 8.0, 40.0, P4, ndl.NDL_NORM_CONTINUOUS),
+    (1, 333, 50, 10.0, 50.0, P6, ndl.NDL_NORM_DISCRETE),
+    (2, 80, 10, 3.0, 10.0, P2, ndl.NDL_NORM_DISCRETE),
+    (2, 61, 9, 3.0, 9.0, P4, ndl.NDL_NORM_NONE),
+    (3, 20, 4, 2.0, 4.0, P2, ndl.NDL_NORM_CONTINUOUS),
+])
+def test_fast_polynomial_profiles_equal_direct(prec, dim, n, R, mlo, mhi, poly, norm):
+    """Profiles p(r) = sum_j a_j r^2j with K = 1..3: the whole kernel goes
+    through panel moments of degree 2K (no remainder), with collar data."""
+    K = len(poly) - 1
+    say(f"case fast poly dim={dim} n={n} K={K} prec={prec}")
+    delta, c, u = rand_problem(dim, n, R, mlo, mhi, seed=520 + n + K, smooth=True)
+    kw = dict(kernel=ndl.NDL_G_POLY, poly=poly, norm=norm)
+    got, info = gpu_apply(dim, n, R, delta, c, u, prec, fast=True, **kw)
+    ref = oracle_apply(dim, n, R, delta, c, u, prec, **kw)
+    err = rel_l2(got, ref)
+    say("  rel l2", err, "levels", info.fast_levels)
+    assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("N", [512, 4096])
+def test_fast_example2(N):
+    """The paper's second example: 1D, delta(x) = delta0 (1 + exp(-20 (x - 1/2)^2)),
+    delta0 = 1/4 (horizons of N/4 to N/2 nodes), C = 1, the kernel p^6(|s|/delta)
+    with K = 3 and the bare 1/delta^3 scaling, zero volume constraint; FP64."""
+    say(f"case example2 N={N}")
+    delta = F.example2_delta(N)
+    R = int(np.ceil(delta.max() * N)) + 1
+    c = np.ones(N)
+    g = np.random.default_rng(N)
+    u = np.zeros(N + 2 * R)
+    u[R:R + N] = g.standard_normal(N)
+    kw = dict(kernel=ndl.NDL_G_POLY, poly=P6, norm=ndl.NDL_NORM_NONE)
+    got, info = gpu_apply(1, N, R, delta, c, u, ndl.NDL_F64, fast=True, **kw)
+    ref = oracle_apply(1, N, R, delta, c, u, ndl.NDL_F64, **kw)
+    err = rel_l2(got, ref)
+    say("  rel l2", err, "levels", info.fast_levels)
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("prec", [ndl.NDL_F64, ndl.NDL_F32C])
+def test_fast_2d_workload_full_size(prec):
+    """The 2D workload at full size (1024^2, m in [2, 6], r^-3 profile,
+    lognormal c), through the hierarchical path."""
+    say(f"case fast c2 full prec={prec}")
+    w = F.diffusion_2d()
+    n, R = 1024, 6
+    u = F.pad(w["u"], R)
+    got, info = gpu_apply(2, n, R, w["delta"], w["coef"], u, prec, fast=True)
+    ref = oracle_apply(2, n, R, w["delta"], w["coef"], u, prec)
+    err = rel_l2(got, ref)
+    say("  rel l2", err, "levels", info.fast_levels)
+    assert err <= TOL[prec]
+
+
+def test_fast_rejects_unsupported_plans():
+    import torch
+    n = 16
+    d = torch.full((n, n), 3.0 / n, dtype=torch.float64, device="cuda")
+    c = torch.ones((n, n), dtype=torch.float64, device="cuda")
+    for kw in [dict(form=ndl.NDL_DIV), dict(kernel=ndl.NDL_G_POLY, poly=(1.0, 0.5, 0.2, 0.1)),
+               dict(model=ndl.NDL_PERIDYNAMIC, kernel=ndl.NDL_G_POLY, poly=P2)]:
+        with pytest.raises(ndl.NdlError) as e:
+            ndl.ndl_plan_create(ndl.make_problem(2, n, 4, d, c, prec=ndl.NDL_F64, **kw), want_fast=1, keep=(d, c))
+        assert e.value.code == ndl.NDL_EUNSUPPORTED
