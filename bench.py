@@ -283,7 +283,10 @@ def bench_sweep(n=1024, ms=(2, 4, 8, 16, 32, 64), example1=True):
     return {"n": n, "profile": "const (p^0 exact)", "precision": "fp32 data, fp64 panel sums", "points": out}
 
 
-def bench_pd(steps=5, batch=8, n=2048):
+def bench_pd(steps=5, batch=8, n=2048, fast=False):
+    """Peridynamics on 8 fields of 2048^2 (m in [3, 12], Voronoi c, rotation plus
+    a random field): the direct sum (FP32, Kahan), or the hierarchical path
+    (degree-2 panel moments per component, F32C) with fast=True."""
     import torch
     from paper_1905_08375_amd import fields as F
     from paper_1905_08375_amd import ndl
@@ -292,15 +295,87 @@ def bench_pd(steps=5, batch=8, n=2048):
     d = torch.from_numpy(w["delta"].astype(np.float32)).cuda()
     c = torch.from_numpy(w["coef"].astype(np.float32)).cuda()
     u = torch.from_numpy(w["u"].astype(np.float32)).cuda()
+    prec = ndl.NDL_F32C if fast else ndl.NDL_F32K
     plan = ndl.ndl_plan_create(ndl.make_problem(2, n, R, d, c, model=ndl.NDL_PERIDYNAMIC, kernel=ndl.NDL_G_INV_R,
-                                                prec=ndl.NDL_F32K), keep=(d, c))
-    ndl.ndl_autotune(plan)
+                                                prec=prec), want_fast=int(fast), keep=(d, c))
+    if not fast:
+        ndl.ndl_autotune(plan)
     out = torch.empty((batch, 2, n, n), dtype=torch.float32, device="cuda")
-    secs, _ = timed(lambda: ndl.ndl_apply(plan, u, out, batch), steps, 1)
+    fn = (lambda: ndl.ndl_apply_fast(plan, u, out, batch)) if fast else (lambda: ndl.ndl_apply(plan, u, out, batch))
+    secs, _ = timed(fn, steps, 1)
     per = secs / steps
     inf = plan.info()
-    return {"ms_per_batch_apply": per * 1e3, "gpoint_fields_per_s": batch * n * n / per / 1e9,
-            "pairs_per_point": inf.pairs_per_point, "tile": [inf.tile_x, inf.tile_y]}
+    res = {"ms_per_batch_apply": per * 1e3, "gpoint_fields_per_s": batch * n * n / per / 1e9,
+           "pairs_per_point": inf.pairs_per_point}
+    if fast:
+        res["levels"] = inf.fast_levels
+    else:
+        res["tile"] = [inf.tile_x, inf.tile_y]
+    plan.close()
+    return res
+
+
+def bench_example2(sizes=(4096, 8192, 16384)):
+    """The paper's second example at growing N: 1D, delta(x) = (1/4)(1 +
+    exp(-20 (x - 1/2)^2)) (N/4 to N/2 neighbours per side), the K = 3
+    polynomial p^6, zero volume constraint, FP64; the hierarchical path (panel
+    moments of degree 6) against the direct sum."""
+    import torch
+    from paper_1905_08375_amd import fields as F
+    from paper_1905_08375_amd import ndl
+    p6 = (35 / 16, -35 / 16, 21 / 16, -5 / 16)
+    pts = []
+    for N in sizes:
+        delta = F.example2_delta(N)
+        R = int(np.ceil(delta.max() * N)) + 1
+        d = torch.from_numpy(delta).cuda()
+        c = torch.ones(N, dtype=torch.float64, device="cuda")
+        g = np.random.default_rng(N)
+        u = torch.zeros(N + 2 * R, dtype=torch.float64, device="cuda")
+        u[R:R + N] = torch.from_numpy(g.standard_normal(N)).cuda()
+        plan = ndl.ndl_plan_create(ndl.make_problem(1, N, R, d, c, kernel=ndl.NDL_G_POLY, poly=p6,
+                                                    norm=ndl.NDL_NORM_NONE, prec=ndl.NDL_F64), want_fast=1,
+                                   keep=(d, c))
+        o = torch.empty(N, dtype=torch.float64, device="cuda")
+        row = {"N": N, "neighbours_per_node": plan.info().pairs_per_point}
+        for nm, fn in [("fast_ms", lambda: ndl.ndl_apply_fast(plan, u, o, 1)),
+                       ("direct_ms", lambda: ndl.ndl_apply(plan, u, o, 1))]:
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            first = time.perf_counter() - t0
+            k = int(max(2, min(50, 0.25 / max(first, 1e-6))))
+            secs, _ = timed(fn, k, 1)
+            row[nm] = secs / k * 1e3
+        row["fast_speedup"] = row["direct_ms"] / row["fast_ms"]
+        plan.close()
+        pts.append(row)
+    return {"profile": "p^6 (K = 3)", "precision": "fp64", "points": pts}
+
+
+def bench_big(steps=200, n=4096):
+    """The headline kernel on a 4096^2 grid with the same horizon and
+    coefficient recipe (m in [2, 6]): launch latency amortised over 16x the
+    nodes."""
+    import torch
+    from paper_1905_08375_amd import fields as F
+    from paper_1905_08375_amd import ndl
+    R = 6
+    w = F.diffusion_2d(n=n)
+    d = torch.from_numpy(w["delta"].astype(np.float32)).cuda()
+    c = torch.from_numpy(w["coef"].astype(np.float32)).cuda()
+    u = torch.from_numpy(F.pad(w["u"], R).astype(np.float32)).cuda()
+    plan = ndl.ndl_plan_create(ndl.make_problem(2, n, R, d, c, prec=ndl.NDL_F32K), keep=(d, c))
+    ndl.ndl_autotune(plan)
+    out = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    secs, _ = timed_graph(lambda: ndl.ndl_apply(plan, u, out, 1), steps, 10)
+    per = secs / steps
+    inf = plan.info()
+    plan.close()
+    return {"n": n, "us_per_apply": per * 1e6, "gpoint_per_s": n * n / per / 1e9,
+            "hbm_frac": 16.0 * n * n / per / 1e9 / HBM_PEAK_GBS, "tile": [inf.tile_x, inf.tile_y]}
 
 
 def bench_1d(steps=200):
@@ -354,7 +429,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-rows", action="store_true", help="headline only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", default="", help="run one row only (profiling): cg64, pcg3d, net, pd, sweep, fast, f64, 1d")
+    ap.add_argument("--only", default="", help="run one row only (profiling): cg64, pcg3d, net, pd, pdfast, ex2, big, sweep, fast, f64, 1d")
     ap.add_argument("--cg-iters", type=int, default=0, help="cap the solver iterations (profiling)")
     ap.add_argument("--variant", type=int, default=None,
                     help="fixed tile variant for the headline instead of the autotuner's (profiling runs)")
@@ -370,7 +445,8 @@ def main():
     if args.only:
         fn = {"cg64": lambda: bench_solve(max_iter=args.cg_iters or None),
               "pcg3d": lambda: bench_pcg_3d(max_iter=args.cg_iters or None),
-              "net": bench_net, "pd": bench_pd, "1d": bench_1d, "sweep": bench_sweep, "f64": lambda: bench_apply(ndl.NDL_F64, False, args.steps, args.warmup)["seconds"],
+              "net": bench_net, "pd": bench_pd, "pdfast": lambda: bench_pd(fast=True), "ex2": bench_example2,
+              "big": bench_big, "1d": bench_1d, "sweep": bench_sweep, "f64": lambda: bench_apply(ndl.NDL_F64, False, args.steps, args.warmup)["seconds"],
               "fast": lambda: bench_apply(ndl.NDL_F32C, True, args.steps, args.warmup)["seconds"]}[args.only]
         print(json.dumps({"only": args.only, "result": fn()}, default=str), flush=True)
         return
@@ -408,8 +484,14 @@ def main():
         rows["sweep_const_2d_1024"] = bench_sweep()
         log("row: 1D 4096 direct FP64")
         rows["direct_1d_4096_f64"] = bench_1d()
+        log("row: direct apply at 4096^2")
+        rows["direct_f32k_4096"] = bench_big()
         log("row: peridynamics 2048^2 x 8 fields")
         rows["pd_2048x8_f32k"] = bench_pd()
+        log("row: peridynamics 2048^2 x 8 fields, hierarchical")
+        rows["pd_2048x8_fast_f32c"] = bench_pd(fast=True)
+        log("row: the paper's second example (1D, K = 3) at growing N")
+        rows["example2_1d_k3"] = bench_example2()
         log("row: 64 batched solves to 1e-8")
         rows["cg_64_uneven_to_1e-8"] = bench_solve()
         log("row: 3D 256^3 PCG to 1e-8, plain vs learned")

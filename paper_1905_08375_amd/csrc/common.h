@@ -31,6 +31,10 @@ int hip_fail(hipError_t e, const char* what, const char* file, int line);
     } while (0)
 
 // ------------------------------------------------------------------ lattice
+// Largest integer cutoff k = ceil((delta n)^2) - 1 a plan accepts (horizons up
+// to 8192 nodes): tables indexed by k stay below 2^26 entries.
+constexpr int kMaxCutoff = 1 << 26;
+
 constexpr int cisqrt(int64_t k)
 {
     int j = 0;
@@ -102,6 +106,7 @@ struct Plan {
     double* d_pyr = nullptr;   // panel moments, FP64, all levels
     int64_t pyr_elems = 0;
     double* d_wtab = nullptr;  // full-ball sums of the polynomial part per cutoff k
+    int64_t fast_wrow = 0;     // row length of d_wtab
 };
 
 // host helpers implemented in the .hip files

@@ -53,7 +53,8 @@ __global__ __launch_bounds__(256) void k_cutoffs(const T* __restrict__ delta, in
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
         double a = (double)delta[i] * (double)n;
         double t = a * a;
-        int k = (int)ceil(t) - 1;
+        // cutoffs past kMaxCutoff are reported as kMaxCutoff + 1 (the plan rejects them)
+        int k = t > (double)kMaxCutoff ? kMaxCutoff + 1 : (int)ceil(t) - 1;
         kout[i] = k;
         kmx = max(kmx, k);
         kmn = min(kmn, k);
@@ -478,6 +479,10 @@ static int plan_fields_t(Plan& p, hipStream_t s)
     NDL_HIP(hipFree(d_ext));
     p.kmax = ext[0];
     p.kmin = ext[1];
+    if (p.kmax > kMaxCutoff) {
+        set_error("horizon too wide: (delta n)^2 above %d somewhere (the per-cutoff tables are bounded)", kMaxCutoff);
+        return NDL_EUNSUPPORTED;
+    }
     if (p.kmin < 0) {
         set_error("horizon below one grid spacing somewhere (k < 0): delta must be > 0");
         return NDL_EINVAL;

@@ -325,7 +325,7 @@ struct FastArgs {
     int tiles[3];
     int ls0, ls1;               // LDS strides of box axes 0, 1
     int ext[3];                 // grid extent per box axis (1 for unused)
-    int kmax1;                  // kmax + 1 (row length of the full-ball tables)
+    int64_t wrow;               // row length of the full-ball tables (kmax + 1; 1D: isqrt(kmax) + 1)
     int64_t N, NP;
     int64_t lev[kMaxLevels];    // offsets (doubles) of levels 1..S in the pyramid
     double poly[8];             // a_j of the polynomial profile
@@ -565,16 +565,18 @@ __global__ __launch_bounds__(256) void k_fast_step3(const T* __restrict__ u, T* 
         }
     };
     decompose_runs<I>(DIM, (I)P, xp, (I)k, emit);
-    // eq. "nonlocalP": minus the polynomial summed over the full ball times u(x)
+    // eq. "nonlocalP": minus the polynomial summed over the full ball times u(x);
+    // the tables are indexed by k (1D: by the ball's reach isqrt(k))
+    const int64_t kw = DIM == 1 ? (int64_t)isqrt_i<int64_t>((int64_t)k) : (int64_t)k;
     double res[NC];
     const double pw0 = (MODEL == 0 && a.poly_mode) ? 1.0 : (double)pwn[gi];
     if (MODEL == 0) {
         double W = 0.0;
 #pragma unroll
-        for (int j = 0; j <= DEG / 2; ++j) W += b[j] * wtab[j * a.kmax1 + k];
+        for (int j = 0; j <= DEG / 2; ++j) W += b[j] * wtab[(int64_t)j * a.wrow + kw];
         res[0] = pw0 * (G[0] - W * u0[0]);
     } else {
-        const double W = wtab[k] / (double)DIM;  // sum of z z^T over the ball = T2[k]/dim I
+        const double W = wtab[kw] / (double)DIM;  // sum of z z^T over the ball = T2[k]/dim I
 #pragma unroll
         for (int c = 0; c < NC; ++c) res[c] = pw0 * (G[c] - W * u0[c]);
     }
@@ -602,10 +604,10 @@ __global__ __launch_bounds__(256) void k_fast_step3(const T* __restrict__ u, T* 
             if (q > k) break;
             int64_t goff = 0;
             if (!STAGE) goff = ((int64_t)z[0] * P1 + z[1]) * P + z[2];
-            const double kw = w - pw0;
+            const double kwt = w - pw0;
             if (MODEL == 0) {
                 const double d = (uval(0, pc + goff, cidx + off) - u0[0]) + (uval(0, pc - goff, cidx - off) - u0[0]);
-                kap[0] += kw * d;
+                kap[0] += kwt * d;
             } else {
                 // box axes 3 - DIM .. 2 carry the components 0 .. DIM - 1
                 double zc[3] = {0.0, 0.0, 0.0}, proj = 0.0;
@@ -616,7 +618,7 @@ __global__ __launch_bounds__(256) void k_fast_step3(const T* __restrict__ u, T* 
                         (uval(c, pc + goff, cidx + off) - u0[c]) + (uval(c, pc - goff, cidx - off) - u0[c]);
                     proj += zc[c] * d;
                 }
-                proj *= kw;
+                proj *= kwt;
 #pragma unroll
                 for (int c = 0; c < NC; ++c) kap[c] += proj * zc[c];
             }
@@ -733,21 +735,25 @@ int fast_prepare(Plan& p, hipStream_t s, bool with_workspace)
         NDL_HIP(hipGetLastError());
     }
     // full-ball tables: row j holds sum_{|z|^2 <= k} |z|^2j (centre included)
-    // for j = 0..K (diffusion), or the single row sum |z|^2 (peridynamics)
+    // for j = 0..K (diffusion), or the single row sum |z|^2 (peridynamics).
+    // In 1D the ball of cutoff k is |z| <= isqrt(k), so the rows are indexed
+    // by that reach instead of k.
     std::vector<Off> full = ball_offsets(p.dim, p.kmax, false);
     const int rows = p.model == NDL_PERIDYNAMIC ? 1 : deg / 2 + 1;
-    std::vector<double> tab((size_t)rows * (p.kmax + 1), 0.0);
+    const int64_t wrow = p.dim == 1 ? (int64_t)cisqrt(p.kmax) + 1 : p.kmax + 1;
+    std::vector<double> tab((size_t)rows * wrow, 0.0);
     for (int j = 0; j < rows; ++j) {
         const int pw = p.model == NDL_PERIDYNAMIC ? 1 : j;
-        std::vector<double> shell(p.kmax + 1, 0.0);
+        std::vector<double> shell(wrow, 0.0);
         if (pw == 0) shell[0] = 1.0;
-        for (auto& o : full) shell[o.q] += std::pow((double)o.q, pw);
+        for (auto& o : full) shell[p.dim == 1 ? (int64_t)std::abs(o.z0) : o.q] += std::pow((double)o.q, pw);
         double acc = 0.0;
-        for (int64_t k = 0; k <= p.kmax; ++k) {
+        for (int64_t k = 0; k < wrow; ++k) {
             acc += shell[k];
-            tab[(size_t)j * (p.kmax + 1) + k] = acc;
+            tab[(size_t)j * wrow + k] = acc;
         }
     }
+    p.fast_wrow = wrow;
     NDL_HIP(hipMalloc(&p.d_wtab, tab.size() * sizeof(double)));
     NDL_HIP(hipMemcpy(p.d_wtab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
     NDL_HIP(hipStreamSynchronize(s));
@@ -846,7 +852,7 @@ static int launch_fast_k(Plan& p, const void* u, void* Lu, int batch, hipStream_
     a.S = p.fast_S;
     a.poly_mode = p.kernel == NDL_G_POLY ? 1 : 0;
     a.P = (int)std::min<int64_t>(p.P, 0x7fffffff);
-    a.kmax1 = (int)p.kmax + 1;
+    a.wrow = p.fast_wrow;
     a.N = p.N;
     a.NP = p.NP;
     for (int sc = 1; sc <= p.fast_S; ++sc) a.lev[sc] = p.lev_off[sc];

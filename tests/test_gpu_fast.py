@@ -97,7 +97,7 @@ def test_fast_polynomial_profiles_equal_direct(prec, dim, n, R, mlo, mhi, poly, 
     assert err <= TOL[prec]
 
 
-@pytest.mark.parametrize("N", [512, 4096])
+@pytest.mark.parametrize("N", [512, 4096, 16384])
 def test_fast_example2(N):
     """The paper's second example: 1D, delta(x) = delta0 (1 + exp(-20 (x - 1/2)^2)),
     delta0 = 1/4 (horizons of N/4 to N/2 nodes), C = 1, the kernel p^6(|s|/delta)
@@ -130,6 +130,19 @@ def test_fast_2d_workload_full_size(prec):
     err = rel_l2(got, ref)
     say("  rel l2", err, "levels", info.fast_levels)
     assert err <= TOL[prec]
+
+
+def test_horizon_beyond_the_cutoff_tables_is_rejected():
+    """A 1D horizon of 16384 nodes ((delta n)^2 above 2^26): the plan refuses
+    it before building per-cutoff tables of that length."""
+    import torch
+    N = 32768
+    d = torch.full((N,), 0.5, dtype=torch.float64, device="cuda")
+    c = torch.ones(N, dtype=torch.float64, device="cuda")
+    with pytest.raises(ndl.NdlError) as e:
+        ndl.ndl_plan_create(ndl.make_problem(1, N, N // 2 + 1, d, c, kernel=ndl.NDL_G_CONST, prec=ndl.NDL_F64),
+                            want_fast=1, keep=(d, c))
+    assert e.value.code == ndl.NDL_EUNSUPPORTED
 
 
 def test_fast_rejects_unsupported_plans():
