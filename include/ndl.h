@@ -30,8 +30,8 @@
  *  - Layouts are C order with the last axis fastest.  A state u is the padded
  *    box [batch][ncomp][(n+2R)^dim] whose collar of width R = collar holds the
  *    volume-constraint data (zero for the Dirichlet problem of Section 3);
- *    outputs are [batch][ncomp][n^dim].  ncomp = 2 for peridynamics (component
- *    a is the displacement along axis a), else 1.
+ *    outputs are [batch][ncomp][n^dim].  ncomp = dim for peridynamics
+ *    (component a is the displacement along axis a), else 1.
  *  - Element type follows prec: NDL_F64 = double everywhere; NDL_F32C and
  *    NDL_F32K = float storage with compensated accumulation inside the sums.
  */
@@ -59,12 +59,14 @@ enum {
  * pairs add exactly in FP64).  NDL_F32K: FP32 storage and FP32 arithmetic
  * with Kahan-compensated accumulation. */
 typedef enum { NDL_F64 = 0, NDL_F32C = 1, NDL_F32K = 2 } ndl_prec;
-typedef enum { NDL_DIFFUSION = 0, NDL_PERIDYNAMIC = 1 } ndl_model; /* PD: dim == 2 */
+typedef enum { NDL_DIFFUSION = 0, NDL_PERIDYNAMIC = 1 } ndl_model; /* PD: dim 2 or 3 */
 typedef enum { NDL_ND = 0, NDL_DIV = 1 } ndl_form;                 /* Section 2 cases (a), (b) */
 /* Radial profile g(r), r = |y-x|/delta:  CONST 1 (the p^0 of Section 3);
- * INV_R 1/r (eq. "kernelgamma"); FRAC r^-(dim+2s) (fractional micromodulus,
- * Section 1); POLY sum_j poly[j] r^(2j) (the even p^{2K} of Section 3). */
-typedef enum { NDL_G_CONST = 0, NDL_G_INV_R = 1, NDL_G_FRAC = 2, NDL_G_POLY = 3 } ndl_kernel;
+ * INV_R 1/r and CONE (1 - r)/r (the two micromoduli of eq. "kernelgamma");
+ * FRAC r^-(dim+2s) (fractional micromodulus, Section 1); POLY
+ * sum_j poly[j] r^(2j) (the even p^{2K} of Section 3).  Case (b) takes the
+ * power profiles CONST, INV_R, FRAC; the hierarchical path all but CONE. */
+typedef enum { NDL_G_CONST = 0, NDL_G_INV_R = 1, NDL_G_FRAC = 2, NDL_G_POLY = 3, NDL_G_CONE = 4 } ndl_kernel;
 /* Constant A: DISCRETE makes the lattice second moment equal m2_target, so
  * L|x|^2 = 2 dim c exactly (the local limit C Delta u of case (a));
  * CONTINUOUS does the same for the integral over the ball; NONE is the bare

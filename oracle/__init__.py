@@ -19,7 +19,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libndl_oracle.so")
 
-KERNELS = {"const": 0, "inv_r": 1, "frac": 2, "poly": 3}
+KERNELS = {"const": 0, "inv_r": 1, "frac": 2, "poly": 3, "cone": 4}
 NORMS = {"discrete": 0, "continuous": 1, "none": 2}
 
 
@@ -125,17 +125,17 @@ def profile(p: Problem, r: float) -> float:
 
 
 def apply(p: Problem, delta, coef, u_padded) -> np.ndarray:
-    """Direct sum L u.  u_padded: (ncomp, P, ..) with P = n + 2R (ncomp = 2 for
+    """Direct sum L u.  u_padded: (ncomp, P, ..) with P = n + 2R (ncomp = dim for
     peridynamics, axis may be omitted for diffusion).  Returns (ncomp?, n, ..)."""
     s, keep = _prob(p)
     delta = _f64(delta); coef = _f64(coef); u = _f64(u_padded)
-    ncomp = 2 if p.model == "peridynamic" else 1
+    ncomp = p.dim if p.model == "peridynamic" else 1
     out = np.zeros((ncomp,) + (p.n,) * p.dim)
     fn = lib().or_apply_div if p.form == "div" else lib().or_apply_nd
     rc = fn(C.byref(s), _d(delta), _d(coef), _d(u), _d(out))
     if rc != 0:
         raise ValueError("oracle: collar narrower than the horizon")
-    return out if ncomp == 2 else out[0]
+    return out if p.model == "peridynamic" else out[0]
 
 
 def div_diag(p: Problem, delta, coef) -> np.ndarray:

@@ -32,9 +32,9 @@ typedef struct {
     int dim;            /* 1, 2 or 3 */
     int64_t n;          /* nodes per axis */
     int R;              /* collar width of the padded state */
-    int model;          /* 0: scalar diffusion, 1: linear bond-based peridynamics (dim 2) */
+    int model;          /* 0: scalar diffusion, 1: linear bond-based peridynamics (dim 2 or 3) */
     int form;           /* 0: case (a), C and delta depend on x only; 1: case (b), symmetrised */
-    int kernel;         /* profile g: 0 const, 1 1/r, 2 r^-(d+2s), 3 even polynomial p(r) */
+    int kernel;         /* profile g: 0 const, 1 1/r, 2 r^-(d+2s), 3 even polynomial p(r), 4 cone (1-r)/r */
     double s;           /* fractional order for kernel 2 */
     int K;              /* kernel 3: p(r) = sum_{j<=K} poly[j] r^(2j) */
     const double* poly;
@@ -67,9 +67,10 @@ static int64_t isqrt_floor(int64_t k)
 }
 
 /* ------------------------------------------------------------------ profile */
-/* Radial profiles g(r), r = |y-x|/delta (Section 2: eq. "kernelgamma" gives 1/r;
- * the fractional type r^-(d+2s) is the micromodulus family of Section 1; the
- * even polynomial p^{2K} is the truncated part of the splitting in Section 3). */
+/* Radial profiles g(r), r = |y-x|/delta (Section 2: eq. "kernelgamma" gives 1/r
+ * and the conical (1-r)/r, both on r < 1; the fractional type r^-(d+2s) is the
+ * micromodulus family of Section 1; the even polynomial p^{2K} is the truncated
+ * part of the splitting in Section 3). */
 double or_profile(const or_problem* p, double r)
 {
     switch (p->kernel) {
@@ -81,6 +82,7 @@ double or_profile(const or_problem* p, double r)
         for (int j = 0; j <= p->K; j++) { acc += p->poly[j] * pw; pw *= r2; }
         return acc;
     }
+    case 4: return (1.0 - r) / r;
     }
     return 0.0;
 }
@@ -106,6 +108,7 @@ static double radial_moment(const or_problem* p)
         for (int j = 0; j <= p->K; j++) acc += p->poly[j] / (2.0 * j + d + 2.0);
         return acc;
     }
+    case 4: return 1.0 / (d + 1.0) - 1.0 / (d + 2.0); /* int_0^1 (1-r) r^d dr */
     }
     return 0.0;
 }
@@ -161,7 +164,7 @@ double or_norm(const or_problem* p, int64_t k, double m, double delta)
     if (p->norm == 2) return 1.0 / pow(delta, d + 2.0);
     if (p->norm == 1)
         return p->m2 / (sphere_area(d) * pow(delta, d + 2.0) * radial_moment(p));
-    if (g_memo && p->kernel != 3 && k <= g_memo->kmax) {
+    if (g_memo && p->kernel <= 2 && k <= g_memo->kmax) {
         double e = power_exponent(p);
         double T = g_memo->T[k];
         return T > 0.0 ? p->m2 * pow(m, e) / (pow(h, (double)d + 2.0) * T) : INFINITY;
@@ -221,7 +224,7 @@ static int64_t npoints(const or_problem* p)
 /* ------------------------------------------------------------------ apply */
 /* Case (a), eq. "eq:diffusion" with C = C(x), delta = delta(x):
  *   L u_i = sum_{0<|z|^2<=k_i} c_i A_i g(|z|/m_i) (u_{i+z} - u_i) h^d.
- * Peridynamics (Section 1, linear bond force):
+ * Peridynamics (Section 1, linear bond force), ncomp = d displacement components:
  *   L u_i = sum_z c_i A_i g(|z|/m_i) [e.(u_{i+z} - u_i)] e h^d,  e = z/|z|.
  * u: [ncomp][padded box], out: [ncomp][n^d].  Returns 0, or -1 if the collar
  * is narrower than the widest horizon. */
@@ -246,7 +249,7 @@ int or_apply_nd(const or_problem* p, const double* delta, const double* coef,
         int64_t J = isqrt_floor(k);
         int64_t lo1 = d >= 2 ? -J : 0, hi1 = d >= 2 ? J : 0;
         int64_t lo2 = d >= 3 ? -J : 0, hi2 = d >= 3 ? J : 0;
-        double acc0 = 0.0, acc1 = 0.0;
+        double acc[3] = {0.0, 0.0, 0.0};
         int64_t xi = pidx(p, x);
         for (z[0] = -J; z[0] <= J; z[0]++)
             for (z[1] = lo1; z[1] <= hi1; z[1]++)
@@ -258,18 +261,19 @@ int or_apply_nd(const or_problem* p, const double* delta, const double* coef,
                     double len = sqrt((double)q);
                     double w = coef[i] * A * or_profile(p, len / m);
                     if (p->model == 0) {
-                        acc0 += w * (u[yi] - u[xi]) * hd;
+                        acc[0] += w * (u[yi] - u[xi]) * hd;
                     } else {
-                        double e0 = (double)z[0] / len, e1 = (double)z[1] / len;
-                        double du0 = u[yi] - u[xi];
-                        double du1 = u[Pn + yi] - u[Pn + xi];
-                        double proj = e0 * du0 + e1 * du1;
-                        acc0 += w * proj * e0 * hd;
-                        acc1 += w * proj * e1 * hd;
+                        /* bond direction e and the projection e.(u(y) - u(x)) */
+                        double e[3], proj = 0.0;
+                        for (int c = 0; c < d; c++) {
+                            e[c] = (double)z[c] / len;
+                            proj += e[c] * (u[c * Pn + yi] - u[c * Pn + xi]);
+                        }
+                        for (int c = 0; c < d; c++) acc[c] += w * proj * e[c] * hd;
                     }
                 }
-        out[i] = acc0;
-        if (p->model == 1) out[N + i] = acc1;
+        int nc = p->model == 1 ? d : 1;
+        for (int c = 0; c < nc; c++) out[c * N + i] = acc[c];
     }
     return 0;
 }
@@ -321,7 +325,7 @@ int or_apply_div(const or_problem* p, const double* delta, const double* coef,
     int64_t J = div_reach(p, delta);
     if (J > p->R) return -1;
     moment_memo mm = {0, NULL};
-    if (p->norm == 0 && p->kernel != 3) { memo_build(p, max_cutoff(p, delta), &mm); g_memo = &mm; }
+    if (p->norm == 0 && p->kernel <= 2) { memo_build(p, max_cutoff(p, delta), &mm); g_memo = &mm; }
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; i++) {
         int64_t x[3], y[3], z[3] = {0, 0, 0}, kij;
@@ -355,7 +359,7 @@ int or_div_diag(const or_problem* p, const double* delta, const double* coef, do
     double hd = pow(1.0 / (double)p->n, (double)d);
     int64_t J = div_reach(p, delta);
     moment_memo mm = {0, NULL};
-    if (p->norm == 0 && p->kernel != 3) { memo_build(p, max_cutoff(p, delta), &mm); g_memo = &mm; }
+    if (p->norm == 0 && p->kernel <= 2) { memo_build(p, max_cutoff(p, delta), &mm); g_memo = &mm; }
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; i++) {
         int64_t x[3], y[3], z[3] = {0, 0, 0}, kij;

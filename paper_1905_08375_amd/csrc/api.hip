@@ -44,8 +44,8 @@ static int validate(const ndl_problem* q)
     double tot = std::pow((double)P, q->dim);
     if (q->collar < 0 || tot > 4.0e9) { set_error("collar/grid out of range"); return NDL_EINVAL; }
     if (q->model != NDL_DIFFUSION && q->model != NDL_PERIDYNAMIC) { set_error("bad model"); return NDL_EINVAL; }
-    if (q->model == NDL_PERIDYNAMIC && q->dim != 2) {
-        set_error("peridynamic model is implemented for dim == 2");
+    if (q->model == NDL_PERIDYNAMIC && q->dim < 2) {
+        set_error("peridynamic model is implemented for dim 2 and 3");
         return NDL_EUNSUPPORTED;
     }
     if (q->form != NDL_ND && q->form != NDL_DIV) { set_error("bad form"); return NDL_EINVAL; }
@@ -53,7 +53,11 @@ static int validate(const ndl_problem* q)
         set_error("case (b) is implemented for the diffusion model");
         return NDL_EUNSUPPORTED;
     }
-    if (q->kernel < 0 || q->kernel > NDL_G_POLY) { set_error("bad kernel"); return NDL_EINVAL; }
+    if (q->kernel < 0 || q->kernel > NDL_G_CONE) { set_error("bad kernel"); return NDL_EINVAL; }
+    if (q->kernel == NDL_G_CONE && q->form == NDL_DIV) {
+        set_error("case (b) supports the power profiles only");
+        return NDL_EUNSUPPORTED;
+    }
     if (q->kernel == NDL_G_FRAC && !(q->s >= 0.0 && q->s < 1.0)) {
         set_error("fractional order s must be in [0, 1)");
         return NDL_EINVAL;
@@ -95,7 +99,7 @@ int ndl_plan_create(const ndl_problem* prob, int want_fast, ndl_plan* out, void*
     p->kernel = prob->kernel;
     p->norm = prob->norm;
     p->prec = prob->prec;
-    p->ncomp = prob->model == NDL_PERIDYNAMIC ? 2 : 1;
+    p->ncomp = prob->model == NDL_PERIDYNAMIC ? prob->dim : 1;
     p->N = 1;
     p->NP = 1;
     p->P = p->n + 2 * p->R;
@@ -106,6 +110,7 @@ int ndl_plan_create(const ndl_problem* prob, int want_fast, ndl_plan* out, void*
     case NDL_G_CONST: p->expo = 0.0; break;
     case NDL_G_INV_R: p->expo = -1.0; break;
     case NDL_G_FRAC: p->expo = -((double)p->dim + 2.0 * prob->s); break;
+    case NDL_G_CONE: p->expo = -1.0; break;  // the 1/r factor (weights formed per pair)
     default: p->expo = 0.0; break;
     }
     hipStream_t s = (hipStream_t)stream;

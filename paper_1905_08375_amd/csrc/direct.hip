@@ -93,7 +93,8 @@ struct ScaleArgs {
 
 // Per-node scale s_i of case (a): L u_i = s_i sum_z w(z) (u_{i+z} - u_i), with
 // w(z) = |z|^expo for power profiles (s_i = c_i A_i m_i^-expo h^d) and
-// w(z) = p(|z|^2/m_i^2) for POLY (s_i = c_i A_i h^d).
+// w(z) = g(|z|/m_i) for POLY and CONE (s_i = c_i A_i h^d), whose weights the
+// kernels form per pair from a per-node value (POLY 1/m_i^2, CONE m_i).
 template <typename T>
 __global__ void k_scales(const T* __restrict__ delta, const T* __restrict__ coef, const int32_t* __restrict__ kk,
                          int64_t N, ScaleArgs a, const double* __restrict__ Ttab, const int4* __restrict__ full,
@@ -109,7 +110,7 @@ __global__ void k_scales(const T* __restrict__ delta, const T* __restrict__ coef
     double dd2 = pow(d, (double)(a.dim + 2));
     int k = kk[i];
     double s;
-    if (a.kernel != NDL_G_POLY) {
+    if (a.kernel <= NDL_G_FRAC) {
         if (a.norm == NDL_NORM_DISCRETE)
             s = Ttab[k] > 0.0 ? c * a.m2 * nn * nn / Ttab[k] : 0.0;
         else if (a.norm == NDL_NORM_CONTINUOUS)
@@ -117,15 +118,20 @@ __global__ void k_scales(const T* __restrict__ delta, const T* __restrict__ coef
         else
             s = c * pow(m, -a.expo) * hd / dd2;
     } else {
+        // profiles evaluated per pair: POLY p(|z|^2/m^2), CONE (m - |z|)/|z|
         double im2 = 1.0 / (m * m);
+        auto gval = [&](int q) {
+            if (a.kernel == NDL_G_CONE) return m / sqrt((double)q) - 1.0;
+            double r2 = q * im2, pw = 1.0, g = 0.0;
+            for (int j = 0; j <= a.K; j++) { g += a.poly[j] * pw; pw *= r2; }
+            return g;
+        };
         if (a.norm == NDL_NORM_DISCRETE) {
             double tot = 0.0;
             for (int p = 0; p < nfull; p++) {
                 int q = full[p].w;
                 if (q > k) break;
-                double r2 = q * im2, pw = 1.0, g = 0.0;
-                for (int j = 0; j <= a.K; j++) { g += a.poly[j] * pw; pw *= r2; }
-                tot += g * q;
+                tot += gval(q) * q;
             }
             s = tot != 0.0 ? c * a.m2 * nn * nn / tot : 0.0;
         } else if (a.norm == NDL_NORM_CONTINUOUS) {
@@ -133,7 +139,7 @@ __global__ void k_scales(const T* __restrict__ delta, const T* __restrict__ coef
         } else {
             s = c * hd / dd2;
         }
-        invm2[i] = (T)im2;
+        invm2[i] = (T)(a.kernel == NDL_G_CONE ? m : im2);
     }
     sout[i] = (T)s;
 }
@@ -213,24 +219,26 @@ __device__ __forceinline__ void stage_grid(T* __restrict__ lds, const T* __restr
 // ------------------------------------------------------------------ case (a)
 // Generic direct sum over the half ball: pairs {z, -z} share |z| and so their
 // weight; the second difference (u_+ - u_0) + (u_- - u_0) keeps the
-// cancellation exact for smooth u.  MODEL 1 adds the bond projection
-// [z.(D)] z of the peridynamic force, with D the paired second difference
-// of each displacement component.
-template <typename T, int MODEL, bool POLY>
+// cancellation exact for smooth u.  NC > 1 is peridynamics with NC = dim
+// displacement components (box axes 3 - NC .. 2 carry components 0 .. NC-1):
+// the bond projection [z.D] z of the paired second differences D.  PROF: 0
+// tabulated power weights, 1 POLY p(|z|^2/m^2), 2 CONE (m - |z|)/|z|, the last
+// two formed per pair from the per-node value pv (1/m^2 or m).
+template <typename T, int NC, int PROF>
 __global__ __launch_bounds__(256) void k_direct_nd(const T* __restrict__ u, T* __restrict__ out,
                                                    const int32_t* __restrict__ kk, const T* __restrict__ sc,
-                                                   const T* __restrict__ invm2, const int4* __restrict__ pairs,
+                                                   const T* __restrict__ pv, const int4* __restrict__ pairs,
                                                    const T* __restrict__ pw, int npairs, ScaleArgs a, Box B,
                                                    int64_t N, int64_t NPad, int split)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* tile = reinterpret_cast<T*>(smem_raw);
-    const int ncomp = MODEL ? 2 : 1;
+    constexpr bool PD = NC > 1;
     int tot = B.L[0] * B.L[1] * B.L[2];
     // the half-ball table with this tile's flat LDS offsets (uniform reads in the pair loop)
     constexpr int kStage = 512;
     __shared__ int s_off[kStage], s_q[kStage];
-    __shared__ short s_zy[kStage], s_zx[kStage];
+    __shared__ short s_z[3][kStage];
     __shared__ T s_w[kStage];
     const bool staged = npairs <= kStage;
     if (staged)
@@ -238,8 +246,9 @@ __global__ __launch_bounds__(256) void k_direct_nd(const T* __restrict__ u, T* _
             int4 o = pairs[p];
             s_off[p] = o.x * B.ls0 + o.y * B.ls1 + o.z;
             s_q[p] = o.w;
-            s_zy[p] = (short)o.y;
-            s_zx[p] = (short)o.z;
+            s_z[0][p] = (short)o.x;
+            s_z[1][p] = (short)o.y;
+            s_z[2][p] = (short)o.z;
             s_w[p] = pw[p];
         }
     int nb = B.tiles[0] * B.tiles[1] * B.tiles[2];
@@ -248,9 +257,9 @@ __global__ __launch_bounds__(256) void k_direct_nd(const T* __restrict__ u, T* _
     int t1 = (t / B.tiles[2]) % B.tiles[1];
     int t0i = t / (B.tiles[2] * B.tiles[1]);
     int org[3] = {t0i * B.E[0], t1 * B.E[1], t2 * B.E[2]};
-    const T* ub = u + (int64_t)blockIdx.y * ncomp * NPad;
-    T* ob = out + (int64_t)blockIdx.y * ncomp * N;
-    for (int c = 0; c < ncomp; c++) stage(tile + c * tot, ub + c * NPad, B, org);
+    const T* ub = u + (int64_t)blockIdx.y * NC * NPad;
+    T* ob = out + (int64_t)blockIdx.y * NC * N;
+    for (int c = 0; c < NC; c++) stage(tile + c * tot, ub + c * NPad, B, org);
     __syncthreads();
 
     // `split` lanes (a power of two dividing 64) share one node: lane `sub`
@@ -269,55 +278,69 @@ __global__ __launch_bounds__(256) void k_direct_nd(const T* __restrict__ u, T* _
         int k = valid ? kk[gi] : -1;
         int kw = wave_max(k);
         int cidx = (e0 + B.halo[0]) * B.ls0 + (e1 + B.halo[1]) * B.ls1 + (e2 + B.halo[2]);
-        T u0 = tile[cidx];
-        T v0 = MODEL ? tile[tot + cidx] : T(0);
-        T im2 = POLY && valid ? invm2[gi] : T(0);
-        Acc<T> A0, A1;
+        T u0[NC];
+#pragma unroll
+        for (int c = 0; c < NC; c++) u0[c] = tile[c * tot + cidx];
+        const T pn = PROF != 0 && valid ? pv[gi] : T(0);
+        Acc<T> A[NC];
         for (int p = sub, cnt = 0; p < npairs; p += split, cnt++) {
-            int4 o;
+            int zz[3];
             int off, qw;
             T w;
             if (staged) {
                 qw = s_q[p];
                 off = s_off[p];
                 w = s_w[p];
-                o = make_int4(0, MODEL ? (int)s_zy[p] : 0, MODEL ? (int)s_zx[p] : 0, qw);
+                zz[0] = s_z[0][p]; zz[1] = s_z[1][p]; zz[2] = s_z[2][p];
             } else {
-                o = pairs[p];
+                const int4 o = pairs[p];
                 qw = o.w;
                 off = o.x * B.ls0 + o.y * B.ls1 + o.z;
                 w = pw[p];
+                zz[0] = o.x; zz[1] = o.y; zz[2] = o.z;
             }
             if (qw > kw) break;
             if (qw <= k) {
-                if (POLY) {
-                    T r2 = (T)o.w * im2, g = 0, pp = 1;
+                if (PROF == 1) {
+                    T r2 = (T)qw * pn, g = 0, pp = 1;
                     for (int j = 0; j <= a.K; j++) { g += (T)a.poly[j] * pp; pp *= r2; }
-                    w = MODEL ? g / (T)o.w : g;
+                    w = PD ? g / (T)qw : g;
+                } else if (PROF == 2) {
+                    const T g = pn / sqrt((T)qw) - T(1);
+                    w = PD ? g / (T)qw : g;
                 }
-                T d0 = (tile[cidx + off] - u0) + (tile[cidx - off] - u0);
-                if (MODEL == 0) {
-                    A0.fma_(w, d0);
+                if (!PD) {
+                    const T d0 = (tile[cidx + off] - u0[0]) + (tile[cidx - off] - u0[0]);
+                    A[0].fma_(w, d0);
                 } else {
-                    T d1 = (tile[tot + cidx + off] - v0) + (tile[tot + cidx - off] - v0);
-                    // in 2D the box axes 1, 2 carry the components 0, 1
-                    T z0 = (T)o.y, z1 = (T)o.z;
-                    T proj = w * (z0 * d0 + z1 * d1);
-                    A0.fma_(proj, z0);
-                    A1.fma_(proj, z1);
+                    T zc[NC], proj = 0;
+#pragma unroll
+                    for (int c = 0; c < NC; c++) {
+                        zc[c] = (T)zz[3 - NC + c];
+                        const T d = (tile[c * tot + cidx + off] - u0[c]) + (tile[c * tot + cidx - off] - u0[c]);
+                        proj += zc[c] * d;
+                    }
+                    proj *= w;
+#pragma unroll
+                    for (int c = 0; c < NC; c++) A[c].fma_(proj, zc[c]);
                 }
             }
-            if ((cnt & 7) == 7) { A0.flush(); if (MODEL) A1.flush(); }
+            if ((cnt & 7) == 7) {
+#pragma unroll
+                for (int c = 0; c < NC; c++) A[c].flush();
+            }
         }
-        T v0s = A0.value(), v1s = MODEL ? A1.value() : T(0);
+        T v[NC];
+#pragma unroll
+        for (int c = 0; c < NC; c++) v[c] = A[c].value();
         for (int o = split >> 1; o >= 1; o >>= 1) {
-            v0s += __shfl_xor(v0s, o, 64);
-            if (MODEL) v1s += __shfl_xor(v1s, o, 64);
+#pragma unroll
+            for (int c = 0; c < NC; c++) v[c] += __shfl_xor(v[c], o, 64);
         }
         if (valid && sub == 0) {
-            T s = sc[gi];
-            ob[gi] = s * v0s;
-            if (MODEL) ob[N + gi] = s * v1s;
+            const T s = sc[gi];
+#pragma unroll
+            for (int c = 0; c < NC; c++) ob[c * N + gi] = s * v[c];
         }
     }
 }
@@ -415,6 +438,7 @@ static double radial_moment(const Plan& p)
     case NDL_G_CONST: return 1.0 / (d + 2.0);
     case NDL_G_INV_R: return 1.0 / (d + 1.0);
     case NDL_G_FRAC: return 1.0 / (2.0 - 2.0 * p.prob.s);
+    case NDL_G_CONE: return 1.0 / (d + 1.0) - 1.0 / (d + 2.0);
     default: {
         double acc = 0.0;
         for (size_t j = 0; j < p.poly.size(); j++) acc += p.poly[j] / (2.0 * j + d + 2.0);
@@ -557,7 +581,7 @@ static int plan_fields_t(Plan& p, hipStream_t s)
     }
     if (p.form == NDL_ND) {
         NDL_HIP(hipMalloc(&p.d_scale, p.N * elem_size(p.prec)));
-        if (p.kernel == NDL_G_POLY) NDL_HIP(hipMalloc(&p.d_invm2, p.N * elem_size(p.prec)));
+        if (p.kernel == NDL_G_POLY || p.kernel == NDL_G_CONE) NDL_HIP(hipMalloc(&p.d_invm2, p.N * elem_size(p.prec)));
         ScaleArgs a = scale_args(p);
         k_scales<T><<<dim3((unsigned)nblk), dim3(256), 0, s>>>(delta, coef, p.d_k, p.N, a, d_T, p.d_full, p.nfull,
                                                               (T*)p.d_scale, (T*)p.d_invm2);
@@ -581,6 +605,7 @@ static void default_tile(const Plan& p, int* E)
     }
     if (p.dim == 1) { E[0] = 1; E[1] = 1; E[2] = 512; }
     else if (p.dim == 2) { E[0] = 1; E[1] = 16; E[2] = 64; }
+    else if (p.model == NDL_PERIDYNAMIC) { E[0] = 2; E[1] = 4; E[2] = 32; }  // three staged components
     else { E[0] = 4; E[1] = 8; E[2] = 32; }
 }
 
@@ -595,35 +620,37 @@ static int tile_and_split(const Plan& p, int* E)
     return E[2] <= 256 && 256 % E[2] == 0 ? std::min(64, 256 / E[2]) : 1;
 }
 
-template <typename T>
-static int launch_direct_t(Plan& p, const void* u, void* Lu, int batch, hipStream_t s)
+template <typename T, int NC, int PROF>
+static int launch_direct_k(Plan& p, const void* u, void* Lu, int batch, hipStream_t s)
 {
     int E[3];
     const int split = tile_and_split(p, E);
     Box B = make_box(p.dim, p.n, p.R, p.J, E[0], E[1], E[2]);
     int nb = B.tiles[0] * B.tiles[1] * B.tiles[2];
-    size_t lds = (size_t)B.L[0] * B.L[1] * B.L[2] * sizeof(T) * p.ncomp;
+    size_t lds = (size_t)B.L[0] * B.L[1] * B.L[2] * sizeof(T) * NC;
+    NDL_TRY(lds_check((const void*)k_direct_nd<T, NC, PROF>, lds));
     ScaleArgs a = scale_args(p);
-    if (p.model == NDL_PERIDYNAMIC)
-        NDL_TRY(lds_check(p.kernel == NDL_G_POLY ? (const void*)k_direct_nd<T, 1, true> : (const void*)k_direct_nd<T, 1, false>, lds));
-    else
-        NDL_TRY(lds_check(p.kernel == NDL_G_POLY ? (const void*)k_direct_nd<T, 0, true> : (const void*)k_direct_nd<T, 0, false>, lds));
-    dim3 grid((unsigned)nb, (unsigned)batch);
-    const T* uu = static_cast<const T*>(u);
-    T* oo = static_cast<T*>(Lu);
-    bool poly = p.kernel == NDL_G_POLY;
-#define NDL_LAUNCH(M, PL)                                                                          \
-    k_direct_nd<T, M, PL><<<grid, dim3(256), lds, s>>>(uu, oo, p.d_k, (const T*)p.d_scale,         \
-                                                       (const T*)p.d_invm2, p.d_pairs,             \
-                                                       (const T*)p.d_pairw, p.npairs, a, B, p.N, p.NP, split)
-    if (p.model == NDL_PERIDYNAMIC) {
-        if (poly) NDL_LAUNCH(1, true); else NDL_LAUNCH(1, false);
-    } else {
-        if (poly) NDL_LAUNCH(0, true); else NDL_LAUNCH(0, false);
-    }
-#undef NDL_LAUNCH
+    k_direct_nd<T, NC, PROF><<<dim3((unsigned)nb, (unsigned)batch), dim3(256), lds, s>>>(
+        static_cast<const T*>(u), static_cast<T*>(Lu), p.d_k, (const T*)p.d_scale, (const T*)p.d_invm2, p.d_pairs,
+        (const T*)p.d_pairw, p.npairs, a, B, p.N, p.NP, split);
     NDL_HIP(hipGetLastError());
     return NDL_OK;
+}
+
+template <typename T, int NC>
+static int launch_direct_nc(Plan& p, const void* u, void* Lu, int batch, hipStream_t s)
+{
+    if (p.kernel == NDL_G_POLY) return launch_direct_k<T, NC, 1>(p, u, Lu, batch, s);
+    if (p.kernel == NDL_G_CONE) return launch_direct_k<T, NC, 2>(p, u, Lu, batch, s);
+    return launch_direct_k<T, NC, 0>(p, u, Lu, batch, s);
+}
+
+template <typename T>
+static int launch_direct_t(Plan& p, const void* u, void* Lu, int batch, hipStream_t s)
+{
+    if (p.model != NDL_PERIDYNAMIC) return launch_direct_nc<T, 1>(p, u, Lu, batch, s);
+    if (p.dim == 2) return launch_direct_nc<T, 2>(p, u, Lu, batch, s);
+    return launch_direct_nc<T, 3>(p, u, Lu, batch, s);
 }
 
 int launch_direct(Plan& p, const void* u, void* Lu, int batch, hipStream_t s)

@@ -677,6 +677,7 @@ __global__ void k_split(const T* __restrict__ delta, int64_t N, int64_t n, doubl
 // moment degree of a plan's hierarchical path (-1: not supported)
 static int fast_degree(const Plan& p)
 {
+    if (p.kernel == NDL_G_CONE) return -1;  // no polynomial part at the horizon (g(1) = 0)
     if (p.model == NDL_PERIDYNAMIC) return p.kernel == NDL_G_POLY ? -1 : 2;
     if (p.kernel != NDL_G_POLY) return 0;
     const int K = (int)p.poly.size() - 1;
@@ -694,7 +695,8 @@ int fast_prepare(Plan& p, hipStream_t s, bool with_workspace)
     }
     const int deg = fast_degree(p);
     if (deg < 0) {
-        set_error(p.model == NDL_PERIDYNAMIC
+        set_error(p.kernel == NDL_G_CONE ? "hierarchical path: the conical profile has no polynomial part"
+                  : p.model == NDL_PERIDYNAMIC
                       ? "hierarchical peridynamics needs a power profile"
                       : "hierarchical path: polynomial profiles up to K = 3 (1D), 2 (2D), 1 (3D)");
         return NDL_EUNSUPPORTED;

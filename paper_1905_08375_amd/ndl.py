@@ -18,7 +18,7 @@ NDL_OK, NDL_EINVAL, NDL_ENOMEM, NDL_EUNSUPPORTED, NDL_ENOTSPD, NDL_ENOCONV, NDL_
 NDL_F64, NDL_F32C, NDL_F32K = 0, 1, 2
 NDL_DIFFUSION, NDL_PERIDYNAMIC = 0, 1
 NDL_ND, NDL_DIV = 0, 1
-NDL_G_CONST, NDL_G_INV_R, NDL_G_FRAC, NDL_G_POLY = 0, 1, 2, 3
+NDL_G_CONST, NDL_G_INV_R, NDL_G_FRAC, NDL_G_POLY, NDL_G_CONE = 0, 1, 2, 3, 4
 NDL_NORM_DISCRETE, NDL_NORM_CONTINUOUS, NDL_NORM_NONE = 0, 1, 2
 
 # every symbol include/ndl.h declares

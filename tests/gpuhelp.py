@@ -7,7 +7,8 @@ import oracle as O
 from paper_1905_08375_amd import fields as F
 from paper_1905_08375_amd import ndl
 
-KNAME = {ndl.NDL_G_CONST: "const", ndl.NDL_G_INV_R: "inv_r", ndl.NDL_G_FRAC: "frac", ndl.NDL_G_POLY: "poly"}
+KNAME = {ndl.NDL_G_CONST: "const", ndl.NDL_G_INV_R: "inv_r", ndl.NDL_G_FRAC: "frac", ndl.NDL_G_POLY: "poly",
+         ndl.NDL_G_CONE: "cone"}
 NNAME = {ndl.NDL_NORM_DISCRETE: "discrete", ndl.NDL_NORM_CONTINUOUS: "continuous", ndl.NDL_NORM_NONE: "none"}
 
 TOL = {ndl.NDL_F64: 1e-12, ndl.NDL_F32C: 1e-6, ndl.NDL_F32K: 1e-6}
@@ -58,7 +59,7 @@ def gpu_apply(dim, n, R, delta, coef, u_pad, prec, *, model=ndl.NDL_DIFFUSION, f
     prob = ndl.make_problem(dim, n, R, d_delta, d_coef, model=model, form=form, kernel=kernel, s=s, poly=poly,
                             norm=norm, prec=prec)
     plan = ndl.ndl_plan_create(prob, want_fast=fast, keep=(d_delta, d_coef))
-    ncomp = 2 if model == ndl.NDL_PERIDYNAMIC else 1
+    ncomp = dim if model == ndl.NDL_PERIDYNAMIC else 1
     nb = 1 if batch is None else batch
     d_u = dev(u_pad, prec)
     out = torch.zeros((nb, ncomp) + (n,) * dim, dtype=torch_dtype(prec), device="cuda")

@@ -25,7 +25,7 @@ def rand_fields(n, dim, mlo, mhi, seed):
 
 
 KERNELS = [("const", {}), ("inv_r", {}), ("frac", {"s": 0.5}), ("frac", {"s": 0.25}),
-           ("poly", {"poly": [2.1875, -2.1875, 1.3125, -0.3125]})]
+           ("poly", {"poly": [2.1875, -2.1875, 1.3125, -0.3125]}), ("cone", {})]
 
 
 # --------------------------------------------------------------- P1
@@ -41,26 +41,34 @@ def test_constant_in_kernel(dim, form):
     assert np.all(O.apply(P, delta, c, u) == 0.0)
 
 
-def test_pd_rigid_translation_exact_zero():
-    n, R = 14, 5
-    P = O.Problem(dim=2, n=n, R=R, model="peridynamic", kernel="inv_r")
-    delta, c = rand_fields(n, 2, 2.0, 5.0, 2)
-    u = np.empty((2, n + 2 * R, n + 2 * R))
-    u[0] = 0.3
-    u[1] = -1.7
+@pytest.mark.parametrize("dim,kname", [(2, "inv_r"), (2, "cone"), (3, "inv_r"), (3, "cone")])
+def test_pd_rigid_translation_exact_zero(dim, kname):
+    n, R = {2: 14, 3: 7}[dim], 5
+    P = O.Problem(dim=dim, n=n, R=R, model="peridynamic", kernel=kname)
+    delta, c = rand_fields(n, dim, 2.0, 5.0, 2)
+    u = np.empty((dim,) + (n + 2 * R,) * dim)
+    for a, v in enumerate([0.3, -1.7, 0.9][:dim]):
+        u[a] = v
     assert np.all(O.apply(P, delta, c, u) == 0.0)
 
 
-def test_pd_infinitesimal_rotation_zero():
-    """theta J (x - x0): every bond stretch e.(theta J z) vanishes (Section 1 linear force)."""
-    n, R = 16, 6
-    P = O.Problem(dim=2, n=n, R=R, model="peridynamic", kernel="inv_r")
-    delta, c = rand_fields(n, 2, 2.0, 6.0, 3)
-    X1, X2 = F.padded_coords(n, 2, R)
-    th = 0.37
-    u = np.stack([-th * (X2 - 0.31), th * (X1 - 0.77)])
+@pytest.mark.parametrize("dim,kname", [(2, "inv_r"), (2, "cone"), (3, "inv_r"), (3, "frac")])
+def test_pd_infinitesimal_rotation_zero(dim, kname):
+    """u = W (x - x0) with W antisymmetric (an infinitesimal rotation): every
+    bond stretch e.(W z) vanishes (Section 1 linear force), so L u = 0 up to
+    rounding; in 3D about an axis that is no lattice axis."""
+    n, R = {2: 16, 3: 8}[dim], 6
+    P = O.Problem(dim=dim, n=n, R=R, model="peridynamic", kernel=kname, s=0.5)
+    delta, c = rand_fields(n, dim, 2.0, 6.0, 3)
+    X = F.padded_coords(n, dim, R)
+    x0 = [0.31, 0.77, 0.45][:dim]
+    if dim == 2:
+        W = np.array([[0.0, -0.37], [0.37, 0.0]])
+    else:
+        W = np.array([[0.0, -0.37, 0.21], [0.37, 0.0, -0.55], [-0.21, 0.55, 0.0]])
+    u = np.stack([sum(W[a, b] * (X[b] - x0[b]) for b in range(dim)) for a in range(dim)])
     Lu = O.apply(P, delta, c, u)
-    scale = np.abs(c).max() * 16 * n * n * th / n  # |omega| h^d |du| order
+    scale = np.abs(c).max() * 2 * dim * (dim + 2) * n * n * 0.6 / n  # |omega| h^d |du| order
     assert np.abs(Lu).max() < 1e-12 * scale
 
 
@@ -83,16 +91,21 @@ def test_quadratic_reproduces_laplacian(dim, kname, kw):
     assert np.abs(O.apply(P, delta, c, lin)).max() < 1e-9 * n
 
 
-def test_pd_quadratic_identity():
-    """Peridynamics with M = 2d(d+2): L (|x|^2, 0) = (M/d c, 0) exactly on the lattice."""
-    n, R = 16, 7
-    P = O.Problem(dim=2, n=n, R=R, model="peridynamic", kernel="inv_r")
-    delta, c = rand_fields(n, 2, 2.0, 7.0, 9)
-    X1, X2 = F.padded_coords(n, 2, R)
-    u = np.stack([X1 ** 2 + X2 ** 2, np.zeros_like(X1)])
+@pytest.mark.parametrize("dim,kname", [(2, "inv_r"), (2, "cone"), (3, "inv_r"), (3, "cone")])
+def test_pd_quadratic_identity(dim, kname):
+    """Peridynamics with M = 2d(d+2): L (|x|^2, 0, ..) = (M/d c, 0, ..) exactly
+    on the lattice (the ball is symmetric under axis permutations, so the
+    z_1^2-weighted sum is 1/d of the normalised second moment)."""
+    n, R = {2: 16, 3: 8}[dim], 7
+    P = O.Problem(dim=dim, n=n, R=R, model="peridynamic", kernel=kname)
+    delta, c = rand_fields(n, dim, 2.0, 7.0, 9)
+    X = F.padded_coords(n, dim, R)
+    u = np.stack([sum(x * x for x in X)] + [np.zeros_like(X[0])] * (dim - 1))
     Lu = O.apply(P, delta, c, u)
-    assert np.allclose(Lu[0], 8.0 * c, rtol=1e-12)
-    assert np.abs(Lu[1]).max() < 1e-11
+    M = 2 * dim * (dim + 2)
+    assert np.allclose(Lu[0], M / dim * c, rtol=1e-12)
+    for a in range(1, dim):
+        assert np.abs(Lu[a]).max() < 1e-11 * M
 
 
 def test_pd_local_limit_navier():
@@ -166,6 +179,8 @@ def test_constant_coefficients_are_a_convolution(kname, kw):
         prof = np.zeros_like(r)
         for a in reversed(kw["poly"]):
             prof = prof * r * r + a
+    elif kname == "cone":
+        prof = (1 - r) / r  # the conical micromodulus of eq. "kernelgamma"
     else:
         prof = r ** (-(2 + 2 * kw["s"]))
     prof = np.where(inside, prof, 0.0)
