@@ -299,7 +299,7 @@ def bench_pd(steps=5, batch=8, n=2048, fast=False):
     plan = ndl.ndl_plan_create(ndl.make_problem(2, n, R, d, c, model=ndl.NDL_PERIDYNAMIC, kernel=ndl.NDL_G_INV_R,
                                                 prec=prec), want_fast=int(fast), keep=(d, c))
     if not fast:
-        ndl.ndl_autotune(plan)
+        ndl.ndl_autotune_apply(plan, u, batch)  # tile tuned on these fields at this batch (plan time)
     out = torch.empty((batch, 2, n, n), dtype=torch.float32, device="cuda")
     fn = (lambda: ndl.ndl_apply_fast(plan, u, out, batch)) if fast else (lambda: ndl.ndl_apply(plan, u, out, batch))
     secs, _ = timed(fn, steps, 1)

@@ -252,6 +252,27 @@ int ndl_net_conv_test(int cin, int cout, int S, const uint16_t* x, const float* 
  * NDL_AUTOTUNE_CACHE, if set).  Returns the chosen tile in the plan info. */
 int ndl_autotune(ndl_plan plan, void* stream);
 
+/* The same search on the caller's own state u (layout of ndl_apply) at the
+ * caller's batch, timing applies of u into a scratch output; cached per
+ * batch.  Use it when the plan serves batched calls (the best tile for one
+ * field need not be the best for eight). */
+int ndl_autotune_apply(ndl_plan plan, const void* u, int batch, void* stream);
+
+/* The batched case (b) apply that ndl_cg_solve iterates: y_i = -L x_i with
+ * the zero volume constraint for nprob case (b) diffusion plans (power
+ * profile; one dimension, precision class and profile) in one persistent
+ * launch over the tiles of all of them (Section 2, case (b)).  x_i, y_i:
+ * device arrays of n_i^dim values of the plans' element type.  variant picks
+ * the launch shape (nodes per lane and persistent grid size), 0 <= variant <
+ * *nvariants, or -1 for the autotuner's choice for this batch (timed here on
+ * x when not cached; ndl_cg_solve tunes the same way before it captures its
+ * graph).  Every variant gives bitwise the same y.  variant_used and
+ * nvariants (optional host pointers) report the variant run and the size of
+ * the space (1 when the batch runs the generic kernel).  Allocates its
+ * concatenated buffers; synchronises the stream. */
+int ndl_div_batch_apply(const ndl_plan* plans, int nprob, const void* const* x, void* const* y, int variant,
+                        int* variant_used, int* nvariants, void* stream);
+
 /* Force a tile variant of the direct kernel (0 <= variant < ndl_plan_num_variants;
  * the autotuner's search space).  For tests and fixed deployments. */
 int ndl_plan_set_variant(ndl_plan plan, int variant);

@@ -228,4 +228,10 @@ int ndl_autotune(ndl_plan plan, void* stream)
     return autotune(*reinterpret_cast<Plan*>(plan), (hipStream_t)stream);
 }
 
+int ndl_autotune_apply(ndl_plan plan, const void* u, int batch, void* stream)
+{
+    if (!plan || !u || batch < 1 || batch > 65535) { set_error("ndl_autotune_apply: bad arguments"); return NDL_EINVAL; }
+    return autotune_apply(*reinterpret_cast<Plan*>(plan), u, batch, (hipStream_t)stream);
+}
+
 }  // extern "C"

@@ -1,14 +1,18 @@
 // Tile autotuner for the direct kernels: times every tile variant of the
-// kernel a plan uses (hipEvents, on the caller's stream, on scratch buffers)
-// and keeps the fastest.  Results are cached per (dim, form, model, prec,
-// reach J, n, ncomp) in memory and, when NDL_AUTOTUNE_CACHE names a file, in
-// that file ("key variant" lines) so later processes skip the search.
+// kernel a plan uses (hipEvents, on the caller's stream) and keeps the
+// fastest: either on a scratch state of ones at batch 1 (ndl_autotune) or on
+// the caller's own state at the caller's batch (ndl_autotune_apply).  Results
+// are cached per (dim, form, model, prec, reach J, n, ncomp, profile, batch)
+// in memory and, when NDL_AUTOTUNE_CACHE names a file, in that file ("key
+// variant" lines) so later processes skip the search.  The batched case (b)
+// solver keeps its launch variants in the same cache.
 #include <cstdlib>
 #include <fstream>
 #include <map>
 #include <mutex>
 #include <vector>
 #include <sstream>
+#include <string>
 
 #include "common.h"
 
@@ -18,11 +22,11 @@ static std::mutex g_mu;
 static std::map<std::string, int> g_cache;
 static bool g_loaded = false;
 
-static std::string key_of(const Plan& p)
+static std::string key_of(const Plan& p, int batch)
 {
     std::ostringstream k;
     k << "d" << p.dim << ".f" << p.form << ".m" << p.model << ".p" << p.prec << ".J" << p.J << ".n" << p.n
-      << ".c" << p.ncomp << ".g" << p.kernel;
+      << ".c" << p.ncomp << ".g" << p.kernel << ".b" << batch;
     return k.str();
 }
 
@@ -46,39 +50,49 @@ static void save_file(const std::string& k, int v)
     f << k << " " << v << "\n";
 }
 
-int autotune(Plan& p, hipStream_t s)
+bool tune_cache_lookup(const std::string& key, int* variant)
 {
-    if (!direct_2d_applies(p)) return NDL_OK;  // one variant only
     std::lock_guard<std::mutex> lk(g_mu);
     load_file();
-    std::string key = key_of(p);
     auto it = g_cache.find(key);
-    if (it != g_cache.end()) {
-        p.variant = it->second;
-        return NDL_OK;
-    }
-    size_t es = elem_size(p.prec);
-    void *u = nullptr, *o = nullptr;
-    NDL_HIP(hipMalloc(&u, (size_t)p.NP * p.ncomp * es));
-    NDL_HIP(hipMalloc(&o, (size_t)p.N * p.ncomp * es));
-    NDL_HIP(hipMemsetAsync(u, 0, (size_t)p.NP * p.ncomp * es, s));
+    if (it == g_cache.end()) return false;
+    *variant = it->second;
+    return true;
+}
+
+void tune_cache_store(const std::string& key, int variant)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_cache[key] = variant;
+    save_file(key, variant);
+}
+
+__global__ void k_fill_ones(float* a, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 1.0f;
+}
+
+// time every variant applying L to u (batch states) into out; keep the fastest
+static int tune_variants(Plan& p, const void* u, void* out, int batch, hipStream_t s, int* best_out)
+{
     hipEvent_t e0, e1;
     NDL_HIP(hipEventCreate(&e0));
     NDL_HIP(hipEventCreate(&e1));
-    // three rounds over all variants (20 timed launches each after 3 warm
-    // ones); a variant's time is its best round, which keeps clock ramps and
+    // three rounds over all variants (timed launches after warm ones); a
+    // variant's time is its best round, which keeps clock ramps and
     // neighbours' noise out of the comparison of near-equal tiles
-    int nv = num_variants_2d();
+    const int nv = num_variants_2d();
+    const int reps = std::max(2, 20 / std::max(1, batch));
     std::vector<float> t(nv, 1e30f);
     int rc = NDL_OK;
     for (int round = 0; round < 3 && rc == NDL_OK; ++round) {
         for (int v = 0; v < nv && rc == NDL_OK; ++v) {
             p.variant = v;
-            for (int w = 0; w < 3 && rc == NDL_OK; ++w) rc = launch_direct(p, u, o, 1, s);
+            for (int w = 0; w < 2 && rc == NDL_OK; ++w) rc = launch_direct(p, u, out, batch, s);
             if (rc != NDL_OK) break;
             (void)hipEventRecord(e0, s);
-            const int reps = 20;
-            for (int r = 0; r < reps && rc == NDL_OK; ++r) rc = launch_direct(p, u, o, 1, s);
+            for (int r = 0; r < reps && rc == NDL_OK; ++r) rc = launch_direct(p, u, out, batch, s);
             (void)hipEventRecord(e1, s);
             (void)hipEventSynchronize(e1);
             float ms = 0.f;
@@ -91,12 +105,53 @@ int autotune(Plan& p, hipStream_t s)
         if (t[v] < t[best]) best = v;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    *best_out = best;
+    return rc;
+}
+
+int autotune(Plan& p, hipStream_t s)
+{
+    if (!direct_2d_applies(p)) return NDL_OK;  // one variant only
+    const std::string key = key_of(p, 1);
+    int cached = 0;
+    if (tune_cache_lookup(key, &cached)) {
+        p.variant = cached;
+        return NDL_OK;
+    }
+    size_t es = elem_size(p.prec);
+    void *u = nullptr, *o = nullptr;
+    NDL_HIP(hipMalloc(&u, (size_t)p.NP * p.ncomp * es));
+    NDL_HIP(hipMalloc(&o, (size_t)p.N * p.ncomp * es));
+    // a state of ones (any non-zero data; the kernels' work does not depend on it)
+    const int64_t nf = (int64_t)(p.NP * p.ncomp * es / sizeof(float));
+    k_fill_ones<<<(unsigned)((nf + 255) / 256), 256, 0, s>>>((float*)u, nf);
+    int best = 0;
+    int rc = tune_variants(p, u, o, 1, s, &best);
     (void)hipFree(u);
     (void)hipFree(o);
     p.variant = best;
     if (rc != NDL_OK) return rc;
-    g_cache[key] = best;
-    save_file(key, best);
+    tune_cache_store(key, best);
+    return NDL_OK;
+}
+
+int autotune_apply(Plan& p, const void* u, int batch, hipStream_t s)
+{
+    if (!direct_2d_applies(p)) return NDL_OK;
+    const std::string key = key_of(p, batch);
+    int cached = 0;
+    if (tune_cache_lookup(key, &cached)) {
+        p.variant = cached;
+        return NDL_OK;
+    }
+    void* o = nullptr;
+    NDL_HIP(hipMalloc(&o, (size_t)p.N * p.ncomp * batch * elem_size(p.prec)));
+    int best = 0;
+    int rc = tune_variants(p, u, o, batch, s, &best);
+    (void)hipFree(o);
+    p.variant = best;
+    if (rc != NDL_OK) return rc;
+    tune_cache_store(key, best);
     return NDL_OK;
 }
 

@@ -122,6 +122,11 @@ int launch_fast(Plan& p, const void* u, void* Lu, int batch, hipStream_t s, doub
 int fast_static_workspace(double** ptr, int64_t* capacity_elems);
 int fast_decomp_host(Plan& p, const int64_t* node, int32_t* out, int cap, int* count);
 int autotune(Plan& p, hipStream_t s);
+// the direct kernel's tile tuned on the caller's state at the caller's batch
+int autotune_apply(Plan& p, const void* u, int batch, hipStream_t s);
+// the autotuner's cache (in memory, and the file named by NDL_AUTOTUNE_CACHE)
+bool tune_cache_lookup(const std::string& key, int* variant);
+void tune_cache_store(const std::string& key, int variant);
 bool net_is_linear(void* net);
 // z = M(r); add_jacobi (linear mode): z = r dinv + M(r), the two-level form, in the same pass
 int net_precond(void* net, const Plan& p, const void* r, void* z, hipStream_t s, const void* dinv = nullptr,

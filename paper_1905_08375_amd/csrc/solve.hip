@@ -17,6 +17,7 @@
 // tolerance, and x += ||r|| d in FP64; every dot product and norm is FP64.
 #include <algorithm>
 #include <chrono>
+#include <string>
 #include <cmath>
 #include <memory>
 #include <type_traits>
@@ -236,32 +237,35 @@ __global__ __launch_bounds__(256) void k_div_items(const Inst* __restrict__ inst
 // only tiles within J of the boundary test for.
 // 3D: 2 nodes per lane, 16 waves per 8 x 4 x 64 tile (the haloed tile leaves
 // room for one block per CU, so the occupancy comes from the block's waves)
-#ifndef NDL_DIV3_PY
-#define NDL_DIV3_PY 2
-#endif
-#ifndef NDL_DIV2_PY
-#define NDL_DIV2_PY 4
-#endif
 // Tile of one block: 16 x 64 (2D) or 8 x 4 x 64 (3D) nodes, PY nodes per
 // lane.  FP64 vectors on 3D problems with FP32 fields (the outer residual of
 // the mixed-precision solve) stage 4 planes at a time, in two halves, so that
 // the 8-byte u and c' fit the LDS next to the 4-byte horizon.
-template <typename T, int DIM>
+// Launch variants (the autotuner's search space): nodes per lane PY, which
+// sets the block size for the fixed tile, times the persistent grid size.
+// Every variant sums each node's pairs in the same order, so all give bitwise
+// the same q = -L p; only the block's reduction of the p.q partial differs.
+constexpr int kDivPY2[3] = {4, 2, 8};  // 2D, first = default
+constexpr int kDivPY3[2] = {2, 4};     // 3D, first = default
+constexpr int kDivGrid[3] = {2048, 1024, 4096};
+inline int div_num_variants(int dim) { return (dim == 3 ? 2 : 3) * 3; }
+
+template <typename T, int DIM, int PYV>
 struct DivShape {
-    static constexpr int PY = DIM == 3 ? NDL_DIV3_PY : NDL_DIV2_PY;
+    static constexpr int PY = PYV;
     static constexpr int TY = DIM == 3 ? 4 : 16;
     static constexpr int TZ = DIM == 3 ? (sizeof(T) == 8 ? 4 : 8) : 1;
     static constexpr int SUB = DIM == 3 ? 8 / TZ : 1;  // staged slabs per item
     static constexpr int THREADS = 64 * TZ * TY / PY;
 };
 
-template <typename T, typename D, bool DIAG, int JT, int DIM>
-__global__ __launch_bounds__((DivShape<T, DIM>::THREADS)) void k_div2_items(
+template <typename T, typename D, bool DIAG, int JT, int DIM, int PYV>
+__global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items(
     const Inst* __restrict__ insts, const int2* __restrict__ items, int nitems, const T* __restrict__ pvec,
     T* __restrict__ qvec, const int4* __restrict__ full, const double* __restrict__ fw, const double* __restrict__ Tinv,
     const Scal* __restrict__ sc, double* __restrict__ part)
 {
-    using SH = DivShape<T, DIM>;
+    using SH = DivShape<T, DIM, PYV>;
     constexpr bool F32 = sizeof(T) == 4;
     constexpr int PY = SH::PY;
     constexpr int NWAVES = SH::THREADS / 64;
@@ -764,6 +768,7 @@ struct Batch {
     int64_t total = 0;
     int dim = 0, Jmax = 0;
     int64_t kmax = 0;
+    int variant = 0;         // launch variant of the specialised item kernel (autotuned)
 };
 
 static int build_batch(const ndl_plan* plans, int nprob, Batch& B, bool f64_fields, std::vector<DevBuf>& keep)
@@ -853,8 +858,8 @@ static size_t items_lds(const Batch& B, bool f32data = false)
     if (use_div_spec<T>(B, f32data)) {
         const int J = B.Jmax;
         size_t cells;
-        if (B.dim == 3) cells = (size_t)(DivShape<T, 3>::TZ + 2 * J) * (DivShape<T, 3>::TY + 2 * J) * (64 + 2 * J);
-        else cells = (size_t)(DivShape<T, 2>::TY + 2 * J) * (64 + 2 * J);
+        if (B.dim == 3) cells = (size_t)(DivShape<T, 3, 2>::TZ + 2 * J) * (DivShape<T, 3, 2>::TY + 2 * J) * (64 + 2 * J);
+        else cells = (size_t)(DivShape<T, 2, 4>::TY + 2 * J) * (64 + 2 * J);
         return cells * ((B.dim == 3 ? sizeof(float) : sizeof(double)) + 2 * sizeof(T));
     }
     int L[3] = {I0.E[0] + (B.dim >= 3 ? 2 * B.Jmax : 0), I0.E[1] + (B.dim >= 2 ? 2 * B.Jmax : 0),
@@ -863,10 +868,40 @@ static size_t items_lds(const Batch& B, bool f32data = false)
     return cells * sizeof(T) * (sizeof(T) == 4 ? 3 : 1);
 }
 
-#define NDL_DIV2_KERNELS(T_, D_, DD)                                                                             \
-    (const void*)k_div2_items<T_, D_, false, 1, DD>, (const void*)k_div2_items<T_, D_, true, 1, DD>,            \
-        (const void*)k_div2_items<T_, D_, false, 2, DD>, (const void*)k_div2_items<T_, D_, true, 2, DD>,        \
-        (const void*)k_div2_items<T_, D_, false, 3, DD>, (const void*)k_div2_items<T_, D_, true, 3, DD>
+// every instantiation of the specialised item kernel for element type T and
+// field type DT in dim DD (reaches 1..JMAX, all launch variants, DIAG at the
+// default variant)
+template <typename T, typename DT, int DD, int JJ>
+static void div2_kernels_j(std::vector<const void*>& v)
+{
+    constexpr int P0 = DD == 3 ? kDivPY3[0] : kDivPY2[0];
+    v.push_back((const void*)k_div2_items<T, DT, true, JJ, DD, P0>);
+    if constexpr (DD == 3) {
+        v.push_back((const void*)k_div2_items<T, DT, false, JJ, DD, kDivPY3[0]>);
+        v.push_back((const void*)k_div2_items<T, DT, false, JJ, DD, kDivPY3[1]>);
+    } else {
+        v.push_back((const void*)k_div2_items<T, DT, false, JJ, DD, kDivPY2[0]>);
+        v.push_back((const void*)k_div2_items<T, DT, false, JJ, DD, kDivPY2[1]>);
+        v.push_back((const void*)k_div2_items<T, DT, false, JJ, DD, kDivPY2[2]>);
+    }
+}
+
+template <typename T, typename DT, int DD>
+static std::vector<const void*> div2_kernels()
+{
+    std::vector<const void*> v;
+    div2_kernels_j<T, DT, DD, 1>(v);
+    div2_kernels_j<T, DT, DD, 2>(v);
+    div2_kernels_j<T, DT, DD, 3>(v);
+    if constexpr (DD == 2) {
+        div2_kernels_j<T, DT, DD, 4>(v);
+        div2_kernels_j<T, DT, DD, 5>(v);
+        div2_kernels_j<T, DT, DD, 6>(v);
+        div2_kernels_j<T, DT, DD, 7>(v);
+        div2_kernels_j<T, DT, DD, 8>(v);
+    }
+    return v;
+}
 
 template <typename T>
 static int prepare_lds(const Batch& B, bool f32data = false)
@@ -878,52 +913,75 @@ static int prepare_lds(const Batch& B, bool f32data = false)
     }
     // plus ~14 KiB of static LDS (reduction, tables)
     if (lds + 16 * 1024 > 64 * 1024) {
-        const void* fns[] = {(const void*)k_div_items<T, false, true>, (const void*)k_div_items<T, true, true>,
-                             (const void*)k_div_items<T, false, false>, (const void*)k_div_items<T, true, false>};
+        std::vector<const void*> fns = {(const void*)k_div_items<T, false, true>,
+                                        (const void*)k_div_items<T, true, true>,
+                                        (const void*)k_div_items<T, false, false>,
+                                        (const void*)k_div_items<T, true, false>};
+        for (const void* f : div2_kernels<T, T, 2>()) fns.push_back(f);
+        for (const void* f : div2_kernels<T, T, 3>()) fns.push_back(f);
+        if (f32data && sizeof(T) == 8)
+            for (const void* f : div2_kernels<double, float, 3>()) fns.push_back(f);
         for (const void* f : fns) NDL_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        const void* fns2[] = {NDL_DIV2_KERNELS(T, T, 2),
-                              (const void*)k_div2_items<T, T, false, 4, 2>, (const void*)k_div2_items<T, T, true, 4, 2>,
-                              (const void*)k_div2_items<T, T, false, 5, 2>, (const void*)k_div2_items<T, T, true, 5, 2>,
-                              (const void*)k_div2_items<T, T, false, 6, 2>, (const void*)k_div2_items<T, T, true, 6, 2>,
-                              (const void*)k_div2_items<T, T, false, 7, 2>, (const void*)k_div2_items<T, T, true, 7, 2>,
-                              (const void*)k_div2_items<T, T, false, 8, 2>, (const void*)k_div2_items<T, T, true, 8, 2>,
-                              NDL_DIV2_KERNELS(T, T, 3)};
-        for (const void* f : fns2) NDL_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        if (f32data && sizeof(T) == 8) {
-            const void* fns3[] = {NDL_DIV2_KERNELS(double, float, 3)};
-            for (const void* f : fns3)
-                NDL_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        }
     }
     return NDL_OK;
 }
-#undef NDL_DIV2_KERNELS
+
+template <typename T, typename DT, int JJ, int DD, int PY>
+static void launch_div2(unsigned g, size_t lds, hipStream_t s, const Inst* d_insts, const int2* d_items, int nitems,
+                        const T* p, T* q, const int4* full, const double* fw, const double* Tinv, const Scal* sc,
+                        double* part)
+{
+    constexpr unsigned nt = (unsigned)DivShape<T, DD, PY>::THREADS;
+    k_div2_items<T, DT, false, JJ, DD, PY><<<g, nt, lds, s>>>(d_insts, d_items, nitems, p, q, full, fw, Tinv, sc,
+                                                              part);
+}
+
+template <typename T, typename DT, int JJ, int DD>
+static void launch_div2_v(int variant, bool diag, unsigned nitems_u, size_t lds, hipStream_t s,
+                          const Inst* d_insts, const int2* d_items, const T* p, T* q, const int4* full,
+                          const double* fw, const double* Tinv, const Scal* sc, double* part)
+{
+    const int nitems = (int)nitems_u;
+    const int gi = variant % 3, pi = variant / 3;
+    const unsigned g = (unsigned)std::min(nitems, kDivGrid[gi]);
+    if (diag) {
+        constexpr int P0 = DD == 3 ? kDivPY3[0] : kDivPY2[0];
+        constexpr unsigned nt = (unsigned)DivShape<T, DD, P0>::THREADS;
+        const unsigned gd = (unsigned)std::min(nitems, kDivGrid[0]);
+        k_div2_items<T, DT, true, JJ, DD, P0><<<gd, nt, lds, s>>>(d_insts, d_items, nitems, p, q, full, fw, Tinv,
+                                                                  sc, part);
+        return;
+    }
+    if constexpr (DD == 3) {
+        if (pi == 1) launch_div2<T, DT, JJ, DD, kDivPY3[1]>(g, lds, s, d_insts, d_items, nitems, p, q, full, fw, Tinv, sc, part);
+        else launch_div2<T, DT, JJ, DD, kDivPY3[0]>(g, lds, s, d_insts, d_items, nitems, p, q, full, fw, Tinv, sc, part);
+    } else {
+        if (pi == 1) launch_div2<T, DT, JJ, DD, kDivPY2[1]>(g, lds, s, d_insts, d_items, nitems, p, q, full, fw, Tinv, sc, part);
+        else if (pi == 2) launch_div2<T, DT, JJ, DD, kDivPY2[2]>(g, lds, s, d_insts, d_items, nitems, p, q, full, fw, Tinv, sc, part);
+        else launch_div2<T, DT, JJ, DD, kDivPY2[0]>(g, lds, s, d_insts, d_items, nitems, p, q, full, fw, Tinv, sc, part);
+    }
+}
 
 // q = -L p over the items.  f32data: the items' fields are FP32 while the
 // vectors are FP64 (3D specialised kernel only; otherwise the caller passes
-// FP64 fields).
+// FP64 fields).  variant < 0: the batch's tuned variant.
 template <typename T>
 static int launch_div_items(const Batch& B, const Inst* d_insts, const int2* d_items, const T* p, T* q,
                             const int4* full, const double* fw, int nfull, const double* Tinv, const Scal* sc,
-                            double* part, bool diag, hipStream_t s, bool f32data = false)
+                            double* part, bool diag, hipStream_t s, bool f32data = false, int variant = -1)
 {
     size_t lds = items_lds<T>(B, f32data);
     int nitems = (int)B.items.size();
     unsigned g = (unsigned)std::min(nitems, 256 * 8);
     bool disc = B.insts[0].norm == NDL_NORM_DISCRETE;
     if (use_div_spec<T>(B, f32data)) {
+        const int v = variant >= 0 ? variant : B.variant;
         const int key = B.dim * 16 + B.Jmax;
 #define NDL_DIV2_CASE(DD, JJ, DT)                                                                                 \
-    case DD * 16 + JJ: {                                                                                          \
-        const unsigned nt = (unsigned)DivShape<T, DD>::THREADS;                                                   \
-        if (diag)                                                                                                 \
-            k_div2_items<T, DT, true, JJ, DD><<<g, nt, lds, s>>>(d_insts, d_items, nitems, p, q, full, fw, Tinv,  \
-                                                                  sc, part);                                      \
-        else                                                                                                      \
-            k_div2_items<T, DT, false, JJ, DD><<<g, nt, lds, s>>>(d_insts, d_items, nitems, p, q, full, fw, Tinv, \
-                                                                   sc, part);                                     \
-        break;                                                                                                    \
-    }
+    case DD * 16 + JJ:                                                                                            \
+        launch_div2_v<T, DT, JJ, DD>(v, diag, (unsigned)nitems, lds, s, d_insts, d_items, p, q, full, fw, Tinv,   \
+                                     sc, part);                                                                   \
+        break;
         if (f32data && sizeof(T) == 8) {
             if constexpr (sizeof(T) == 8) {
                 switch (key) {
@@ -968,6 +1026,10 @@ static int launch_div_items(const Batch& B, const Inst* d_insts, const int2* d_i
     NDL_HIP(hipGetLastError());
     return NDL_OK;
 }
+
+template <typename T>
+static int tune_div_batch(Batch& B, const Inst* di, const int2* dit, const T* p, T* q, const int4* full,
+                          const double* fw, int nfull, const double* Tinv, hipStream_t s);
 
 template <typename T>
 static int cg_solve_t(const ndl_plan* plans, int nprob, const double* const* b, double* const* x,
@@ -1079,6 +1141,9 @@ static int cg_solve_t(const ndl_plan* plans, int nprob, const double* const* b, 
                                 (const double*)d_fw.p, nfull, (const double*)d_Tinv.p, nullptr, nullptr, true, s));
     k_recip<T><<<grid_for(tot), 256, 0, s>>>((const T*)vq.p, (T*)vdinv.p, tot);
     NDL_HIP(hipGetLastError());
+    // launch variant of the apply, timed on this batch (before the graph is captured)
+    NDL_TRY(tune_div_batch<T>(B, di, dit, (const T*)vdinv.p, (T*)vq.p, (const int4*)d_full.p,
+                              (const double*)d_fw.p, nfull, (const double*)d_Tinv.p, s));
 
     // ||b||^2 per problem
     NDL_HIP(hipMemsetAsync(vax.p, 0, tot * sizeof(double), s));
@@ -1242,18 +1307,17 @@ struct OpCache {
     int nfull = 0, nitems = 0;
 };
 
-template <typename T>
-static int op_build(const Plan& P, OpCache& oc, hipStream_t s)
+// The batch tables of the item kernels for `nprob` plans (one dimension and
+// profile): instances, items, the full-ball table and M / T_e[k].
+static int op_tables(const ndl_plan* plans, int nprob, OpCache& oc)
 {
-    if (oc.plan == &P && oc.plan_uid == P.uid) return NDL_OK;
-    oc = OpCache();
-    ndl_plan h = reinterpret_cast<ndl_plan>(const_cast<Plan*>(&P));
     std::vector<DevBuf> keep;
-    NDL_TRY(build_batch(&h, 1, oc.B, false, keep));
+    NDL_TRY(build_batch(plans, nprob, oc.B, false, keep));
+    const Plan& P = *reinterpret_cast<const Plan*>(plans[0]);
     oc.nitems = (int)oc.B.items.size();
-    NDL_TRY(alloc<Inst>(oc.insts, 1));
+    NDL_TRY(alloc<Inst>(oc.insts, nprob));
     NDL_TRY(alloc<int2>(oc.items, oc.nitems));
-    NDL_HIP(hipMemcpy(oc.insts.p, oc.B.insts.data(), sizeof(Inst), hipMemcpyHostToDevice));
+    NDL_HIP(hipMemcpy(oc.insts.p, oc.B.insts.data(), nprob * sizeof(Inst), hipMemcpyHostToDevice));
     NDL_HIP(hipMemcpy(oc.items.p, oc.B.items.data(), oc.nitems * sizeof(int2), hipMemcpyHostToDevice));
     std::vector<Off> full = ball_offsets(oc.B.dim, oc.B.kmax, false);
     std::vector<int4> fb;
@@ -1278,6 +1342,65 @@ static int op_build(const Plan& P, OpCache& oc, hipStream_t s)
     NDL_HIP(hipMemcpy(oc.fw.p, fwv.data(), fwv.size() * sizeof(double), hipMemcpyHostToDevice));
     NDL_HIP(hipMemcpy(oc.Tinv.p, Tinv.data(), Tinv.size() * sizeof(double), hipMemcpyHostToDevice));
     oc.nfull = (int)fb.size();
+    return NDL_OK;
+}
+
+// Autotuner of the batched item kernel: times every launch variant on the
+// batch itself (input p, non-zero, output q as scratch) and keeps the fastest
+// in B.variant; cached per (dim, reach, element type, batch size class).
+template <typename T>
+static int tune_div_batch(Batch& B, const Inst* di, const int2* dit, const T* p, T* q, const int4* full,
+                          const double* fw, int nfull, const double* Tinv, hipStream_t s)
+{
+    if (!use_div_spec<T>(B)) return NDL_OK;
+    const int nitems = (int)B.items.size();
+    int lg = 0;
+    while ((1 << (lg + 1)) <= nitems) ++lg;
+    const std::string key = "div.d" + std::to_string(B.dim) + ".J" + std::to_string(B.Jmax) + ".t" +
+                            std::to_string(sizeof(T)) + ".i" + std::to_string(lg);
+    int cached = 0;
+    if (tune_cache_lookup(key, &cached) && cached >= 0 && cached < div_num_variants(B.dim)) {
+        B.variant = cached;
+        return NDL_OK;
+    }
+    hipEvent_t e0, e1;
+    NDL_HIP(hipEventCreate(&e0));
+    NDL_HIP(hipEventCreate(&e1));
+    const int nv = div_num_variants(B.dim);
+    std::vector<float> t(nv, 1e30f);
+    int rc = NDL_OK;
+    for (int round = 0; round < 2 && rc == NDL_OK; ++round)
+        for (int v = 0; v < nv && rc == NDL_OK; ++v) {
+            rc = launch_div_items<T>(B, di, dit, p, q, full, fw, nfull, Tinv, nullptr, nullptr, false, s, false, v);
+            if (rc != NDL_OK) break;
+            (void)hipEventRecord(e0, s);
+            for (int r = 0; r < 4 && rc == NDL_OK; ++r)
+                rc = launch_div_items<T>(B, di, dit, p, q, full, fw, nfull, Tinv, nullptr, nullptr, false, s, false,
+                                         v);
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            t[v] = std::min(t[v], ms);
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != NDL_OK) return rc;
+    int best = 0;
+    for (int v = 1; v < nv; ++v)
+        if (t[v] < t[best]) best = v;
+    B.variant = best;
+    tune_cache_store(key, best);
+    return NDL_OK;
+}
+
+template <typename T>
+static int op_build(const Plan& P, OpCache& oc, hipStream_t s)
+{
+    if (oc.plan == &P && oc.plan_uid == P.uid) return NDL_OK;
+    oc = OpCache();
+    ndl_plan h = reinterpret_cast<ndl_plan>(const_cast<Plan*>(&P));
+    NDL_TRY(op_tables(&h, 1, oc));
     NDL_TRY(alloc<double>(oc.part, oc.nitems));
     NDL_TRY(alloc<double>(oc.sres, 2));
     NDL_TRY(alloc<T>(oc.dinv, P.N));
@@ -1287,7 +1410,15 @@ static int op_build(const Plan& P, OpCache& oc, hipStream_t s)
                                 (const double*)oc.Tinv.p, nullptr, nullptr, true, s));
     k_recip<T><<<grid_for(P.N), 256, 0, s>>>((const T*)oc.dinv.p, (T*)oc.dinv.p, P.N);
     NDL_HIP(hipGetLastError());
-    NDL_HIP(hipStreamSynchronize(s));
+    {
+        // tune the apply on the diagonal's inverse (a non-zero field) into a scratch output
+        DevBuf scr;
+        NDL_TRY(alloc<T>(scr, P.N));
+        NDL_TRY(tune_div_batch<T>(oc.B, (const Inst*)oc.insts.p, (const int2*)oc.items.p, (const T*)oc.dinv.p,
+                                  (T*)scr.p, (const int4*)oc.full.p, (const double*)oc.fw.p, oc.nfull,
+                                  (const double*)oc.Tinv.p, s));
+        NDL_HIP(hipStreamSynchronize(s));
+    }
     oc.plan = &P;
     oc.plan_uid = P.uid;
     return NDL_OK;
@@ -1523,6 +1654,8 @@ static int pcg_learned_t(const ndl_plan plan, const double* b, double* x, const 
     NDL_TRY(launch_div_items<T>(B, di, dit, (const T*)nullptr, (T*)vq.p, (const int4*)d_full.p, (const double*)d_fw.p,
                                 nfull, (const double*)d_Tinv.p, nullptr, nullptr, true, s));
     k_recip<T><<<grid_for(N), 256, 0, s>>>((const T*)vq.p, (T*)vdinv.p, N);
+    NDL_TRY(tune_div_batch<T>(B, di, dit, (const T*)vdinv.p, (T*)vq.p, (const int4*)d_full.p,
+                              (const double*)d_fw.p, nfull, (const double*)d_Tinv.p, s));
     unsigned gi = (unsigned)std::min(nitems, 256 * 8);
     auto sum_items = [&](const double* part, double* out) -> int {
         k_item_sums<<<1, 256, 0, s>>>(1, di, part, (double*)sres.p);
@@ -1730,6 +1863,74 @@ int ndl_cg_solve(const ndl_plan* plans, int nprob, const double* const* b, doubl
     }
     return p0->prec == NDL_F64 ? cg_solve_t<double>(plans, nprob, b, x, opts, reports, s)
                                : cg_solve_t<float>(plans, nprob, b, x, opts, reports, s);
+}
+
+}  // extern "C"
+
+namespace ndl {
+template <typename T>
+static int div_batch_apply_t(const ndl_plan* plans, int nprob, const void* const* x, void* const* y, int variant,
+                             int* used, int* nv, hipStream_t s)
+{
+    OpCache oc;
+    NDL_TRY(op_tables(plans, nprob, oc));
+    Batch& B = oc.B;
+    const bool spec = use_div_spec<T>(B);
+    const int nvar = spec ? div_num_variants(B.dim) : 1;
+    if (nv) *nv = nvar;
+    if (variant >= nvar) {
+        set_error("ndl_div_batch_apply: variant %d out of range [0, %d)", variant, nvar);
+        return NDL_EINVAL;
+    }
+    DevBuf vin, vout;
+    NDL_TRY(alloc<T>(vin, B.total));
+    NDL_TRY(alloc<T>(vout, B.total));
+    NDL_HIP(hipMemsetAsync(vin.p, 0, B.total * sizeof(T), s));
+    for (int i = 0; i < nprob; ++i)
+        NDL_HIP(hipMemcpyAsync((T*)vin.p + B.insts[i].off, x[i], B.insts[i].N * sizeof(T), hipMemcpyDeviceToDevice, s));
+    NDL_TRY(prepare_lds<T>(B));
+    const Inst* di = (const Inst*)oc.insts.p;
+    const int2* dit = (const int2*)oc.items.p;
+    if (variant < 0)
+        NDL_TRY(tune_div_batch<T>(B, di, dit, (const T*)vin.p, (T*)vout.p, (const int4*)oc.full.p,
+                                  (const double*)oc.fw.p, oc.nfull, (const double*)oc.Tinv.p, s));
+    else
+        B.variant = variant;
+    NDL_TRY(launch_div_items<T>(B, di, dit, (const T*)vin.p, (T*)vout.p, (const int4*)oc.full.p,
+                                (const double*)oc.fw.p, oc.nfull, (const double*)oc.Tinv.p, nullptr, nullptr, false,
+                                s));
+    for (int i = 0; i < nprob; ++i)
+        NDL_HIP(hipMemcpyAsync(y[i], (const T*)vout.p + B.insts[i].off, B.insts[i].N * sizeof(T),
+                               hipMemcpyDeviceToDevice, s));
+    NDL_HIP(hipStreamSynchronize(s));
+    if (used) *used = spec ? B.variant : 0;
+    return NDL_OK;
+}
+}  // namespace ndl
+
+extern "C" {
+int ndl_div_batch_apply(const ndl_plan* plans, int nprob, const void* const* x, void* const* y, int variant,
+                        int* variant_used, int* nvariants, void* stream)
+{
+    using namespace ndl;
+    if (!plans || nprob <= 0 || !x || !y) { set_error("ndl_div_batch_apply: bad arguments"); return NDL_EINVAL; }
+    const Plan* p0 = reinterpret_cast<const Plan*>(plans[0]);
+    for (int i = 0; i < nprob; ++i) {
+        const Plan* p = reinterpret_cast<const Plan*>(plans[i]);
+        if (!p || !x[i] || !y[i]) { set_error("ndl_div_batch_apply: null plan or vector %d", i); return NDL_EINVAL; }
+        if (p->form != NDL_DIV || p->model != NDL_DIFFUSION || p->kernel > NDL_G_FRAC) {
+            set_error("ndl_div_batch_apply: case (b) diffusion plans with a power profile");
+            return NDL_EUNSUPPORTED;
+        }
+        if (p->dim != p0->dim || (p->prec == NDL_F64) != (p0->prec == NDL_F64) || p->kernel != p0->kernel ||
+            p->expo != p0->expo || p->m2 != p0->m2 || p->norm != p0->norm) {
+            set_error("ndl_div_batch_apply: all plans must share dim, precision class and kernel");
+            return NDL_EINVAL;
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    return p0->prec == NDL_F64 ? div_batch_apply_t<double>(plans, nprob, x, y, variant, variant_used, nvariants, s)
+                               : div_batch_apply_t<float>(plans, nprob, x, y, variant, variant_used, nvariants, s);
 }
 
 

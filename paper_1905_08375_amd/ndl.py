@@ -28,6 +28,7 @@ EXPORTS = [
     "ndl_net_save", "ndl_net_load", "ndl_net_num_params", "ndl_net_train_step", "ndl_precond_apply",
     "ndl_autotune", "ndl_last_error", "ndl_version", "ndl_plan_set_variant", "ndl_plan_num_variants",
     "ndl_net_conv_test", "ndl_net_train_step_energy", "ndl_net_layer_tensor", "ndl_apply_fast_noalloc",
+    "ndl_autotune_apply", "ndl_div_batch_apply",
 ]
 
 
@@ -95,6 +96,9 @@ def lib():
             "ndl_net_train_step": [vp, C.c_int, C.c_int, vp, vp, vp, C.c_float, C.POINTER(C.c_float), vp],
             "ndl_precond_apply": [vp, vp, vp, vp, vp],
             "ndl_autotune": [vp, vp],
+            "ndl_autotune_apply": [vp, vp, C.c_int, vp],
+            "ndl_div_batch_apply": [C.POINTER(vp), C.c_int, C.POINTER(vp), C.POINTER(vp), C.c_int,
+                                    C.POINTER(C.c_int), C.POINTER(C.c_int), vp],
             "ndl_plan_set_variant": [vp, C.c_int],
             "ndl_plan_num_variants": [vp, C.POINTER(C.c_int)],
             "ndl_net_train_step_energy": [vp, vp, C.c_int, vp, vp, C.c_float, C.POINTER(C.c_float), vp],
@@ -227,6 +231,23 @@ def ndl_plan_num_variants(plan: Plan) -> int:
 def ndl_autotune(plan: Plan, stream=None):
     _check(lib().ndl_autotune(plan.handle, _stream(stream)), "ndl_autotune")
     return plan.info()
+
+
+def ndl_autotune_apply(plan: Plan, u, batch: int = 1, stream=None):
+    _check(lib().ndl_autotune_apply(plan.handle, _ptr(u), int(batch), _stream(stream)), "ndl_autotune_apply")
+    return plan.info()
+
+
+def ndl_div_batch_apply(plans: Sequence[Plan], x_list, y_list, variant: int = -1, stream=None):
+    """y_i = -L x_i for case (b) plans in one batched launch; returns (variant used, number of variants)."""
+    n = len(plans)
+    ph = (C.c_void_p * n)(*[p.handle.value if isinstance(p.handle, C.c_void_p) else p.handle for p in plans])
+    xp = (C.c_void_p * n)(*[_ptr(x) for x in x_list])
+    yp = (C.c_void_p * n)(*[_ptr(y) for y in y_list])
+    used, nv = C.c_int(), C.c_int()
+    _check(lib().ndl_div_batch_apply(ph, n, xp, yp, int(variant), C.byref(used), C.byref(nv), _stream(stream)),
+           "ndl_div_batch_apply")
+    return used.value, nv.value
 
 
 def ndl_cg_solve(plans: Sequence[Plan], b_list, x_list, rtol=1e-8, max_iter=200000, precond=0, net=None,

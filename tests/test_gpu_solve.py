@@ -6,7 +6,7 @@ import pytest
 import oracle as O
 from paper_1905_08375_amd import fields as F
 from paper_1905_08375_amd import ndl
-from gpuhelp import dev, say
+from gpuhelp import dev, rel_l2, say
 
 pytestmark = pytest.mark.gpu
 
@@ -274,3 +274,64 @@ def test_batched_cg_on_the_workload_size_mix():
         say(f"  inst {i} n={n} iters={rep.iters} outer={rep.outer} gpu_res={rep.rel_res_fp64:.2e} oracle_res={rr:.2e}")
         assert rep.converged == 1
         assert rr <= 1.05e-8
+
+
+def _div_batch(sizes, dim, prec, R, seed, mlo=2.0, mhi=8.0):
+    import torch
+    plans, xs, ws = [], [], []
+    for i, n in enumerate(sizes):
+        g = np.random.default_rng(seed + i)
+        X = F.mesh(n, dim)
+        ph = g.uniform(0, 1, size=2)
+        m = (mlo + mhi) / 2 + (mhi - mlo) / 2 * np.sin(2 * np.pi * (X[0] + ph[0])) * np.cos(2 * np.pi * (X[-1] + ph[1]))
+        c = np.exp(g.normal(0.0, 0.5, (n,) * dim))
+        x = g.standard_normal((n,) * dim)
+        d_d, d_c = dev(m / n, prec), dev(c, prec)
+        plans.append(ndl.ndl_plan_create(ndl.make_problem(dim, n, R, d_d, d_c, form=ndl.NDL_DIV, prec=prec),
+                                         keep=(d_d, d_c)))
+        xs.append(dev(x, prec))
+        ws.append((m / n, c, x))
+    return plans, xs, ws
+
+
+@pytest.mark.parametrize("dim,prec,sizes,R,mhi", [
+    (2, ndl.NDL_F32C, [768, 768, 512, 512, 512, 512, 300, 101, 37], 8, 8.0),
+    (2, ndl.NDL_F64, [384, 200, 77], 8, 8.0),
+    (3, ndl.NDL_F32C, [40, 33, 24], 4, 4.0),
+])
+def test_batched_apply_every_variant(dim, prec, sizes, R, mhi):
+    """The solver's batched case (b) apply (one persistent launch over the tiles
+    of uneven problems; in 2D more tiles than any grid holds) in every launch
+    variant the autotuner may pick: each matches the FP64 oracle, all are
+    bitwise alike, and the tuned choice is one of them."""
+    import torch
+    say(f"case batched apply variants dim={dim} prec={prec} sizes={sizes}")
+    plans, xs, ws = _div_batch(sizes, dim, prec, R, 700 + dim, mhi=mhi)
+    tdt = torch.float64 if prec == ndl.NDL_F64 else torch.float32
+    refs = []
+    for (delta, c, x), n in zip(ws, sizes):
+        P = O.Problem(dim=dim, n=n, R=R, form="div", kernel="frac")
+        npt = np.float64 if prec == ndl.NDL_F64 else np.float32
+        refs.append(-O.apply(P, delta.astype(npt).astype(np.float64), c.astype(npt).astype(np.float64),
+                             F.pad(x.astype(npt).astype(np.float64), R)))
+    first, nvar = None, None
+    v = 0
+    while nvar is None or v < nvar:
+        ys = [torch.full((n,) * dim, float("nan"), dtype=tdt, device="cuda") for n in sizes]
+        used, nvar = ndl.ndl_div_batch_apply(plans, xs, ys, v)
+        assert used == v
+        got = [y.cpu().numpy() for y in ys]
+        errs = [rel_l2(gg, rr) for gg, rr in zip(got, refs)]
+        say(f"  variant {v}/{nvar} max rel l2 {max(errs):.2e}")
+        assert max(errs) <= (1e-12 if prec == ndl.NDL_F64 else 1e-6)
+        if first is None:
+            first = got
+        else:
+            assert all(np.array_equal(a, b) for a, b in zip(got, first)), v
+        v += 1
+    assert nvar > 1
+    ys = [torch.empty((n,) * dim, dtype=tdt, device="cuda") for n in sizes]
+    used, _ = ndl.ndl_div_batch_apply(plans, xs, ys, -1)
+    say(f"  tuned variant {used}")
+    assert 0 <= used < nvar
+    assert all(np.array_equal(y.cpu().numpy(), b) for y, b in zip(ys, first))
