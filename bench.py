@@ -242,7 +242,8 @@ def bench_net(n=256, seed=100, reps=50):
 def bench_sweep(n=1024, ms=(2, 4, 8, 16, 32, 64), example1=True):
     """Direct sum vs the Section 3 evaluation for the constant profile (p^0 = g
     exactly, so the hierarchical path is pure panel sums) at growing horizon
-    m = delta n; the last point is the paper's Example 1 (delta = 1/2, direct
+    m = delta n, by the dyadic panels (fast_ms) and by the row prefix sums
+    (rows_ms); the last point is the paper's Example 1 (delta = 1/2, direct
     sum out of reach of the LDS tile, hierarchical only)."""
     import torch
     from paper_1905_08375_amd import fields as F
@@ -273,11 +274,15 @@ def bench_sweep(n=1024, ms=(2, 4, 8, 16, 32, 64), example1=True):
             return secs / k
 
         row["fast_ms"] = run(lambda: ndl.ndl_apply_fast(plan, u, o, 1)) * 1e3
+        ndl.ndl_plan_set_fast_method(plan, 1)  # the row variant of Steps 2 and 3
+        row["rows_ms"] = run(lambda: ndl.ndl_apply_fast(plan, u, o, 1)) * 1e3
+        ndl.ndl_plan_set_fast_method(plan, 0)
         if delta < 0.5:
             ndl.ndl_autotune(plan)
             row["direct_ms"] = run(lambda: ndl.ndl_apply(plan, u, o, 1)) * 1e3
             row["direct_tile"] = [plan.info().tile_x, plan.info().tile_y]
             row["fast_speedup"] = row["direct_ms"] / row["fast_ms"]
+            row["rows_speedup"] = row["direct_ms"] / row["rows_ms"]
         plan.close()
         out.append(row)
     return {"n": n, "profile": "const (p^0 exact)", "precision": "fp32 data, fp64 panel sums", "points": out}

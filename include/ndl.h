@@ -117,6 +117,8 @@ typedef struct {
                              2 = column by column for run-time horizons (2D
                              diffusion with J > 7); variants with the same order
                              give bitwise identical results */
+    int32_t fast_method;  /* method of ndl_apply_fast: 0 = dyadic panels (Steps 1-3
+                             of Section 3), 1 = row prefix sums */
 } ndl_plan_info;
 int ndl_plan_get_info(ndl_plan plan, ndl_plan_info* info);
 
@@ -145,6 +147,17 @@ int ndl_apply_fast(ndl_plan plan, const void* u, void* Lu, int batch, void* stre
  * that overlap on one GPU (different streams, or threads without ordering)
  * race; calls ordered on one stream do not. */
 int ndl_apply_fast_noalloc(ndl_plan plan, const void* u, void* Lu, int batch, void* stream);
+
+/* Method of the hierarchical path of a plan made with want_fast != 0:
+ * 0 = the dyadic panels of Section 3 (default); 1 = row prefix sums, the
+ * variant with per-row interval sums in place of the dyadic decomposition
+ * (the "other geometries than boxes" of the conclusion): Step 2 becomes
+ * compensated FP64 prefix sums of u along every row of the padded box, and
+ * Step 3 sums, per node, the 2J+1 (2D; (2J+1)^2 in 3D) row intervals of its
+ * ball.  The row method serves diffusion with a degree-0 polynomial part
+ * (power profiles and K = 0); NDL_EUNSUPPORTED otherwise.  ndl_autotune on
+ * such a plan also times both methods and keeps the faster. */
+int ndl_plan_set_fast_method(ndl_plan plan, int method);
 
 /* Step 1 as used by ndl_apply_fast, for one node (test hook): writes up to cap
  * panels as (s, j_1..j_dim) int32 records, s = log2 of the panel side in

@@ -149,6 +149,21 @@ int ndl_plan_get_info(ndl_plan plan, ndl_plan_info* info)
     info->variant = p->variant;
     info->fast_levels = p->fast ? p->fast_S + 1 : 0;
     info->pairs_per_point = p->avg_ball;
+    info->fast_method = p->fast_method;
+    return NDL_OK;
+}
+
+int ndl_plan_set_fast_method(ndl_plan plan, int method)
+{
+    if (!plan) { set_error("null plan"); return NDL_EINVAL; }
+    Plan* p = reinterpret_cast<Plan*>(plan);
+    if (!p->fast) { set_error("plan was created without want_fast"); return NDL_EINVAL; }
+    if (method < 0 || method > 1) { set_error("fast method %d: 0 (dyadic panels) or 1 (row prefix sums)", method); return NDL_EINVAL; }
+    if (method >= fast_num_methods(*p)) {
+        set_error("the row method serves diffusion with a degree-0 polynomial part");
+        return NDL_EUNSUPPORTED;
+    }
+    p->fast_method = method;
     return NDL_OK;
 }
 

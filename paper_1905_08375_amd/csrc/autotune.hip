@@ -67,11 +67,7 @@ void tune_cache_store(const std::string& key, int variant)
     save_file(key, variant);
 }
 
-__global__ void k_fill_ones(float* a, int64_t n)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i] = 1.0f;
-}
+
 
 // time every variant applying L to u (batch states) into out; keep the fastest
 static int tune_variants(Plan& p, const void* u, void* out, int batch, hipStream_t s, int* best_out)
@@ -109,8 +105,58 @@ static int tune_variants(Plan& p, const void* u, void* out, int batch, hipStream
     return rc;
 }
 
+__global__ void k_fill_ones(float* a, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 1.0f;
+}
+
+// the faster method of the hierarchical path (dyadic panels or row prefix sums)
+static int autotune_fast(Plan& p, hipStream_t s)
+{
+    if (fast_num_methods(p) < 2 || !p.d_pyr) return NDL_OK;
+    const std::string key = "fast." + key_of(p, 1);
+    int cached = 0;
+    if (tune_cache_lookup(key, &cached)) {
+        p.fast_method = cached;
+        return NDL_OK;
+    }
+    size_t es = elem_size(p.prec);
+    void *u = nullptr, *o = nullptr;
+    NDL_HIP(hipMalloc(&u, (size_t)p.NP * es));
+    NDL_HIP(hipMalloc(&o, (size_t)p.N * es));
+    const int64_t nf = (int64_t)(p.NP * es / sizeof(float));
+    k_fill_ones<<<(unsigned)((nf + 255) / 256), 256, 0, s>>>((float*)u, nf);
+    hipEvent_t e0, e1;
+    NDL_HIP(hipEventCreate(&e0));
+    NDL_HIP(hipEventCreate(&e1));
+    float t[2] = {1e30f, 1e30f};
+    int rc = NDL_OK;
+    for (int round = 0; round < 3 && rc == NDL_OK; ++round)
+        for (int m = 0; m < 2 && rc == NDL_OK; ++m) {
+            p.fast_method = m;
+            rc = launch_fast(p, u, o, 1, s);
+            (void)hipEventRecord(e0, s);
+            for (int r = 0; r < 5 && rc == NDL_OK; ++r) rc = launch_fast(p, u, o, 1, s);
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            t[m] = std::min(t[m], ms);
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(u);
+    (void)hipFree(o);
+    p.fast_method = t[1] < t[0] ? 1 : 0;
+    if (rc != NDL_OK) return rc;
+    tune_cache_store(key, p.fast_method);
+    return NDL_OK;
+}
+
 int autotune(Plan& p, hipStream_t s)
 {
+    NDL_TRY(autotune_fast(p, s));
     if (!direct_2d_applies(p)) return NDL_OK;  // one variant only
     const std::string key = key_of(p, 1);
     int cached = 0;

@@ -103,6 +103,7 @@ struct Plan {
     std::vector<int64_t> lev_off;   // offsets of each level in d_pyr (elements)
     std::vector<int64_t> lev_ext;   // panels per axis on each level
     int fast_deg = 0;          // moment degree of the panels (0: partial sums)
+    int fast_method = 0;       // 0: dyadic panels (Steps 1-3), 1: row prefix sums (degree 0 diffusion)
     double* d_pyr = nullptr;   // panel moments, FP64, all levels
     int64_t pyr_elems = 0;
     double* d_wtab = nullptr;  // full-ball sums of the polynomial part per cutoff k
@@ -121,6 +122,8 @@ int launch_fast(Plan& p, const void* u, void* Lu, int batch, hipStream_t s, doub
 // the static pyramid workspace of the calling thread's current device
 int fast_static_workspace(double** ptr, int64_t* capacity_elems);
 int fast_decomp_host(Plan& p, const int64_t* node, int32_t* out, int cap, int* count);
+// 1 if the plan's hierarchical path can run the row variant
+int fast_num_methods(const Plan& p);
 int autotune(Plan& p, hipStream_t s);
 // the direct kernel's tile tuned on the caller's state at the caller's batch
 int autotune_apply(Plan& p, const void* u, int batch, hipStream_t s);

@@ -316,6 +316,55 @@ __global__ __launch_bounds__(256) void k_mom_next(const double* __restrict__ pre
     for (int q = 0; q < NC * NM; ++q) o[q] = acc[q];
 }
 
+// ------------------------------------------------------------------ rows (Step 2')
+// The row variant of the partial sums: per row of the padded box (all axes
+// but the last fixed), compensated prefix sums of u along the row, kept as a
+// pair (hi, lo) of FP64 values with hi + lo the exact running sum up to the
+// rounding of lo.  S[row][j] = sum_{t < j} u[row][t], j = 0..P; the sum of
+// any interval [a, b] is (hi[b+1] - hi[a]) + (lo[b+1] - lo[a]), accurate to
+// the interval's own size however far along the row it lies.  One wave per
+// row: chunks of 64 values, an inclusive scan across the lanes with exact
+// two-sums, and a carry from chunk to chunk.
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e)
+{
+    s = a + b;
+    const double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_row_prefix(const T* __restrict__ u, double2* __restrict__ S, int64_t P,
+                                                    int64_t nrows)
+{
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= nrows) return;
+    const int lane = threadIdx.x & 63;
+    const T* ur = u + row * P;
+    double2* Sr = S + row * (P + 1);
+    if (lane == 0) Sr[0] = make_double2(0.0, 0.0);
+    double chi = 0.0, clo = 0.0;  // carry: the row's sum so far
+    for (int64_t c0 = 0; c0 < P; c0 += 64) {
+        const int64_t j = c0 + lane;
+        double hi = j < P ? (double)ur[j] : 0.0, lo = 0.0;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const double ohi = __shfl_up(hi, o, 64), olo = __shfl_up(lo, o, 64);
+            if (lane >= o) {
+                double s, e;
+                two_sum(ohi, hi, s, e);
+                hi = s;
+                lo = lo + olo + e;
+            }
+        }
+        double s, e;
+        two_sum(chi, hi, s, e);
+        const double slo = clo + lo + e;
+        if (j < P) Sr[j + 1] = make_double2(s, slo);
+        chi = __shfl(s, 63, 64);
+        clo = __shfl(slo, 63, 64);
+    }
+}
+
 // ------------------------------------------------------------------ Step 3
 struct FastArgs {
     int R, S;
@@ -399,7 +448,7 @@ __device__ inline void panel_pd(const double* mu, const double* D, double* F)
 // MODEL 0 diffusion (NC = 1), 1 peridynamics (NC = DIM).  DEG: moment degree.
 // KAPPA: a direct remainder (power profiles).  STAGE: u of the tile plus a halo
 // of the ball's reach in LDS (remainder and single-node panels read there).
-template <typename T, int DIM, int MODEL, int DEG, bool KAPPA, bool STAGE>
+template <typename T, int DIM, int MODEL, int DEG, bool KAPPA, bool STAGE, int METHOD = 0>
 __global__ __launch_bounds__(256) void k_fast_step3(const T* __restrict__ u, T* __restrict__ out,
                                                     const double* __restrict__ pyr, FastArgs a,
                                                     const int32_t* __restrict__ kk, const T* __restrict__ sc,
@@ -564,7 +613,30 @@ __global__ __launch_bounds__(256) void k_fast_step3(const T* __restrict__ u, T* 
             }
         }
     };
-    decompose_runs<I>(DIM, (I)P, xp, (I)k, emit);
+    if (METHOD == 0) {
+        decompose_runs<I>(DIM, (I)P, xp, (I)k, emit);
+    } else {
+        // rows: for every row offset (a, b) of the ball, the interval
+        // |z_last| <= isqrt(k - a^2 - b^2) from the row's prefix sums
+        const double2* S = reinterpret_cast<const double2*>(pyr);
+        const I J = isqrt_i<I>((I)k);
+        const I J0 = DIM == 3 ? J : 0, J1 = DIM >= 2 ? J : 0;
+        double ghi = 0.0, glo = 0.0;
+        for (I a = -J0; a <= J0; ++a)
+            for (I b2 = -J1; b2 <= J1; ++b2) {
+                const I rem = (I)k - a * a - b2 * b2;
+                if (rem < 0) continue;
+                const I w = isqrt_i<I>(rem);
+                int64_t row = 0;
+                if (DIM == 2) row = (int64_t)(xp[0] + b2);
+                if (DIM == 3) row = (int64_t)(xp[0] + a) * P + (int64_t)(xp[1] + b2);
+                const double2* Sr = S + row * (P + 1);
+                const double2 hi = Sr[xp[DIM - 1] + w + 1], lo = Sr[xp[DIM - 1] - w];
+                ghi += hi.x - lo.x;
+                glo += hi.y - lo.y;
+            }
+        G[0] = ghi + glo;
+    }
     // eq. "nonlocalP": minus the polynomial summed over the full ball times u(x);
     // the tables are indexed by k (1D: by the ball's reach isqrt(k))
     const int64_t kw = DIM == 1 ? (int64_t)isqrt_i<int64_t>((int64_t)k) : (int64_t)k;
@@ -721,6 +793,13 @@ int fast_prepare(Plan& p, hipStream_t s, bool with_workspace)
         p.lev_ext[sc] = E;
         tot += c * nm;
     }
+    // the row variant (partial sums of degree 0 only) keeps two doubles per
+    // prefix entry, (P + 1) entries per row, in the same buffer
+    if (deg == 0 && p.model == NDL_DIFFUSION) {
+        int64_t rows = 1;
+        for (int a = 0; a < p.dim - 1; ++a) rows *= p.P;
+        tot = std::max<int64_t>(tot, 2 * rows * (p.P + 1));
+    }
     p.pyr_elems = tot;
     if (with_workspace) NDL_HIP(hipMalloc(&p.d_pyr, std::max<int64_t>(1, tot) * sizeof(double)));
     // per-node weight of the polynomial part (power profiles)
@@ -801,10 +880,10 @@ static bool fast_stage(const Plan& p)
     return fast_lds(p, a) <= 96 * 1024;
 }
 
-template <typename T, int DIM, int MODEL, int DEG, bool KAPPA, bool STAGE>
+template <typename T, int DIM, int MODEL, int DEG, bool KAPPA, bool STAGE, int METHOD>
 static int step3_launch(Plan& p, const FastArgs& a, const T* ub, T* ob, const double* pyr, hipStream_t s)
 {
-    auto fn = k_fast_step3<T, DIM, MODEL, DEG, KAPPA, STAGE>;
+    auto fn = k_fast_step3<T, DIM, MODEL, DEG, KAPPA, STAGE, METHOD>;
     const size_t lds = STAGE ? fast_lds(p, a) : 0;
     if (lds > 48 * 1024)
         NDL_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -816,12 +895,23 @@ static int step3_launch(Plan& p, const FastArgs& a, const T* ub, T* ob, const do
     return NDL_OK;
 }
 
-template <typename T, int DIM, int MODEL, int DEG>
+template <typename T, int DIM, int MODEL, int DEG, int METHOD>
 static int step3_dispatch(Plan& p, const FastArgs& a, const T* ub, T* ob, const double* pyr, hipStream_t s)
 {
-    if (!fast_has_kappa(p)) return step3_launch<T, DIM, MODEL, DEG, false, false>(p, a, ub, ob, pyr, s);
-    if (a.H > 0) return step3_launch<T, DIM, MODEL, DEG, true, true>(p, a, ub, ob, pyr, s);
-    return step3_launch<T, DIM, MODEL, DEG, true, false>(p, a, ub, ob, pyr, s);
+    if (!fast_has_kappa(p)) return step3_launch<T, DIM, MODEL, DEG, false, false, METHOD>(p, a, ub, ob, pyr, s);
+    if (a.H > 0) return step3_launch<T, DIM, MODEL, DEG, true, true, METHOD>(p, a, ub, ob, pyr, s);
+    return step3_launch<T, DIM, MODEL, DEG, true, false, METHOD>(p, a, ub, ob, pyr, s);
+}
+
+template <typename T>
+static int rows_launch(Plan& p, const T* ub, double* pyr, hipStream_t s)
+{
+    int64_t rows = 1;
+    for (int a = 0; a < p.dim - 1; ++a) rows *= p.P;
+    k_row_prefix<T><<<dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s>>>(ub, reinterpret_cast<double2*>(pyr),
+                                                                           p.P, rows);
+    NDL_HIP(hipGetLastError());
+    return NDL_OK;
 }
 
 template <typename T, int DIM, int DEG, int NC>
@@ -862,8 +952,15 @@ static int launch_fast_k(Plan& p, const void* u, void* Lu, int batch, hipStream_
     for (int b = 0; b < batch; ++b) {
         const T* ub = static_cast<const T*>(u) + (int64_t)b * NC * p.NP;
         T* ob = static_cast<T*>(Lu) + (int64_t)b * NC * p.N;
+        if constexpr (MODEL == 0 && DEG == 0) {
+            if (p.fast_method == 1) {
+                NDL_TRY(rows_launch<T>(p, ub, pyr, s));
+                NDL_TRY((step3_dispatch<T, DIM, MODEL, DEG, 1>(p, a, ub, ob, pyr, s)));
+                continue;
+            }
+        }
         NDL_TRY((step2_launch<T, DIM, DEG, NC>(p, ub, pyr, s)));
-        NDL_TRY((step3_dispatch<T, DIM, MODEL, DEG>(p, a, ub, ob, pyr, s)));
+        NDL_TRY((step3_dispatch<T, DIM, MODEL, DEG, 0>(p, a, ub, ob, pyr, s)));
     }
     return NDL_OK;
 }
@@ -929,6 +1026,8 @@ int fast_static_workspace(double** ptr, int64_t* capacity_elems)
     *capacity_elems = kStaticWorkspaceBytes / (int64_t)sizeof(double);
     return NDL_OK;
 }
+
+int fast_num_methods(const Plan& p) { return p.fast && p.fast_deg == 0 && p.model == NDL_DIFFUSION ? 2 : 1; }
 
 // Device-side record of one node's decomposition (in the tree over the padded
 // box: node coordinates shifted by the collar), for the parity test.

@@ -28,7 +28,7 @@ EXPORTS = [
     "ndl_net_save", "ndl_net_load", "ndl_net_num_params", "ndl_net_train_step", "ndl_precond_apply",
     "ndl_autotune", "ndl_last_error", "ndl_version", "ndl_plan_set_variant", "ndl_plan_num_variants",
     "ndl_net_conv_test", "ndl_net_train_step_energy", "ndl_net_layer_tensor", "ndl_apply_fast_noalloc",
-    "ndl_autotune_apply", "ndl_div_batch_apply",
+    "ndl_autotune_apply", "ndl_div_batch_apply", "ndl_plan_set_fast_method",
 ]
 
 
@@ -42,7 +42,8 @@ class ndl_problem(C.Structure):
 class ndl_plan_info(C.Structure):
     _fields_ = [("n_points", C.c_int64), ("k_max", C.c_int64), ("k_min", C.c_int64), ("ncomp", C.c_int32),
                 ("tile_x", C.c_int32), ("tile_y", C.c_int32), ("tile_z", C.c_int32), ("variant", C.c_int32),
-                ("fast_levels", C.c_int32), ("pairs_per_point", C.c_double), ("pair_order", C.c_int32)]
+                ("fast_levels", C.c_int32), ("pairs_per_point", C.c_double), ("pair_order", C.c_int32),
+                ("fast_method", C.c_int32)]
 
 
 class ndl_cg_opts(C.Structure):
@@ -100,6 +101,7 @@ def lib():
             "ndl_div_batch_apply": [C.POINTER(vp), C.c_int, C.POINTER(vp), C.POINTER(vp), C.c_int,
                                     C.POINTER(C.c_int), C.POINTER(C.c_int), vp],
             "ndl_plan_set_variant": [vp, C.c_int],
+            "ndl_plan_set_fast_method": [vp, C.c_int],
             "ndl_plan_num_variants": [vp, C.POINTER(C.c_int)],
             "ndl_net_train_step_energy": [vp, vp, C.c_int, vp, vp, C.c_float, C.POINTER(C.c_float), vp],
             "ndl_net_conv_test": [C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp, vp, vp],
@@ -220,6 +222,10 @@ def ndl_decompose_node(dim: int, n: int, node: Sequence[int], k: int, cap: int =
 
 def ndl_plan_set_variant(plan: Plan, variant: int):
     _check(lib().ndl_plan_set_variant(plan.handle, int(variant)), "ndl_plan_set_variant")
+
+
+def ndl_plan_set_fast_method(plan: Plan, method: int):
+    _check(lib().ndl_plan_set_fast_method(plan.handle, int(method)), "ndl_plan_set_fast_method")
 
 
 def ndl_plan_num_variants(plan: Plan) -> int:

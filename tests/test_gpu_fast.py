@@ -155,3 +155,71 @@ def test_fast_rejects_unsupported_plans():
         with pytest.raises(ndl.NdlError) as e:
             ndl.ndl_plan_create(ndl.make_problem(2, n, 4, d, c, prec=ndl.NDL_F64, **kw), want_fast=1, keep=(d, c))
         assert e.value.code == ndl.NDL_EUNSUPPORTED
+
+
+def _fast_rows(dim, n, R, delta, c, u, prec, method, **kw):
+    import torch
+    from gpuhelp import dev, torch_dtype
+    d_d, d_c = dev(delta, prec), dev(c, prec)
+    plan = ndl.ndl_plan_create(ndl.make_problem(dim, n, R, d_d, d_c, prec=prec, **kw), want_fast=1, keep=(d_d, d_c))
+    ndl.ndl_plan_set_fast_method(plan, method)
+    assert plan.info().fast_method == method
+    out = torch.zeros((n,) * dim, dtype=torch_dtype(prec), device="cuda")
+    ndl.ndl_apply_fast(plan, dev(u, prec), out, 1)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy().astype(np.float64)
+    plan.close()
+    return res
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("dim,n,R,mlo,mhi,kernel", [
+    (2, 90, 7, 2.0, 6.0, ndl.NDL_G_FRAC),
+    (2, 70, 17, 4.0, 16.0, ndl.NDL_G_CONST),
+    (1, 300, 30, 5.0, 30.0, ndl.NDL_G_INV_R),
+    (3, 21, 4, 2.0, 4.0, ndl.NDL_G_FRAC),
+    (3, 19, 6, 2.0, 6.0, ndl.NDL_G_CONST),
+])
+def test_fast_rows_equals_direct(prec, dim, n, R, mlo, mhi, kernel):
+    """The row variant of Steps 2 and 3 (compensated prefix sums per row, 2J+1
+    row intervals per node in 2D) against the direct-sum oracle, collar data
+    included, next to the dyadic method on the same inputs."""
+    say(f"case fast rows dim={dim} n={n} kernel={kernel} prec={prec}")
+    delta, c, u = rand_problem(dim, n, R, mlo, mhi, seed=910 + n, smooth=True)
+    kw = dict(kernel=kernel)
+    ref = oracle_apply(dim, n, R, delta, c, u, prec, **kw)
+    for method in (1, 0):
+        got = _fast_rows(dim, n, R, delta, c, u, prec, method, **kw)
+        err = rel_l2(got, ref)
+        say(f"  method {method} rel l2 {err:.3e}")
+        assert err <= TOL[prec]
+
+
+def test_fast_rows_example1():
+    """Example 1 (delta = 1/2, C = 1, p^0 = 1, zero volume constraint) at n = 128
+    through the row variant: 129 row intervals per node instead of ~10^4 pairs."""
+    say("case example1 rows")
+    n, R = 128, 65
+    delta = np.full((n, n), 0.5)
+    c = np.ones((n, n))
+    g = np.random.default_rng(3)
+    u = np.zeros((n + 2 * R, n + 2 * R))
+    u[R:-R, R:-R] = g.standard_normal((n, n))
+    kw = dict(kernel=ndl.NDL_G_CONST, norm=ndl.NDL_NORM_NONE)
+    got = _fast_rows(2, n, R, delta, c, u, ndl.NDL_F64, 1, **kw)
+    P = O.Problem(dim=2, n=n, R=R, kernel="const", norm="none")
+    ref = O.fast_apply_const(P, delta, c, u[R:-R, R:-R])
+    assert rel_l2(got, ref) <= 1e-12
+
+
+def test_fast_rows_rejected_where_it_does_not_apply():
+    import torch
+    n = 16
+    d = torch.full((n, n), 3.0 / n, dtype=torch.float64, device="cuda")
+    c = torch.ones((n, n), dtype=torch.float64, device="cuda")
+    for kw in [dict(kernel=ndl.NDL_G_POLY, poly=P2), dict(model=ndl.NDL_PERIDYNAMIC, kernel=ndl.NDL_G_INV_R)]:
+        plan = ndl.ndl_plan_create(ndl.make_problem(2, n, 4, d, c, prec=ndl.NDL_F64, **kw), want_fast=1, keep=(d, c))
+        with pytest.raises(ndl.NdlError) as e:
+            ndl.ndl_plan_set_fast_method(plan, 1)
+        assert e.value.code == ndl.NDL_EUNSUPPORTED
+        plan.close()
