@@ -35,7 +35,7 @@ class Problem:
     n: int
     R: int
     model: str = "diffusion"      # or "peridynamic"
-    form: str = "nd"              # case (a) "nd" or case (b) "div"
+    form: str = "nd"              # case (a) "nd", case (b) "div", kernel-averaged "sym"
     kernel: str = "frac"
     s: float = 0.5
     poly: Sequence[float] = field(default_factory=lambda: [1.0])
@@ -69,11 +69,12 @@ def lib():
         L.or_norm.argtypes = [P, C.c_int64, C.c_double, C.c_double]
         L.or_profile.restype = C.c_double
         L.or_profile.argtypes = [P, C.c_double]
-        for f in (L.or_apply_nd, L.or_apply_div, L.or_fast_apply_const):
+        for f in (L.or_apply_nd, L.or_apply_div, L.or_apply_sym, L.or_fast_apply_const):
             f.restype = C.c_int
             f.argtypes = [P, dp, dp, dp, dp]
-        L.or_div_diag.restype = C.c_int
-        L.or_div_diag.argtypes = [P, dp, dp, dp]
+        for f in (L.or_div_diag, L.or_sym_diag):
+            f.restype = C.c_int
+            f.argtypes = [P, dp, dp, dp]
         L.or_decompose.restype = C.c_int64
         L.or_decompose.argtypes = [C.c_int, C.c_int64, C.POINTER(C.c_int64), C.c_int64,
                                    C.POINTER(C.c_int), C.POINTER(C.c_int64), C.c_int64]
@@ -93,7 +94,7 @@ def lib():
 def _prob(p: Problem):
     poly = np.ascontiguousarray(np.asarray(p.poly, dtype=np.float64))
     s = _Prob(p.dim, p.n, p.R, 1 if p.model == "peridynamic" else 0,
-              1 if p.form == "div" else 0, KERNELS[p.kernel], float(p.s), len(poly) - 1,
+              {"nd": 0, "div": 1, "sym": 2}[p.form], KERNELS[p.kernel], float(p.s), len(poly) - 1,
               poly.ctypes.data_as(C.POINTER(C.c_double)), NORMS[p.norm], p.second_moment())
     return s, poly
 
@@ -131,7 +132,7 @@ def apply(p: Problem, delta, coef, u_padded) -> np.ndarray:
     delta = _f64(delta); coef = _f64(coef); u = _f64(u_padded)
     ncomp = p.dim if p.model == "peridynamic" else 1
     out = np.zeros((ncomp,) + (p.n,) * p.dim)
-    fn = lib().or_apply_div if p.form == "div" else lib().or_apply_nd
+    fn = {"div": lib().or_apply_div, "sym": lib().or_apply_sym, "nd": lib().or_apply_nd}[p.form]
     rc = fn(C.byref(s), _d(delta), _d(coef), _d(u), _d(out))
     if rc != 0:
         raise ValueError("oracle: collar narrower than the horizon")
@@ -139,10 +140,13 @@ def apply(p: Problem, delta, coef, u_padded) -> np.ndarray:
 
 
 def div_diag(p: Problem, delta, coef) -> np.ndarray:
+    """Diagonal of -L with a zero collar (case (b) for form "div", the
+    kernel-averaged form for "sym")."""
     s, keep = _prob(p)
     delta = _f64(delta); coef = _f64(coef)
     out = np.zeros((p.n,) * p.dim)
-    lib().or_div_diag(C.byref(s), _d(delta), _d(coef), _d(out))
+    fn = lib().or_sym_diag if p.form == "sym" else lib().or_div_diag
+    fn(C.byref(s), _d(delta), _d(coef), _d(out))
     return out
 
 

@@ -33,7 +33,8 @@ typedef struct {
     int64_t n;          /* nodes per axis */
     int R;              /* collar width of the padded state */
     int model;          /* 0: scalar diffusion, 1: linear bond-based peridynamics (dim 2 or 3) */
-    int form;           /* 0: case (a), C and delta depend on x only; 1: case (b), symmetrised */
+    int form;           /* 0: case (a), C and delta depend on x only; 1: case (b), symmetrised;
+                           2: kernel-averaged, omega_s(x,y) = (omega_x(y) + omega_y(x)) / 2 */
     int kernel;         /* profile g: 0 const, 1 1/r, 2 r^-(d+2s), 3 even polynomial p(r), 4 cone (1-r)/r */
     double s;           /* fractional order for kernel 2 */
     int K;              /* kernel 3: p(r) = sum_{j<=K} poly[j] r^(2j) */
@@ -382,6 +383,69 @@ int or_div_diag(const or_problem* p, const double* delta, const double* coef, do
     g_memo = NULL;
     free(mm.T);
     return 0;
+}
+
+/* ------------------------------------------------------------------ kernel-averaged form */
+/* The symmetric operator with the average of the two case (a) kernels of a
+ * pair (cases (a) and (b) of Section 2: the case (a) weight omega_x(y) =
+ * c_x A_x g(|z|/m_x) on the ball of x; averaging it with omega_y(x) makes the
+ * pair weight symmetric):
+ *   L u_i = sum_{z != 0} w_s(i, i+z) (u_{i+z} - u_i) h^d,
+ *   w_s(i, j) = (omega_i(j) + omega_j(i)) / 2 for j in Omega,
+ *   w_s(i, j) = omega_i(j) for j in the collar.
+ * diag != NULL: writes sum_j w_s(i, j) h^d (the diagonal of -L) instead. */
+static double nd_weight(const or_problem* p, const double* delta, const double* coef, int64_t i, int64_t q)
+{
+    int64_t k = or_cutoff(delta[i], p->n);
+    if (q > k) return 0.0;
+    double m = delta[i] * (double)p->n;
+    return coef[i] * or_norm(p, k, m, delta[i]) * or_profile(p, sqrt((double)q) / m);
+}
+
+static int sym_apply(const or_problem* p, const double* delta, const double* coef, const double* u,
+                     double* out, int diag)
+{
+    int d = p->dim;
+    int64_t N = npoints(p);
+    double hd = pow(1.0 / (double)p->n, (double)d);
+    int64_t J = div_reach(p, delta);
+    if (J > p->R) return -1;
+    moment_memo mm = {0, NULL};
+    if (p->norm == 0 && p->kernel <= 2) { memo_build(p, max_cutoff(p, delta), &mm); g_memo = &mm; }
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; i++) {
+        int64_t x[3], y[3], z[3] = {0, 0, 0};
+        unflatten(p, i, x);
+        int64_t lo1 = d >= 2 ? -J : 0, hi1 = d >= 2 ? J : 0;
+        int64_t lo2 = d >= 3 ? -J : 0, hi2 = d >= 3 ? J : 0;
+        int64_t xi = pidx(p, x);
+        double acc = 0.0;
+        for (z[0] = -J; z[0] <= J; z[0]++)
+            for (z[1] = lo1; z[1] <= hi1; z[1]++)
+                for (z[2] = lo2; z[2] <= hi2; z[2]++) {
+                    int64_t q = z[0] * z[0] + z[1] * z[1] + z[2] * z[2];
+                    if (q == 0) continue;
+                    for (int a = 0; a < 3; a++) y[a] = x[a] + z[a];
+                    double w = nd_weight(p, delta, coef, i, q);
+                    if (in_omega(p, y)) w = 0.5 * (w + nd_weight(p, delta, coef, gidx(p, y), q));
+                    if (w == 0.0) continue;
+                    acc += diag ? w * hd : w * (u[pidx(p, y)] - u[xi]) * hd;
+                }
+        out[i] = acc;
+    }
+    g_memo = NULL;
+    free(mm.T);
+    return 0;
+}
+
+int or_apply_sym(const or_problem* p, const double* delta, const double* coef, const double* u, double* out)
+{
+    return sym_apply(p, delta, coef, u, out, 0);
+}
+
+int or_sym_diag(const or_problem* p, const double* delta, const double* coef, double* diag)
+{
+    return sym_apply(p, delta, coef, NULL, diag, 1);
 }
 
 /* ------------------------------------------------------------------ Section 3 */

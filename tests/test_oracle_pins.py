@@ -430,3 +430,48 @@ def test_cg_matches_dense_solve():
     A = -assemble(P, delta, c)
     xd = np.linalg.solve(A, b.ravel())
     assert np.linalg.norm(x.ravel() - xd) <= 1e-8 * np.linalg.norm(xd)
+
+
+# --------------------------------------------------------------- kernel-averaged form
+@pytest.mark.parametrize("dim,n", [(1, 30), (2, 9), (3, 5)])
+@pytest.mark.parametrize("kname,kw", [("frac", {"s": 0.5}), ("const", {}), ("inv_r", {})])
+def test_sym_is_the_average_of_case_a_and_its_transpose(dim, n, kname, kw):
+    """The kernel-averaged operator against the case (a) matrix assembled from
+    unit vectors: every in-grid off-diagonal entry is (A_a[i,j] + A_a[j,i]) / 2,
+    the diagonal makes every row of the full operator (collar partners
+    included) sum to zero, the matrix is symmetric and -A is positive definite
+    (Cholesky), and L of a constant is exactly 0."""
+    R = 4
+    g = np.random.default_rng(60 + dim)
+    delta = g.uniform(1.3, 4.0, (n,) * dim) / n
+    c = np.exp(g.normal(0.0, 0.5, (n,) * dim))
+    Pa = O.Problem(dim=dim, n=n, R=R, form="nd", kernel=kname, **kw)
+    Ps = O.Problem(dim=dim, n=n, R=R, form="sym", kernel=kname, **kw)
+    Aa = assemble(Pa, delta, c)
+    As = assemble(Ps, delta, c)
+    N = n ** dim
+    off = ~np.eye(N, dtype=bool)
+    assert np.allclose(As[off], (0.5 * (Aa + Aa.T))[off], rtol=1e-13, atol=0)
+    assert np.abs(As - As.T).max() <= 1e-13 * np.abs(As).max()
+    np.linalg.cholesky(-As)
+    # the diagonal: minus the in-grid weights minus the collar weights of case (a)
+    collar = -Aa.sum(axis=1)  # case (a) rows sum to minus the collar weights
+    assert np.allclose(np.diag(As), -(As.sum(axis=1) - np.diag(As)) - collar, rtol=1e-12, atol=0)
+    assert np.allclose(O.div_diag(Ps, delta, c).ravel(), -np.diag(As), rtol=1e-12, atol=0)
+    u = np.full((n + 2 * R,) * dim, 1.625)
+    assert np.all(O.apply(Ps, delta, c, u) == 0.0)
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_sym_with_constant_fields_is_case_a(dim):
+    """Constant delta and C: both kernels of a pair coincide, so the
+    kernel-averaged form is case (a) itself, collar data included."""
+    n = {1: 40, 2: 12, 3: 6}[dim]
+    R = 5
+    delta = np.full((n,) * dim, 3.4 / n)
+    c = np.full((n,) * dim, 0.8)
+    u = np.random.default_rng(dim).standard_normal((n + 2 * R,) * dim)
+    Pa = O.Problem(dim=dim, n=n, R=R, form="nd", kernel="frac")
+    Ps = O.Problem(dim=dim, n=n, R=R, form="sym", kernel="frac")
+    La, Ls = O.apply(Pa, delta, c, u), O.apply(Ps, delta, c, u)
+    assert np.abs(La - Ls).max() <= 1e-13 * np.abs(La).max()
