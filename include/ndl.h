@@ -60,7 +60,10 @@ enum {
  * with Kahan-compensated accumulation. */
 typedef enum { NDL_F64 = 0, NDL_F32C = 1, NDL_F32K = 2 } ndl_prec;
 typedef enum { NDL_DIFFUSION = 0, NDL_PERIDYNAMIC = 1 } ndl_model; /* PD: dim 2 or 3 */
-typedef enum { NDL_ND = 0, NDL_DIV = 1 } ndl_form;                 /* Section 2 cases (a), (b) */
+/* Section 2 cases (a), (b); NDL_SYM: the kernel-averaged symmetric form
+ * omega_s(x,y) = (omega_x(y) + omega_y(x))/2 of the case (a) weights (a
+ * collar partner keeps omega_x), whose negative is SPD; power profiles. */
+typedef enum { NDL_ND = 0, NDL_DIV = 1, NDL_SYM = 2 } ndl_form;
 /* Radial profile g(r), r = |y-x|/delta:  CONST 1 (the p^0 of Section 3);
  * INV_R 1/r and CONE (1 - r)/r (the two micromoduli of eq. "kernelgamma");
  * FRAC r^-(dim+2s) (fractional micromodulus, Section 1); POLY
@@ -173,8 +176,12 @@ int ndl_fast_decomposition(ndl_plan plan, const int64_t* node, int32_t* panels, 
 int ndl_decompose_node(int32_t dim, int64_t n, const int64_t* node, int64_t k, int32_t* panels,
                        int32_t cap, int32_t* count);
 
-/* Batched CG on -L x = b (case (b), zero volume constraint), one independent
- * problem per plan (uneven sizes allowed).  b, x: device FP64 arrays of n^dim
+/* Batched CG on -L x = b (case (b), or the kernel-averaged form; zero volume
+ * constraint), one independent problem per plan (uneven sizes allowed).
+ * NDL_SYM plans (FP64) run Jacobi-CG one problem after another, with the
+ * direct apply or, with opts->use_fast, the fast evaluation (the case (a)
+ * hierarchical gather plus its adjoint scatter); the final residual is
+ * recomputed with the direct apply.  For case (b):  b, x: device FP64 arrays of n^dim
  * (x holds the start value).  Stops when the FP64 true residual
  * ||b + L x|| / ||b|| <= rtol.  With NDL_F32C plans the inner iterations use
  * the compensated FP32 apply inside an FP64 iterative refinement; dot
@@ -188,6 +195,7 @@ typedef struct {
     void* net;            /* ndl_net for precond == 1 */
     int32_t graph_iters;  /* iterations per captured graph launch (0 = default) */
     double inner_rtol;    /* refinement: inner reduction per outer step (0 = default) */
+    int32_t use_fast;     /* NDL_SYM plans: iterate with ndl_apply_fast (plans made with want_fast) */
 } ndl_cg_opts;
 
 typedef struct {

@@ -29,7 +29,7 @@ static void free_plan(Plan* p)
 {
     if (!p) return;
     void* bufs[] = {p->d_k, p->d_scale, p->d_invm2, p->d_split, p->d_invT, p->d_pairs, p->d_pairw, p->d_wq,
-                    p->d_full, p->d_fullw, p->d_pyr, p->d_wtab};
+                    p->d_full, p->d_fullw, p->d_pyr, p->d_wtab, p->d_symws};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -48,7 +48,11 @@ static int validate(const ndl_problem* q)
         set_error("peridynamic model is implemented for dim 2 and 3");
         return NDL_EUNSUPPORTED;
     }
-    if (q->form != NDL_ND && q->form != NDL_DIV) { set_error("bad form"); return NDL_EINVAL; }
+    if (q->form != NDL_ND && q->form != NDL_DIV && q->form != NDL_SYM) { set_error("bad form"); return NDL_EINVAL; }
+    if (q->form == NDL_SYM && (q->model != NDL_DIFFUSION || q->kernel > NDL_G_FRAC)) {
+        set_error("the kernel-averaged form is implemented for diffusion with a power profile");
+        return NDL_EUNSUPPORTED;
+    }
     if (q->form == NDL_DIV && q->model == NDL_PERIDYNAMIC) {
         set_error("case (b) is implemented for the diffusion model");
         return NDL_EUNSUPPORTED;
@@ -117,6 +121,14 @@ int ndl_plan_create(const ndl_problem* prob, int want_fast, ndl_plan* out, void*
     int rc = plan_fields(*p, s);
     if (rc == NDL_OK && want_fast) {
         rc = fast_prepare(*p, s, want_fast != 2);
+        if (rc == NDL_OK && p->form == NDL_SYM) {
+            if (want_fast == 2) {
+                set_error("the kernel-averaged form's fast evaluation needs its workspace (want_fast = 1)");
+                rc = NDL_EUNSUPPORTED;
+            } else {
+                rc = sym_prepare(*p, s);
+            }
+        }
     }
     if (rc != NDL_OK) { free_plan(p); return rc; }
     *out = reinterpret_cast<ndl_plan>(p);
@@ -175,6 +187,7 @@ int ndl_apply(ndl_plan plan, const void* u, void* Lu, int batch, void* stream)
     if (batch > 65535) { set_error("batch too large (max 65535)"); return NDL_EINVAL; }
     hipStream_t s = (hipStream_t)stream;
     if (p->form == NDL_DIV) return launch_div(*p, u, Lu, batch, s);
+    if (p->form == NDL_SYM) return launch_sym(*p, u, Lu, batch, s);
     return launch_direct(*p, u, Lu, batch, s);
 }
 
@@ -188,6 +201,7 @@ int ndl_apply_fast(ndl_plan plan, const void* u, void* Lu, int batch, void* stre
         return NDL_EINVAL;
     }
     if (batch == 0) return NDL_OK;
+    if (p->form == NDL_SYM) return launch_sym_fast(*p, u, Lu, batch, (hipStream_t)stream);
     return launch_fast(*p, u, Lu, batch, (hipStream_t)stream);
 }
 
@@ -199,6 +213,10 @@ int ndl_apply_fast_noalloc(ndl_plan plan, const void* u, void* Lu, int batch, vo
     double* ws = nullptr;
     int64_t cap = 0;
     NDL_TRY(fast_static_workspace(&ws, &cap));
+    if (p->form == NDL_SYM) {
+        set_error("ndl_apply_fast_noalloc: the kernel-averaged form keeps a plan workspace (use ndl_apply_fast)");
+        return NDL_EUNSUPPORTED;
+    }
     if (p->pyr_elems > cap) {
         set_error("ndl_apply_fast_noalloc: the pyramid needs %lld bytes, the static workspace holds %lld",
                   (long long)(p->pyr_elems * (int64_t)sizeof(double)), (long long)(cap * (int64_t)sizeof(double)));

@@ -106,6 +106,7 @@ struct Plan {
     int fast_method = 0;       // 0: dyadic panels (Steps 1-3), 1: row prefix sums (degree 0 diffusion)
     double* d_pyr = nullptr;   // panel moments, FP64, all levels
     int64_t pyr_elems = 0;
+    double* d_symws = nullptr; // workspace of the fast kernel-averaged form
     double* d_wtab = nullptr;  // full-ball sums of the polynomial part per cutoff k
     int64_t fast_wrow = 0;     // row length of d_wtab
 };
@@ -114,6 +115,12 @@ struct Plan {
 int plan_fields(Plan& p, hipStream_t s);                   // k_i, scales, tables
 int launch_direct(Plan& p, const void* u, void* Lu, int batch, hipStream_t s);
 int launch_div(Plan& p, const void* u, void* Lu, int batch, hipStream_t s);
+// kernel-averaged symmetric form: direct sum, fast evaluation and its set-up, CG
+int launch_sym(Plan& p, const void* u, void* Lu, int batch, hipStream_t s);
+int launch_sym_fast(Plan& p, const void* u, void* Lu, int batch, hipStream_t s);
+int sym_prepare(Plan& p, hipStream_t s);
+int sym_cg_solve(const ndl_plan* plans, int nprob, const double* const* b, double* const* x,
+                 const ndl_cg_opts* opts, ndl_cg_report* reports, hipStream_t s);
 // with_workspace: allocate the plan's own pyramid buffer (ndl_apply_fast);
 // without it only ndl_apply_fast_noalloc can run the plan
 int fast_prepare(Plan& p, hipStream_t s, bool with_workspace);

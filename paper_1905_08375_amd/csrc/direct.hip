@@ -579,7 +579,7 @@ static int plan_fields_t(Plan& p, hipStream_t s)
         for (int64_t k = 0; k <= p.kmax; k++) tot += (double)hist[k] * (double)cnt[k];
         p.avg_ball = p.N > 0 ? tot / (double)p.N : 0.0;
     }
-    if (p.form == NDL_ND) {
+    if (p.form != NDL_DIV) {
         NDL_HIP(hipMalloc(&p.d_scale, p.N * elem_size(p.prec)));
         if (p.kernel == NDL_G_POLY || p.kernel == NDL_G_CONE) NDL_HIP(hipMalloc(&p.d_invm2, p.N * elem_size(p.prec)));
         ScaleArgs a = scale_args(p);

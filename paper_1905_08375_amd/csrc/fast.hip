@@ -761,8 +761,8 @@ static int fast_ncomp(const Plan& p) { return p.model == NDL_PERIDYNAMIC ? p.dim
 
 int fast_prepare(Plan& p, hipStream_t s, bool with_workspace)
 {
-    if (p.form != NDL_ND) {
-        set_error("the hierarchical path is implemented for case (a)");
+    if (p.form == NDL_DIV) {
+        set_error("the hierarchical path is implemented for case (a) and the kernel-averaged form");
         return NDL_EUNSUPPORTED;
     }
     const int deg = fast_degree(p);

@@ -1837,6 +1837,17 @@ int ndl_cg_solve(const ndl_plan* plans, int nprob, const double* const* b, doubl
     using namespace ndl;
     if (!plans || nprob <= 0 || !b || !x) { set_error("ndl_cg_solve: bad arguments"); return NDL_EINVAL; }
     const Plan* p0 = reinterpret_cast<const Plan*>(plans[0]);
+    if (p0 && p0->form == NDL_SYM) {
+        for (int i = 0; i < nprob; ++i) {
+            const Plan* p = reinterpret_cast<const Plan*>(plans[i]);
+            if (!p || !b[i] || !x[i] || p->form != NDL_SYM) {
+                set_error("ndl_cg_solve: plans of the kernel-averaged form and vectors expected (problem %d)", i);
+                return NDL_EINVAL;
+            }
+        }
+        if (opts && opts->precond != 0) { set_error("the kernel-averaged form runs Jacobi-CG"); return NDL_EUNSUPPORTED; }
+        return sym_cg_solve(plans, nprob, b, x, opts, reports, (hipStream_t)stream);
+    }
     for (int i = 0; i < nprob; ++i) {
         const Plan* p = reinterpret_cast<const Plan*>(plans[i]);
         if (!p || !b[i] || !x[i]) { set_error("ndl_cg_solve: null plan or vector %d", i); return NDL_EINVAL; }

@@ -17,7 +17,7 @@ NDL_OK, NDL_EINVAL, NDL_ENOMEM, NDL_EUNSUPPORTED, NDL_ENOTSPD, NDL_ENOCONV, NDL_
     0, -1, -2, -3, -4, -5, -6, -7
 NDL_F64, NDL_F32C, NDL_F32K = 0, 1, 2
 NDL_DIFFUSION, NDL_PERIDYNAMIC = 0, 1
-NDL_ND, NDL_DIV = 0, 1
+NDL_ND, NDL_DIV, NDL_SYM = 0, 1, 2
 NDL_G_CONST, NDL_G_INV_R, NDL_G_FRAC, NDL_G_POLY, NDL_G_CONE = 0, 1, 2, 3, 4
 NDL_NORM_DISCRETE, NDL_NORM_CONTINUOUS, NDL_NORM_NONE = 0, 1, 2
 
@@ -48,7 +48,7 @@ class ndl_plan_info(C.Structure):
 
 class ndl_cg_opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("precond", C.c_int32), ("net", C.c_void_p),
-                ("graph_iters", C.c_int32), ("inner_rtol", C.c_double)]
+                ("graph_iters", C.c_int32), ("inner_rtol", C.c_double), ("use_fast", C.c_int32)]
 
 
 class ndl_cg_report(C.Structure):
@@ -257,12 +257,13 @@ def ndl_div_batch_apply(plans: Sequence[Plan], x_list, y_list, variant: int = -1
 
 
 def ndl_cg_solve(plans: Sequence[Plan], b_list, x_list, rtol=1e-8, max_iter=200000, precond=0, net=None,
-                 graph_iters=0, inner_rtol=0.0, stream=None):
+                 graph_iters=0, inner_rtol=0.0, use_fast=False, stream=None):
     n = len(plans)
     ph = (C.c_void_p * n)(*[p.handle.value if isinstance(p.handle, C.c_void_p) else p.handle for p in plans])
     bp = (C.c_void_p * n)(*[_ptr(b) for b in b_list])
     xp = (C.c_void_p * n)(*[_ptr(x) for x in x_list])
-    opts = ndl_cg_opts(rtol, max_iter, precond, net.handle if net is not None else None, graph_iters, inner_rtol)
+    opts = ndl_cg_opts(rtol, max_iter, precond, net.handle if net is not None else None, graph_iters, inner_rtol,
+                       int(bool(use_fast)))
     reps = (ndl_cg_report * n)()
     rc = lib().ndl_cg_solve(ph, n, bp, xp, C.byref(opts), reps, _stream(stream))
     if rc not in (NDL_OK, NDL_ENOCONV):

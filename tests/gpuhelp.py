@@ -47,7 +47,7 @@ def dev(a, prec):
 
 def oracle_problem(dim, n, R, model, form, kernel, s, poly, norm):
     return O.Problem(dim=dim, n=n, R=R, model="peridynamic" if model == ndl.NDL_PERIDYNAMIC else "diffusion",
-                     form="div" if form == ndl.NDL_DIV else "nd", kernel=KNAME[kernel], s=s,
+                     form={ndl.NDL_DIV: "div", ndl.NDL_SYM: "sym"}.get(form, "nd"), kernel=KNAME[kernel], s=s,
                      poly=list(poly), norm=NNAME[norm])
 
 
