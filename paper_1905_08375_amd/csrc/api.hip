@@ -32,6 +32,8 @@ static void free_plan(Plan* p)
                     p->d_full, p->d_fullw, p->d_pyr, p->d_wtab, p->d_symws};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
+    for (int32_t* b : p->d_tord)
+        if (b) (void)hipFree(b);
     delete p;
 }
 
@@ -119,6 +121,7 @@ int ndl_plan_create(const ndl_problem* prob, int want_fast, ndl_plan* out, void*
     }
     hipStream_t s = (hipStream_t)stream;
     int rc = plan_fields(*p, s);
+    if (rc == NDL_OK) rc = tile_orders_2d(*p, s);
     if (rc == NDL_OK && want_fast) {
         rc = fast_prepare(*p, s, want_fast != 2);
         if (rc == NDL_OK && p->form == NDL_SYM) {

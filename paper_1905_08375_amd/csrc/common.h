@@ -93,6 +93,10 @@ struct Plan {
 
     // direct-kernel choice
     int variant = 0;
+    // block -> tile orders of the specialised 2D kernels for tiles of 8, 16
+    // and 32 rows (device), with the tile count each was built for
+    int32_t* d_tord[3] = {nullptr, nullptr, nullptr};
+    int tord_tiles[3] = {0, 0, 0};
     std::vector<double> w2d;   // pair weights of the specialised 2D kernel
     int tile_x = 0, tile_y = 0, tile_z = 0;
 
@@ -209,6 +213,8 @@ int launch_direct_2d_f64(Plan& p, const void* u, void* Lu, int batch, hipStream_
 int launch_direct_2d_f32c(Plan& p, const void* u, void* Lu, int batch, hipStream_t s);
 int launch_direct_2d_f32k(Plan& p, const void* u, void* Lu, int batch, hipStream_t s);
 int num_variants_2d();
+// plan-time block -> tile orders of the specialised 2D kernels (cost-balanced)
+int tile_orders_2d(Plan& p, hipStream_t s);
 void variant_tile_2d(const Plan& p, int variant, int* tx, int* ty);
 int variant_order_2d(const Plan& p, int variant);
 
