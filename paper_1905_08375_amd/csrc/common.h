@@ -162,6 +162,31 @@ __device__ __forceinline__ int xcd_tile(int b, int nb)
     return (b & 7) * per + (b >> 3);
 }
 
+// ------------------------------------------------------------------ staging
+// Fill the tot slots of an LDS tile: slot idx takes load(idx), written by
+// store(idx, value).  Each thread issues the loads of UNR slots before it
+// stores any of them, so UNR loads per thread are in flight at once (a loop
+// that loads and stores one slot per iteration waits a full memory round
+// trip per slot).
+template <int UNR = 4, typename F, typename G>
+__device__ __forceinline__ void stage_batched(int tot, F&& load, G&& store)
+{
+    using V = decltype(load(0));
+    for (int base = threadIdx.x; base < tot; base += UNR * (int)blockDim.x) {
+        V v[UNR];
+#pragma unroll
+        for (int r = 0; r < UNR; ++r) {
+            const int idx = base + r * (int)blockDim.x;
+            if (idx < tot) v[r] = load(idx);
+        }
+#pragma unroll
+        for (int r = 0; r < UNR; ++r) {
+            const int idx = base + r * (int)blockDim.x;
+            if (idx < tot) store(idx, v[r]);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ wave helpers
 __device__ __forceinline__ int wave_max(int v)
 {

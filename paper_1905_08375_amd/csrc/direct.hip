@@ -180,40 +180,22 @@ template <typename T>
 __device__ __forceinline__ void stage(T* __restrict__ lds, const T* __restrict__ f, const Box& B, const int* t0)
 {
     int tot = B.L[0] * B.L[1] * B.L[2];
-    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-        int l2 = idx % B.L[2];
-        int r = idx / B.L[2];
-        int l1 = r % B.L[1];
-        int l0 = r / B.L[1];
-        int g0 = t0[0] + B.rr[0] - B.halo[0] + l0;
-        int g1 = t0[1] + B.rr[1] - B.halo[1] + l1;
-        int g2 = t0[2] + B.rr[2] - B.halo[2] + l2;
-        T v = 0;
-        if (g0 >= 0 && g0 < B.pext[0] && g1 >= 0 && g1 < B.pext[1] && g2 >= 0 && g2 < B.pext[2])
-            v = f[((int64_t)g0 * B.pext[1] + g1) * B.pext[2] + g2];
-        lds[idx] = v;
-    }
-}
-
-// Stage a per-node field (unpadded grid) with halo; outside Omega -> `fill`.
-template <typename T>
-__device__ __forceinline__ void stage_grid(T* __restrict__ lds, const T* __restrict__ f, const Box& B, const int* t0,
-                                           T fill)
-{
-    int tot = B.L[0] * B.L[1] * B.L[2];
-    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-        int l2 = idx % B.L[2];
-        int r = idx / B.L[2];
-        int l1 = r % B.L[1];
-        int l0 = r / B.L[1];
-        int g0 = t0[0] - B.halo[0] + l0;
-        int g1 = t0[1] - B.halo[1] + l1;
-        int g2 = t0[2] - B.halo[2] + l2;
-        T v = fill;
-        if (g0 >= 0 && g0 < B.ext[0] && g1 >= 0 && g1 < B.ext[1] && g2 >= 0 && g2 < B.ext[2])
-            v = f[((int64_t)g0 * B.ext[1] + g1) * B.ext[2] + g2];
-        lds[idx] = v;
-    }
+    stage_batched(
+        tot,
+        [&](int idx) {
+            int l2 = idx % B.L[2];
+            int r = idx / B.L[2];
+            int l1 = r % B.L[1];
+            int l0 = r / B.L[1];
+            int g0 = t0[0] + B.rr[0] - B.halo[0] + l0;
+            int g1 = t0[1] + B.rr[1] - B.halo[1] + l1;
+            int g2 = t0[2] + B.rr[2] - B.halo[2] + l2;
+            T v = 0;
+            if (g0 >= 0 && g0 < B.pext[0] && g1 >= 0 && g1 < B.pext[1] && g2 >= 0 && g2 < B.pext[2])
+                v = f[((int64_t)g0 * B.pext[1] + g1) * B.pext[2] + g2];
+            return v;
+        },
+        [&](int idx, T v) { lds[idx] = v; });
 }
 
 // ------------------------------------------------------------------ case (a)

@@ -492,20 +492,24 @@ __global__ __launch_bounds__(256) void k_fast_step3(const T* __restrict__ u, T* 
     T* ob = out + (int64_t)blockIdx.y * NC * a.N;
     const int tot = a.L[0] * a.L[1] * a.L[2];
     if (STAGE) {
-        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-            const int l2 = idx % a.L[2];
-            const int rr = idx / a.L[2];
-            const int l1 = rr % a.L[1];
-            const int l0 = rr / a.L[1];
-            // padded coordinates of the staged node
-            const int g0 = U0 ? org[0] + a.R - a.H + l0 : 0;
-            const int g1 = U1 ? org[1] + a.R - a.H + l1 : 0;
-            const int g2 = org[2] + a.R - a.H + l2;
-            const bool in = g0 >= 0 && g0 < P0 && g1 >= 0 && g1 < P1 && g2 >= 0 && g2 < P;
-            const int64_t gg = ((int64_t)g0 * P1 + g1) * P + g2;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) tile[c * tot + idx] = in ? ub[c * a.NP + gg] : T(0);
-        }
+        for (int c = 0; c < NC; ++c)
+            stage_batched(
+                tot,
+                [&](int idx) {
+                    const int l2 = idx % a.L[2];
+                    const int rr = idx / a.L[2];
+                    const int l1 = rr % a.L[1];
+                    const int l0 = rr / a.L[1];
+                    // padded coordinates of the staged node
+                    const int g0 = U0 ? org[0] + a.R - a.H + l0 : 0;
+                    const int g1 = U1 ? org[1] + a.R - a.H + l1 : 0;
+                    const int g2 = org[2] + a.R - a.H + l2;
+                    const bool in = g0 >= 0 && g0 < P0 && g1 >= 0 && g1 < P1 && g2 >= 0 && g2 < P;
+                    const int64_t gg = ((int64_t)g0 * P1 + g1) * P + g2;
+                    return in ? ub[c * a.NP + gg] : T(0);
+                },
+                [&](int idx, T v) { tile[c * tot + idx] = v; });
     }
     __syncthreads();
 

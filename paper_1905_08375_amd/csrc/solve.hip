@@ -126,20 +126,36 @@ __global__ __launch_bounds__(256) void k_div_items(const Inst* __restrict__ inst
             s_q[q] = o.w;
             s_fw[q] = fw[q];
         }
-        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-            int l2 = idx % L[2];
-            int r = idx / L[2];
-            int l1 = r % L[1];
-            int l0 = r / L[1];
-            int g0 = org[0] - halo[0] + l0, g1 = org[1] - halo[1] + l1, g2 = org[2] - halo[2] + l2;
-            bool in = g0 >= 0 && g0 < ext[0] && g1 >= 0 && g1 < ext[1] && g2 >= 0 && g2 < ext[2];
-            int64_t gg = ((int64_t)g0 * ext[1] + g1) * ext[2] + g2;
-            if (!DIAG) tu[idx] = in ? p[gg] : T(0);
-            if (STAGE) {
-                td[idx] = in ? dlt[gg] : T(-1);
-                tc[idx] = in ? cf[gg] : T(0);
-            }
-        }
+        struct Slot {
+            T u, d, c;
+        };
+        stage_batched(
+            tot,
+            [&](int idx) {
+                int l2 = idx % L[2];
+                int r = idx / L[2];
+                int l1 = r % L[1];
+                int l0 = r / L[1];
+                int g0 = org[0] - halo[0] + l0, g1 = org[1] - halo[1] + l1, g2 = org[2] - halo[2] + l2;
+                bool in = g0 >= 0 && g0 < ext[0] && g1 >= 0 && g1 < ext[1] && g2 >= 0 && g2 < ext[2];
+                int64_t gg = ((int64_t)g0 * ext[1] + g1) * ext[2] + g2;
+                Slot v{T(0), T(-1), T(0)};
+                if (in) {
+                    if (!DIAG) v.u = p[gg];
+                    if (STAGE) {
+                        v.d = dlt[gg];
+                        v.c = cf[gg];
+                    }
+                }
+                return v;
+            },
+            [&](int idx, const Slot& v) {
+                if (!DIAG) tu[idx] = v.u;
+                if (STAGE) {
+                    td[idx] = v.d;
+                    tc[idx] = v.c;
+                }
+            });
         __syncthreads();
         double dot = 0.0;
         const double nh = 0.5 * (double)I.n;
@@ -312,26 +328,41 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
         const int z0 = org[0] + sub * TZ, y0 = org[1], x0 = org[2];
         const int nz = DIM == 3 ? n : 1;
         double mmax = 0.0, mmin = 1e300;
-        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-            const int sz = idx / PLANE, rem = idx - sz * PLANE;
-            const int r = rem / PITCH, c = rem - r * PITCH;
-            const int gz = z0 - HZ + sz, gy = y0 - J + r, gx = x0 - J + c;
-            const bool in = gz >= 0 && gz < nz && gy >= 0 && gy < n && gx >= 0 && gx < n;
-            const int64_t gg = ((int64_t)gz * n + gy) * n + gx;
-            MT m = MT(-1);
-            T cc = 0, uu = 0;
-            if (in) {
-                m = SC ? (MT)((double)dlt[gg] * nh) : (MT)dlt[gg];
-                cc = (T)((double)cf[gg] * ch);
-                if (!DIAG) uu = p[gg];
-                const double ms = SC ? (double)m : (double)m * nh;
-                mmax = fmax(mmax, ms);
-                mmin = fmin(mmin, ms);
-            }
-            tm[idx] = m;
-            tcc[idx] = cc;
-            tu[idx] = uu;
-        }
+        struct Slot {
+            D d, c;
+            T u;
+            bool in;
+        };
+        stage_batched(
+            tot,
+            [&](int idx) {
+                const int sz = idx / PLANE, rem = idx - sz * PLANE;
+                const int r = rem / PITCH, c = rem - r * PITCH;
+                const int gz = z0 - HZ + sz, gy = y0 - J + r, gx = x0 - J + c;
+                const bool in = gz >= 0 && gz < nz && gy >= 0 && gy < n && gx >= 0 && gx < n;
+                const int64_t gg = ((int64_t)gz * n + gy) * n + gx;
+                Slot v{D(0), D(0), T(0), in};
+                if (in) {
+                    v.d = dlt[gg];
+                    v.c = cf[gg];
+                    if (!DIAG) v.u = p[gg];
+                }
+                return v;
+            },
+            [&](int idx, const Slot& v) {
+                MT m = MT(-1);
+                T cc = 0;
+                if (v.in) {
+                    m = SC ? (MT)((double)v.d * nh) : (MT)v.d;
+                    cc = (T)((double)v.c * ch);
+                    const double ms = SC ? (double)m : (double)m * nh;
+                    mmax = fmax(mmax, ms);
+                    mmin = fmin(mmin, ms);
+                }
+                tm[idx] = m;
+                tcc[idx] = cc;
+                tu[idx] = v.u;
+            });
         // block extremes of m (uniform loop bounds)
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) {

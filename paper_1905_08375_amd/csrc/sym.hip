@@ -74,17 +74,32 @@ __global__ __launch_bounds__(256) void k_direct_sym(const T* __restrict__ u, T* 
     const int hal[3] = {g.L[0] > g.E[0] ? g.H : 0, g.L[1] > g.E[1] ? g.H : 0, g.H};
     const T* ub = u + (int64_t)blockIdx.y * g.NP;
     T* ob = out + (int64_t)blockIdx.y * g.N;
-    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-        const int l2 = idx % g.L[2], rr = idx / g.L[2], l1 = rr % g.L[1], l0 = rr / g.L[1];
-        const int x0 = org[0] - hal[0] + l0, x1 = org[1] - hal[1] + l1, x2 = org[2] - hal[2] + l2;
-        const bool in = x0 >= 0 && x0 < g.ext[0] && x1 >= 0 && x1 < g.ext[1] && x2 >= 0 && x2 < g.ext[2];
-        const int p0 = x0 + g.rr[0], p1 = x1 + g.rr[1], p2 = x2 + g.rr[2];
-        const bool pin = p0 >= 0 && p0 < g.pext[0] && p1 >= 0 && p1 < g.pext[1] && p2 >= 0 && p2 < g.pext[2];
-        const int64_t gi = ((int64_t)x0 * g.ext[1] + x1) * g.ext[2] + x2;
-        tu[idx] = (!DIAG && pin) ? ub[((int64_t)p0 * g.pext[1] + p1) * g.pext[2] + p2] : T(0);
-        tk[idx] = in ? kk[gi] : -1;
-        ts[idx] = in ? sc[gi] : T(0);
-    }
+    struct Slot {
+        T u, s;
+        int k;
+    };
+    stage_batched(
+        tot,
+        [&](int idx) {
+            const int l2 = idx % g.L[2], rr = idx / g.L[2], l1 = rr % g.L[1], l0 = rr / g.L[1];
+            const int x0 = org[0] - hal[0] + l0, x1 = org[1] - hal[1] + l1, x2 = org[2] - hal[2] + l2;
+            const bool in = x0 >= 0 && x0 < g.ext[0] && x1 >= 0 && x1 < g.ext[1] && x2 >= 0 && x2 < g.ext[2];
+            const int p0 = x0 + g.rr[0], p1 = x1 + g.rr[1], p2 = x2 + g.rr[2];
+            const bool pin = p0 >= 0 && p0 < g.pext[0] && p1 >= 0 && p1 < g.pext[1] && p2 >= 0 && p2 < g.pext[2];
+            const int64_t gi = ((int64_t)x0 * g.ext[1] + x1) * g.ext[2] + x2;
+            Slot v{T(0), T(0), -1};
+            if (!DIAG && pin) v.u = ub[((int64_t)p0 * g.pext[1] + p1) * g.pext[2] + p2];
+            if (in) {
+                v.k = kk[gi];
+                v.s = sc[gi];
+            }
+            return v;
+        },
+        [&](int idx, const Slot& v) {
+            tu[idx] = v.u;
+            tk[idx] = v.k;
+            ts[idx] = v.s;
+        });
     __syncthreads();
     const int e2 = threadIdx.x % g.E[2], e1 = (threadIdx.x / g.E[2]) % g.E[1], e0 = threadIdx.x / (g.E[2] * g.E[1]);
     const int x0 = org[0] + e0, x1 = org[1] + e1, x2 = org[2] + e2;
