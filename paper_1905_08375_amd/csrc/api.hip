@@ -29,7 +29,7 @@ static void free_plan(Plan* p)
 {
     if (!p) return;
     void* bufs[] = {p->d_k, p->d_scale, p->d_invm2, p->d_split, p->d_invT, p->d_pairs, p->d_pairw, p->d_wq,
-                    p->d_full, p->d_fullw, p->d_pyr, p->d_wtab, p->d_symws};
+                    p->d_full, p->d_fullw, p->d_pyr, p->d_wtab, p->d_symws, p->d_kseg};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (int32_t* b : p->d_tord)

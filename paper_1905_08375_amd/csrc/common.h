@@ -97,6 +97,8 @@ struct Plan {
     // and 32 rows (device), with the tile count each was built for
     int32_t* d_tord[3] = {nullptr, nullptr, nullptr};
     int tord_tiles[3] = {0, 0, 0};
+    // largest and smallest cutoff of every 64 x 4 node segment (device)
+    int2* d_kseg = nullptr;
     std::vector<double> w2d;   // pair weights of the specialised 2D kernel
     int tile_x = 0, tile_y = 0, tile_z = 0;
 
