@@ -313,9 +313,34 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
         constexpr int TZ = SH::TZ, TY = SH::TY, HZ = DIM == 3 ? J : 0;
         constexpr int PITCH = 64 + 2 * J, SY = TY + 2 * J, SZ = TZ + 2 * HZ;
         constexpr int PLANE = SY * PITCH, tot = SZ * PLANE;
+        // LDS tile: horizon m, coefficient c and vector u of every staged node.
+        // In 3D, FP32 vectors keep a node's three values side by side (one
+        // address per offset for the reads of both nodes of a lane); FP64
+        // vectors keep three arrays (side by side they would not fit the 3D
+        // tile), and so does 2D (its rows of 4 nodes per lane reach past the
+        // paired-read offset range either way)
+        constexpr bool AOS = F32 && DIM == 3;
+        struct Node {
+            MT m;
+            T c, u;
+        };
+        static_assert(!AOS || sizeof(Node) == sizeof(MT) + 2 * sizeof(T), "packed node");
+        Node* tn = reinterpret_cast<Node*>(smem_raw);
         MT* tm = reinterpret_cast<MT*>(smem_raw);
         T* tcc = reinterpret_cast<T*>(tm + tot);
         T* tu = tcc + tot;
+        auto lm = [&](int i) -> MT& {
+            if constexpr (AOS) return tn[i].m;
+            else return tm[i];
+        };
+        auto lc = [&](int i) -> T& {
+            if constexpr (AOS) return tn[i].c;
+            else return tcc[i];
+        };
+        auto lu = [&](int i) -> T& {
+            if constexpr (AOS) return tn[i].u;
+            else return tu[i];
+        };
         const T* p = pvec + I.off;
         const D* dlt = static_cast<const D*>(I.delta);
         const D* cf = static_cast<const D*>(I.coef);
@@ -359,9 +384,9 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
                     mmax = fmax(mmax, ms);
                     mmin = fmin(mmin, ms);
                 }
-                tm[idx] = m;
-                tcc[idx] = cc;
-                tu[idx] = v.u;
+                lm(idx) = m;
+                lc(idx) = cc;
+                lu(idx) = v.u;
             });
         // block extremes of m (uniform loop bounds)
 #pragma unroll
@@ -392,7 +417,7 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
         constexpr int WPP = SH::TY / PY;  // waves per plane
         const int wz = wv / WPP, wy = (wv % WPP) * PY;
         const int base = (wz + HZ) * PLANE + (wy + J) * PITCH + lane + J;
-        double mi[PY];
+        double mi[PY], mh[PY];  // m of the node (scaled by n/2 when SC), and m n / 2
         T cci[PY], ui[PY];
         bool valid[PY];
         Acc<T> acc[PY];
@@ -403,9 +428,13 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
             // tile's largest horizon, so that every pair they form has m_ij > 0
             // and 0 <= k_ij <= k_max (within the table); they are not stored
             valid[j] = x < n && y0 + wy + j < n && z0 + wz < nz;
-            mi[j] = valid[j] ? (double)tm[base + j * PITCH] : (SC ? mmax : mmax / nh);
-            cci[j] = valid[j] ? tcc[base + j * PITCH] : T(0);
-            ui[j] = tu[base + j * PITCH];
+            mi[j] = valid[j] ? (double)lm(base + j * PITCH) : (SC ? mmax : mmax / nh);
+            // m n / 2 is exact in FP64 (an FP32 m times n / 2), so that
+            // fma(m_j, n / 2, m_i n / 2) rounds (m_i + m_j) n / 2 once, as the
+            // product of the exact sum does
+            mh[j] = SC ? mi[j] : (valid[j] ? mi[j] * nh : mmax);
+            cci[j] = valid[j] ? lc(base + j * PITCH) : T(0);
+            ui[j] = lu(base + j * PITCH);
             dsum[j] = 0.0;
         }
         // offsets [0, p_in) lie inside every pair's ball of the tile, [p_in, p_end)
@@ -422,8 +451,15 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
         };
         const int p_in = first_at_least(tmin);
         const int p_end = first_at_least(tmax);
-        // per-lane bases of the three staged fields: a partner read is the
-        // base plus the uniform offset (one add per field and offset)
+        // per-lane bases of the staged fields: a partner read is the base plus
+        // the uniform offset (one add per offset for the interleaved tile, one
+        // per field for the three arrays)
+        // the interleaved tile's lane base as an LDS pointer the compiler
+        // cannot split (its constant part would otherwise be re-added per
+        // offset to reach the paired-read offset range)
+        using LdsNode = const Node __attribute__((address_space(3)));
+        LdsNode* tnb = (LdsNode*)(tn + base);
+        asm volatile("" : "+v"(tnb));
         const MT* tmb = tm + base;
         const T* tcb = tcc + base;
         const T* tub = tu + base;
@@ -445,14 +481,15 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
 #pragma unroll
                 for (int j = 0; j < PY; ++j) {
                     const int jo = j * PITCH + off;
-                    double mj = (double)tmb[jo];
-                    T ccj = tcb[jo];
+                    LdsNode* np = tnb + off;
+                    double mj = AOS ? (double)np[j * PITCH].m : (double)tmb[jo];
+                    T ccj = AOS ? np[j * PITCH].c : tcb[jo];
                     if (EDGE) {
                         const bool out = mj < 0.0;
                         mj = out ? mi[j] : mj;
                         ccj = out ? cci[j] : ccj;
                     }
-                    const double a = SC ? mi[j] + mj : (mi[j] + mj) * nh;
+                    const double a = SC ? mi[j] + mj : fma(mj, nh, mh[j]);
                     const double t = a * a;
                     int kij = (int)ceil(t) - 1;
                     // |z|^2 < t  <=>  |z|^2 <= ceil(t) - 1 = k_ij for an integer |z|^2
@@ -462,7 +499,7 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
                     if (DIAG) {
                         dsum[j] += (double)w;
                     } else {
-                        acc[j].fma_(w, tub[jo] - ui[j]);
+                        acc[j].fma_(w, (AOS ? np[j * PITCH].u : tub[jo]) - ui[j]);
                     }
                 }
                 if (!DIAG && F32 && (q & 7) == 7) {
