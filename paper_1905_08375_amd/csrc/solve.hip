@@ -292,6 +292,7 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
     __shared__ double red[2 * NWAVES];
     __shared__ T tinv_s[256];
     __shared__ int s_q[kMaxOffs];
+    __shared__ T s_fw[kMaxOffs];  // profile weight |z|^expo of the offsets, in the vectors' type
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -349,7 +350,10 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
         __syncthreads();  // the previous item's readers are done
         for (int k = threadIdx.x; k <= I.kmax && k < 256; k += blockDim.x) tinv_s[k] = (T)Tinv[k];
         const int nq = I.nq < kMaxOffs ? I.nq : kMaxOffs;
-        for (int q = threadIdx.x; q < nq; q += blockDim.x) s_q[q] = full[q].w;
+        for (int q = threadIdx.x; q < nq; q += blockDim.x) {
+            s_q[q] = full[q].w;
+            s_fw[q] = (T)fw[q];
+        }
         const int z0 = org[0] + sub * TZ, y0 = org[1], x0 = org[2];
         const int nz = DIM == 3 ? n : 1;
         double mmax = 0.0, mmin = 1e300;
@@ -471,13 +475,11 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
             // the table entries of the next offset are loaded one iteration
             // ahead (the table carries one sentinel entry past its end)
             int4 o = full[pb];
-            double fwq = fw[pb];
             for (int q = pb; q < pe; ++q) {
                 const int off = (DIM == 3 ? o.x * PLANE : 0) + o.y * PITCH + o.z;
                 const int qi = o.w;  // |z|^2 >= 1: the table holds no zero offset
-                const T fq = (T)fwq;
+                const T fq = s_fw[q];
                 o = full[q + 1];
-                fwq = fw[q + 1];
 #pragma unroll
                 for (int j = 0; j < PY; ++j) {
                     const int jo = j * PITCH + off;
