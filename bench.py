@@ -404,6 +404,20 @@ def bench_1d(steps=200):
             "note": "4096 nodes, graph replays: launch-latency bound"}
 
 
+def calib_copy(mib=256, reps=20):
+    """A plain copy of known size (256 MiB read + 256 MiB written per copy), the
+    reference that scales the rocprofv3 FETCH_SIZE / WRITE_SIZE counters of the
+    measured kernels to bytes."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"mib": mib, "copies": reps}
+
+
 def cpu_baseline(budget_s=12.0):
     """The FP64 oracle on the same workload (FP32-rounded inputs), on the host cores."""
     import oracle as O
@@ -434,7 +448,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-rows", action="store_true", help="headline only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", default="", help="run one row only (profiling): cg64, pcg3d, net, pd, pdfast, ex2, big, sweep, fast, f64, 1d")
+    ap.add_argument("--only", default="", help="run one row only (profiling): cg64, pcg3d, net, pd, pdfast, ex2, big, sweep, fast, f64, 1d, "
+                         "or calib (the counter calibration copy)")
     ap.add_argument("--cg-iters", type=int, default=0, help="cap the solver iterations (profiling)")
     ap.add_argument("--variant", type=int, default=None,
                     help="fixed tile variant for the headline instead of the autotuner's (profiling runs)")
@@ -451,7 +466,7 @@ def main():
         fn = {"cg64": lambda: bench_solve(max_iter=args.cg_iters or None),
               "pcg3d": lambda: bench_pcg_3d(max_iter=args.cg_iters or None),
               "net": bench_net, "pd": bench_pd, "pdfast": lambda: bench_pd(fast=True), "ex2": bench_example2,
-              "big": bench_big, "1d": bench_1d, "sweep": bench_sweep, "f64": lambda: bench_apply(ndl.NDL_F64, False, args.steps, args.warmup)["seconds"],
+              "big": bench_big, "1d": bench_1d, "calib": calib_copy, "sweep": bench_sweep, "f64": lambda: bench_apply(ndl.NDL_F64, False, args.steps, args.warmup)["seconds"],
               "fast": lambda: bench_apply(ndl.NDL_F32C, True, args.steps, args.warmup)["seconds"]}[args.only]
         print(json.dumps({"only": args.only, "result": fn()}, default=str), flush=True)
         return

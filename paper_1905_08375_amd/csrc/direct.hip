@@ -76,12 +76,28 @@ __global__ __launch_bounds__(256) void k_cutoffs(const T* __restrict__ delta, in
     }
 }
 
-// histogram of the integer cutoffs (for the average ball size)
-__global__ __launch_bounds__(256) void k_khist(const int32_t* __restrict__ kk, int64_t N,
+// histogram of the integer cutoffs (for the average ball size): per block in
+// LDS when the nbins = k_max + 1 bins fit (kKhistLds), then one global add per
+// non-empty bin; else straight into the global bins
+constexpr int kKhistLds = 4096;
+__global__ __launch_bounds__(256) void k_khist(const int32_t* __restrict__ kk, int64_t N, int nbins,
                                                unsigned long long* __restrict__ hist)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd(&hist[kk[i]], 1ull);
+    extern __shared__ unsigned int sh_hist[];
+    const bool in_lds = nbins <= kKhistLds;
+    if (in_lds) {
+        for (int b = threadIdx.x; b < nbins; b += blockDim.x) sh_hist[b] = 0u;
+        __syncthreads();
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        if (in_lds) atomicAdd(&sh_hist[kk[i]], 1u);
+        else atomicAdd(&hist[kk[i]], 1ull);
+    }
+    if (in_lds) {
+        __syncthreads();
+        for (int b = threadIdx.x; b < nbins; b += blockDim.x)
+            if (sh_hist[b]) atomicAdd(&hist[b], (unsigned long long)sh_hist[b]);
+    }
 }
 
 struct ScaleArgs {
@@ -551,7 +567,9 @@ static int plan_fields_t(Plan& p, hipStream_t s)
         unsigned long long* d_hist = nullptr;
         NDL_HIP(hipMalloc(&d_hist, (p.kmax + 1) * sizeof(unsigned long long)));
         NDL_HIP(hipMemsetAsync(d_hist, 0, (p.kmax + 1) * sizeof(unsigned long long), s));
-        k_khist<<<dim3(ncut), dim3(256), 0, s>>>(p.d_k, p.N, d_hist);
+        const int nbins = (int)(p.kmax + 1);
+        k_khist<<<dim3(ncut), dim3(256), nbins <= kKhistLds ? nbins * sizeof(unsigned int) : 0, s>>>(p.d_k, p.N,
+                                                                                                     nbins, d_hist);
         NDL_HIP(hipGetLastError());
         std::vector<unsigned long long> hist(p.kmax + 1);
         NDL_HIP(hipMemcpyAsync(hist.data(), d_hist, hist.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));

@@ -1768,6 +1768,19 @@ static int pcg_learned_t(const ndl_plan plan, const double* b, double* x, const 
     int iters = 0, outer = 0;
     bool jac = false, conv = false;
     double rel = 1.0;
+    // one problem: every node belongs to problem 0; its outer scale 1/||r||
+    // and active flag live on the device for the whole solve
+    DevBuf down, dsc, dact;
+    {
+        std::vector<int> own((N + 1023) / 1024, 0);
+        const int one = 1;
+        NDL_TRY(alloc<int>(down, own.size()));
+        NDL_TRY(alloc<double>(dsc, 1));
+        NDL_TRY(alloc<int>(dact, 1));
+        NDL_HIP(hipMemcpy(down.p, own.data(), own.size() * sizeof(int), hipMemcpyHostToDevice));
+        NDL_HIP(hipMemcpy(dact.p, &one, sizeof(int), hipMemcpyHostToDevice));
+    }
+    double sc = 1.0;  // host copy of the scale sent for the current outer step
     for (int o = 0; o < 20; ++o) {
         NDL_TRY(launch_div_items<double>(B, dres, dit, (const double*)vx.p, (double*)vax.p, (const int4*)d_full.p,
                                          (const double*)d_fw.p, nfull, (const double*)d_Tinv.p, nullptr, nullptr,
@@ -1783,21 +1796,10 @@ static int pcg_learned_t(const ndl_plan plan, const double* b, double* x, const 
         const double rn = std::sqrt(rn2);
         const double want = std::max(inner_rtol, 0.5 * rtol * bn / rn);
         // inner: -L d = r / ||r||
-        double sc = 1.0 / rn;
-        int owner0 = 0;
-        (void)owner0;
-        {
-            std::vector<int> own((N + 1023) / 1024, 0);
-            DevBuf down;
-            NDL_TRY(alloc<int>(down, own.size()));
-            NDL_HIP(hipMemcpyAsync(down.p, own.data(), own.size() * sizeof(int), hipMemcpyHostToDevice, s));
-            DevBuf dsc;
-            NDL_TRY(alloc<double>(dsc, 1));
-            NDL_HIP(hipMemcpyAsync(dsc.p, &sc, sizeof(double), hipMemcpyHostToDevice, s));
-            k_scale_copy<T, double><<<grid_for(N), 256, 0, s>>>(di, (const int*)down.p, N, (const double*)vr64.p,
-                                                                 (T*)vr.p, (const double*)dsc.p);
-            NDL_HIP(hipStreamSynchronize(s));
-        }
+        sc = 1.0 / rn;
+        NDL_HIP(hipMemcpyAsync(dsc.p, &sc, sizeof(double), hipMemcpyHostToDevice, s));
+        k_scale_copy<T, double><<<grid_for(N), 256, 0, s>>>(di, (const int*)down.p, N, (const double*)vr64.p,
+                                                             (T*)vr.p, (const double*)dsc.p);
         NDL_HIP(hipMemsetAsync(vd.p, 0, N * sizeof(T), s));
         NDL_TRY(precond((const T*)vr.p, (T*)vz.p, jac));
         double rz = 0.0, rr = 1.0, dummy = 0.0;
@@ -1865,20 +1867,9 @@ static int pcg_learned_t(const ndl_plan plan, const double* b, double* x, const 
             NDL_HIP(hipGetLastError());
         }
         // x += ||r|| d
-        {
-            std::vector<int> own((N + 1023) / 1024, 0);
-            DevBuf down, dsc, dact;
-            NDL_TRY(alloc<int>(down, own.size()));
-            NDL_TRY(alloc<double>(dsc, 1));
-            NDL_TRY(alloc<int>(dact, 1));
-            int one = 1;
-            NDL_HIP(hipMemcpyAsync(down.p, own.data(), own.size() * sizeof(int), hipMemcpyHostToDevice, s));
-            NDL_HIP(hipMemcpyAsync(dsc.p, &sc, sizeof(double), hipMemcpyHostToDevice, s));
-            NDL_HIP(hipMemcpyAsync(dact.p, &one, sizeof(int), hipMemcpyHostToDevice, s));
-            k_axpy_outer<T><<<grid_for(N), 256, 0, s>>>((const int*)down.p, N, (double*)vx.p, (const T*)vd.p,
-                                                         (const double*)dsc.p, (const int*)dact.p);
-            NDL_HIP(hipStreamSynchronize(s));
-        }
+        k_axpy_outer<T><<<grid_for(N), 256, 0, s>>>((const int*)down.p, N, (double*)vx.p, (const T*)vd.p,
+                                                     (const double*)dsc.p, (const int*)dact.p);
+        NDL_HIP(hipGetLastError());
     }
     NDL_HIP(hipMemcpyAsync(x, vx.p, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     NDL_HIP(hipStreamSynchronize(s));
