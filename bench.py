@@ -452,7 +452,8 @@ def main():
                          "or calib (the counter calibration copy)")
     ap.add_argument("--cg-iters", type=int, default=0, help="cap the solver iterations (profiling)")
     ap.add_argument("--variant", type=int, default=None,
-                    help="fixed tile variant for the headline instead of the autotuner's (profiling runs)")
+                    help="fixed tile variant for the headline (and --only f64) instead of the autotuner's "
+                         "(profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -466,7 +467,7 @@ def main():
         fn = {"cg64": lambda: bench_solve(max_iter=args.cg_iters or None),
               "pcg3d": lambda: bench_pcg_3d(max_iter=args.cg_iters or None),
               "net": bench_net, "pd": bench_pd, "pdfast": lambda: bench_pd(fast=True), "ex2": bench_example2,
-              "big": bench_big, "1d": bench_1d, "calib": calib_copy, "sweep": bench_sweep, "f64": lambda: bench_apply(ndl.NDL_F64, False, args.steps, args.warmup)["seconds"],
+              "big": bench_big, "1d": bench_1d, "calib": calib_copy, "sweep": bench_sweep, "f64": lambda: bench_apply(ndl.NDL_F64, False, args.steps, args.warmup, args.variant)["seconds"],
               "fast": lambda: bench_apply(ndl.NDL_F32C, True, args.steps, args.warmup)["seconds"]}[args.only]
         print(json.dumps({"only": args.only, "result": fn()}, default=str), flush=True)
         return
