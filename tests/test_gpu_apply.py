@@ -175,6 +175,34 @@ def test_pd_every_tile_variant(prec):
         assert plan.info().pair_order == 1
 
 
+def test_pd_full_workload():
+    """The peridynamic workload at its full size, as the benchmark runs it
+    (2048^2, 8 displacement fields in one launch, m in [3, 12], Voronoi c,
+    FP32 with Kahan sums, the tile tuned on these fields at batch 8): the
+    first and last fields against the oracle."""
+    import torch
+    from gpuhelp import dev
+    prec = ndl.NDL_F32K
+    w = F.peridynamic_2d()
+    n, R, B = 2048, 12, 8
+    say(f"case pd full workload n={n} batch={B}")
+    d_d, d_c, d_u = dev(w["delta"], prec), dev(w["coef"], prec), dev(w["u"], prec)
+    plan = ndl.ndl_plan_create(ndl.make_problem(2, n, R, d_d, d_c, model=ndl.NDL_PERIDYNAMIC,
+                                                kernel=ndl.NDL_G_INV_R, prec=prec), keep=(d_d, d_c))
+    ndl.ndl_autotune_apply(plan, d_u, B)
+    out = torch.zeros((B, 2, n, n), dtype=d_u.dtype, device="cuda")
+    ndl.ndl_apply(plan, d_u, out, B)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    kw = dict(model=ndl.NDL_PERIDYNAMIC, kernel=ndl.NDL_G_INV_R)
+    for b in (0, B - 1):
+        ref = oracle_apply(2, n, R, w["delta"], w["coef"], w["u"][b], prec, **kw)
+        err = rel_l2(o[b], ref)
+        say(f"  field {b} variant {plan.info().variant} rel l2 {err:.3e}")
+        assert err <= TOL[prec], b
+    plan.close()
+
+
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("dim,n,R", [(2, 70, 8), (3, 18, 4), (1, 200, 9)])
 def test_div(prec, dim, n, R):
