@@ -139,11 +139,12 @@ def bench_apply(prec, fast, steps, warmup, variant=None):
     from paper_1905_08375_amd import ndl
     w, n, R, d, c, u = c2_inputs(prec)
     plan = ndl.ndl_plan_create(ndl.make_problem(2, n, R, d, c, prec=prec), want_fast=fast, keep=(d, c))
-    if not fast:
-        if variant is None:
-            ndl.ndl_autotune(plan)  # plan-time tile choice (excluded from timing)
-        else:
-            ndl.ndl_plan_set_variant(plan, variant)  # a fixed tile (profiling runs)
+    if fast:
+        ndl.ndl_autotune(plan)  # plan-time choice of the hierarchical method (dyadic panels or rows)
+    elif variant is None:
+        ndl.ndl_autotune(plan)  # plan-time tile choice (excluded from timing)
+    else:
+        ndl.ndl_plan_set_variant(plan, variant)  # a fixed tile (profiling runs)
     out = torch.empty((n, n), dtype=u.dtype, device="cuda")
     fn = (lambda: ndl.ndl_apply_fast(plan, u, out, 1)) if fast else (lambda: ndl.ndl_apply(plan, u, out, 1))
     fn()
@@ -500,7 +501,8 @@ def main():
         for prec, nm in [(ndl.NDL_F32C, "fast_f32c"), (ndl.NDL_F64, "fast_f64")]:
             log("row:", nm)
             r = bench_apply(prec, True, k, 20)
-            rows[nm] = {"gpoint_per_s": N * k / r["seconds"] / 1e9, "us_per_apply": r["seconds"] / k * 1e6}
+            rows[nm] = {"gpoint_per_s": N * k / r["seconds"] / 1e9, "us_per_apply": r["seconds"] / k * 1e6,
+                        "method": "rows" if r["info"].fast_method == 1 else "dyadic panels"}
         log("row: direct vs hierarchical sweep over the horizon (constant profile)")
         rows["sweep_const_2d_1024"] = bench_sweep()
         log("row: 1D 4096 direct FP64")

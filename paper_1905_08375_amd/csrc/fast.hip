@@ -48,7 +48,9 @@ template <typename I>
 __host__ __device__ inline I isqrt_i(I v)
 {
     if (v < 0) return -1;
-    I r = (I)sqrt((double)v);
+    // first guess from a hardware square root (FP32 for 32-bit arguments: an
+    // error of a unit or two at most, which the corrections below remove)
+    I r = sizeof(I) <= 4 ? (I)sqrtf((float)v) : (I)sqrt((double)v);
     while (r * r > v) --r;
     while ((r + 1) * (r + 1) <= v) ++r;
     return r;
