@@ -628,18 +628,33 @@ __global__ __launch_bounds__(256) void k_fast_step3(const T* __restrict__ u, T* 
         const I J = isqrt_i<I>((I)k);
         const I J0 = DIM == 3 ? J : 0, J1 = DIM >= 2 ? J : 0;
         double ghi = 0.0, glo = 0.0;
+        // rows in groups of 4: the group's 8 loads are issued before any is
+        // used (rows past the ball add exact zeros, the sum order is the rows')
+        constexpr int RG = 4;
         for (I a = -J0; a <= J0; ++a)
-            for (I b2 = -J1; b2 <= J1; ++b2) {
-                const I rem = (I)k - a * a - b2 * b2;
-                if (rem < 0) continue;
-                const I w = isqrt_i<I>(rem);
-                int64_t row = 0;
-                if (DIM == 2) row = (int64_t)(xp[0] + b2);
-                if (DIM == 3) row = (int64_t)(xp[0] + a) * P + (int64_t)(xp[1] + b2);
-                const double2* Sr = S + row * (P + 1);
-                const double2 hi = Sr[xp[DIM - 1] + w + 1], lo = Sr[xp[DIM - 1] - w];
-                ghi += hi.x - lo.x;
-                glo += hi.y - lo.y;
+            for (I b0 = -J1; b0 <= J1; b0 += RG) {
+                double2 hv[RG], lv[RG];
+#pragma unroll
+                for (int i = 0; i < RG; ++i) {
+                    const I b2 = b0 + (I)i;
+                    const I rem = (I)k - a * a - b2 * b2;
+                    hv[i] = make_double2(0.0, 0.0);
+                    lv[i] = make_double2(0.0, 0.0);
+                    if (b2 <= J1 && rem >= 0) {
+                        const I w = isqrt_i<I>(rem);
+                        int64_t row = 0;
+                        if (DIM == 2) row = (int64_t)(xp[0] + b2);
+                        if (DIM == 3) row = (int64_t)(xp[0] + a) * P + (int64_t)(xp[1] + b2);
+                        const double2* Sr = S + row * (P + 1);
+                        hv[i] = Sr[xp[DIM - 1] + w + 1];
+                        lv[i] = Sr[xp[DIM - 1] - w];
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < RG; ++i) {
+                    ghi += hv[i].x - lv[i].x;
+                    glo += hv[i].y - lv[i].y;
+                }
             }
         G[0] = ghi + glo;
     }
