@@ -1556,31 +1556,65 @@ __global__ void k_dot2(const Inst* __restrict__ insts, const int2* __restrict__ 
     }
 }
 
-// p = z + beta p ; z_old = z
+// Device scalars of the flexible PCG inner solve (one problem):
+//   [0] alpha  [1] p.q  [2] breakdown flag (p.q <= 0 or not finite)
+//   [3] r.r    [4] (written with r.r, unused)
+//   [5] r.z of the current direction  [6] beta
+//   [7] flag: the last r.z was not positive or not finite
+constexpr int kLpcgScalars = 8;
+
+// p = z + beta p ; z_old = z (skipped while the r.z flag is set: the host
+// recomputes z by Jacobi first)
 template <typename T>
-__global__ void k_dir2(int64_t n, double beta, const T* __restrict__ z, T* __restrict__ p, T* __restrict__ zold)
+__global__ void k_dir2(int64_t n, const double* __restrict__ sc, const T* __restrict__ z, T* __restrict__ p,
+                       T* __restrict__ zold)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || sc[7] != 0.0) return;
+    const T beta = (T)sc[6];
     T zv = z[i];
-    p[i] = zv + (T)beta * p[i];
+    p[i] = zv + beta * p[i];
     zold[i] = zv;
 }
 
-// alpha = rz / p.q for one problem (items summed in the fixed order); a
-// breakdown (p.q <= 0 or not finite) gives alpha = 0 and flags it.
-// out[0] = alpha, out[1] = p.q, out[2] = breakdown flag.
-__global__ void k_pq_alpha(const Inst* __restrict__ insts, const double* __restrict__ part, double rz,
-                           double* __restrict__ out)
+// alpha = r.z / p.q (items summed in the fixed order).  A breakdown, or a
+// pending r.z flag, gives alpha = 0 (d and r stay as they are); only the
+// former raises the breakdown flag.
+__global__ void k_pq_alpha(const Inst* __restrict__ insts, const double* __restrict__ part, double* __restrict__ sc)
 {
     __shared__ double sh[256];
     const Inst I = insts[0];
     const double pq = problem_sum(I, part, sh);
     if (threadIdx.x != 0) return;
+    const bool pending = sc[7] != 0.0;
     const bool ok = pq > 0.0 && isfinite(pq);
-    out[0] = ok ? rz / pq : 0.0;
-    out[1] = pq;
-    out[2] = ok ? 0.0 : 1.0;
+    sc[0] = (ok && !pending) ? sc[5] / pq : 0.0;
+    sc[1] = pq;
+    sc[2] = (ok || pending) ? 0.0 : 1.0;
+}
+
+// r.z_new and r.z_old from the item partials -> the Polak-Ribiere beta
+// (clipped at 0) and the new r.z; restart = 1 only sets r.z (a new first
+// direction p = z).  A non-positive or non-finite r.z raises flag [7] and
+// leaves r.z and beta unchanged.
+__global__ void k_lpcg_beta(const Inst* __restrict__ insts, const double* __restrict__ pa,
+                            const double* __restrict__ pb, double* __restrict__ sc, int restart)
+{
+    __shared__ double sh[256];
+    const Inst I = insts[0];
+    const double rzn = problem_sum(I, pa, sh);
+    const double rzo = restart ? 0.0 : problem_sum(I, pb, sh);
+    if (threadIdx.x != 0) return;
+    if (!(rzn > 0.0) || !isfinite(rzn)) {
+        sc[7] = 1.0;
+        return;
+    }
+    if (!restart) {
+        double beta = (rzn - rzo) / sc[5];
+        sc[6] = beta >= 0.0 ? beta : 0.0;
+    }
+    sc[5] = rzn;
+    sc[7] = 0.0;
 }
 
 // d += alpha p, r -= alpha q over one problem's items, with the per-item
@@ -1718,8 +1752,8 @@ static int pcg_learned_t(const ndl_plan plan, const double* b, double* x, const 
     NDL_TRY(alloc<double>(pa, nitems));
     NDL_TRY(alloc<double>(pb, nitems));
     NDL_TRY(alloc<double>(sres, 2));
-    DevBuf scal;  // alpha, p.q, breakdown flag, r.r, (spare)
-    NDL_TRY(alloc<double>(scal, 5));
+    DevBuf scal;  // the inner solve's device scalars (k_pq_alpha, k_lpcg_beta)
+    NDL_TRY(alloc<double>(scal, kLpcgScalars));
     NDL_HIP(hipMemcpyAsync(vx.p, x, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     NDL_TRY(launch_div_items<T>(B, di, dit, (const T*)nullptr, (T*)vq.p, (const int4*)d_full.p, (const double*)d_fw.p,
                                 nfull, (const double*)d_Tinv.p, nullptr, nullptr, true, s));
@@ -1733,16 +1767,17 @@ static int pcg_learned_t(const ndl_plan plan, const double* b, double* x, const 
         NDL_HIP(hipStreamSynchronize(s));
         return NDL_OK;
     };
-    // r.a (and r.bb) with one read-back
-    auto dots = [&](const T* r, const T* a, const T* bb, double* o1, double* o2) -> int {
-        k_dot2<T><<<gi, 256, 0, s>>>(di, dit, nitems, r, a, bb, (double*)pa.p, (double*)pb.p);
-        k_item_sums2<<<1, 256, 0, s>>>(di, (const double*)pa.p, bb ? (const double*)pb.p : nullptr,
-                                       (double*)sres.p);
-        double h[2];
-        NDL_HIP(hipMemcpyAsync(h, sres.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    // r.z (and r.z_old) into the device scalars: restart = 1 starts a new
+    // first direction (r.z only), else beta as well
+    auto dots = [&](const T* r, const T* z, const T* zo, int restart) -> int {
+        k_dot2<T><<<gi, 256, 0, s>>>(di, dit, nitems, r, z, zo, (double*)pa.p, (double*)pb.p);
+        k_lpcg_beta<<<1, 256, 0, s>>>(di, (const double*)pa.p, (const double*)pb.p, (double*)scal.p, restart);
+        NDL_HIP(hipGetLastError());
+        return NDL_OK;
+    };
+    auto read_scalars = [&](double* h) -> int {
+        NDL_HIP(hipMemcpyAsync(h, scal.p, kLpcgScalars * sizeof(double), hipMemcpyDeviceToHost, s));
         NDL_HIP(hipStreamSynchronize(s));
-        *o1 = h[0];
-        if (bb) *o2 = h[1];
         return NDL_OK;
     };
     // two-level preconditioner: z = D^-1 r + M(r); the network supplies the
@@ -1802,68 +1837,72 @@ static int pcg_learned_t(const ndl_plan plan, const double* b, double* x, const 
                                                              (T*)vr.p, (const double*)dsc.p);
         NDL_HIP(hipMemsetAsync(vd.p, 0, N * sizeof(T), s));
         NDL_TRY(precond((const T*)vr.p, (T*)vz.p, jac));
-        double rz = 0.0, rr = 1.0, dummy = 0.0;
-        NDL_TRY(dots((const T*)vr.p, (const T*)vz.p, nullptr, &rz, &dummy));
-        if (!(rz > 0.0) || !std::isfinite(rz)) {
+        // first direction p = z; a non-positive r.z from the network falls
+        // back to Jacobi for the rest of the solve
+        double hs[kLpcgScalars];
+        NDL_TRY(dots((const T*)vr.p, (const T*)vz.p, nullptr, 1));
+        NDL_TRY(read_scalars(hs));
+        if (hs[7] != 0.0 && !jac) {
             jac = true;
             NDL_TRY(precond((const T*)vr.p, (T*)vz.p, true));
-            NDL_TRY(dots((const T*)vr.p, (const T*)vz.p, nullptr, &rz, &dummy));
+            NDL_TRY(dots((const T*)vr.p, (const T*)vz.p, nullptr, 1));
         }
+        // restart from the current r with the Jacobi preconditioner
+        auto restart_jacobi = [&]() -> int {
+            jac = true;
+            NDL_TRY(precond((const T*)vr.p, (T*)vz.p, true));
+            NDL_TRY(dots((const T*)vr.p, (const T*)vz.p, nullptr, 1));
+            NDL_HIP(hipMemcpyAsync(vp.p, vz.p, N * sizeof(T), hipMemcpyDeviceToDevice, s));
+            NDL_HIP(hipMemcpyAsync(vzo.p, vz.p, N * sizeof(T), hipMemcpyDeviceToDevice, s));
+            return NDL_OK;
+        };
         NDL_HIP(hipMemcpyAsync(vp.p, vz.p, N * sizeof(T), hipMemcpyDeviceToDevice, s));
         NDL_HIP(hipMemcpyAsync(vzo.p, vz.p, N * sizeof(T), hipMemcpyDeviceToDevice, s));
         double best = 1.0;
         int since_best = 0;
         while (iters < max_iter) {
+            // q = A p with the item partials of p.q; alpha, the update and r.r
+            // on the device; one read-back per iteration
             NDL_TRY(launch_div_items<T>(B, di, dit, (const T*)vp.p, (T*)vq.p, (const int4*)d_full.p,
                                         (const double*)d_fw.p, nfull, (const double*)d_Tinv.p, nullptr, (double*)pa.p,
                                         false, s));
-            // alpha on the device; the update and r.r in one pass (alpha = 0 on a
-            // breakdown, which leaves d and r as they were); one read-back
-            k_pq_alpha<<<1, 256, 0, s>>>(di, (const double*)pa.p, rz, (double*)scal.p);
+            k_pq_alpha<<<1, 256, 0, s>>>(di, (const double*)pa.p, (double*)scal.p);
             k_axpy2_rr<T><<<gi, 256, 0, s>>>(di, dit, nitems, (const double*)scal.p, (T*)vd.p, (T*)vr.p,
                                              (const T*)vp.p, (const T*)vq.p, (double*)pb.p);
             k_item_sums2<<<1, 256, 0, s>>>(di, (const double*)pb.p, nullptr, (double*)scal.p + 3);
-            double hs[5];
-            NDL_HIP(hipMemcpyAsync(hs, scal.p, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
-            NDL_HIP(hipStreamSynchronize(s));
-            const double pq = hs[1];
+            NDL_TRY(read_scalars(hs));
+            if (hs[7] != 0.0) {
+                // the previous iteration's r.z was not positive: its direction
+                // update and this iteration's step were skipped (alpha = 0);
+                // recompute z by Jacobi and take the update with it
+                if (jac) break;
+                jac = true;
+                NDL_TRY(precond((const T*)vr.p, (T*)vz.p, true));
+                NDL_TRY(dots((const T*)vr.p, (const T*)vz.p, (const T*)vzo.p, 0));
+                k_dir2<T><<<grid_for(N), 256, 0, s>>>(N, (const double*)scal.p, (const T*)vz.p, (T*)vp.p,
+                                                      (T*)vzo.p);
+                NDL_HIP(hipGetLastError());
+                continue;
+            }
             ++iters;
             if (hs[2] != 0.0) {
                 if (jac) break;  // even Jacobi broke down: stop this inner solve
-                jac = true;      // fall back and restart the inner directions
-                NDL_TRY(precond((const T*)vr.p, (T*)vz.p, true));
-                NDL_TRY(dots((const T*)vr.p, (const T*)vz.p, nullptr, &rz, &dummy));
-                NDL_HIP(hipMemcpyAsync(vp.p, vz.p, N * sizeof(T), hipMemcpyDeviceToDevice, s));
-                NDL_HIP(hipMemcpyAsync(vzo.p, vz.p, N * sizeof(T), hipMemcpyDeviceToDevice, s));
+                NDL_TRY(restart_jacobi());  // fall back and restart the inner directions
                 continue;
             }
-            (void)pq;
-            rr = hs[3];
+            const double rr = hs[3];
             if (std::sqrt(rr) <= want || !std::isfinite(rr)) break;
             // stagnation of the learned directions (no 0.1% drop of the residual
             // in 200 iterations; CG residuals may plateau for a while): fall
             // back to Jacobi
             if (rr < 0.999 * best) { best = rr; since_best = 0; }
             else if (++since_best > 200 && !jac) {
-                jac = true;
-                NDL_TRY(precond((const T*)vr.p, (T*)vz.p, true));
-                NDL_TRY(dots((const T*)vr.p, (const T*)vz.p, nullptr, &rz, &dummy));
-                NDL_HIP(hipMemcpyAsync(vp.p, vz.p, N * sizeof(T), hipMemcpyDeviceToDevice, s));
-                NDL_HIP(hipMemcpyAsync(vzo.p, vz.p, N * sizeof(T), hipMemcpyDeviceToDevice, s));
+                NDL_TRY(restart_jacobi());
                 continue;
             }
             NDL_TRY(precond((const T*)vr.p, (T*)vz.p, jac));
-            double rzn = 0.0, rzo = 0.0;
-            NDL_TRY(dots((const T*)vr.p, (const T*)vz.p, (const T*)vzo.p, &rzn, &rzo));
-            if (!(rzn > 0.0) || !std::isfinite(rzn)) {
-                jac = true;
-                NDL_TRY(precond((const T*)vr.p, (T*)vz.p, true));
-                NDL_TRY(dots((const T*)vr.p, (const T*)vz.p, (const T*)vzo.p, &rzn, &rzo));
-            }
-            double beta = (rzn - rzo) / rz;
-            if (!(beta >= 0.0)) beta = 0.0;
-            rz = rzn;
-            k_dir2<T><<<grid_for(N), 256, 0, s>>>(N, beta, (const T*)vz.p, (T*)vp.p, (T*)vzo.p);
+            NDL_TRY(dots((const T*)vr.p, (const T*)vz.p, (const T*)vzo.p, 0));
+            k_dir2<T><<<grid_for(N), 256, 0, s>>>(N, (const double*)scal.p, (const T*)vz.p, (T*)vp.p, (T*)vzo.p);
             NDL_HIP(hipGetLastError());
         }
         // x += ||r|| d

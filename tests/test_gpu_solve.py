@@ -214,6 +214,47 @@ def test_trained_preconditioner_gains_over_jacobi(n):
         assert np.linalg.norm(w["b"] - Ax) / np.linalg.norm(w["b"]) <= 1.05e-8
 
 
+@pytest.mark.parametrize("lam", [-0.5, -4.0, -50.0])
+def test_learned_pcg_recovers_from_an_indefinite_network(lam, tmp_path):
+    """The shipped network with its output layer scaled by lam < 0 (so that
+    r.z from the network can be negative): flexible PCG still reaches a true
+    FP64 residual of 1e-8, recomputed by the oracle, through its Jacobi
+    fallback (at the first direction or inside the loop, where the skipped
+    step is retaken with the Jacobi z)."""
+    import struct
+    import torch
+    from paper_1905_08375_amd import precond_train as PT
+    say(f"case indefinite network lam={lam}")
+    net = _shipped_net()
+    path = tmp_path / "w.bin"
+    ndl.ndl_net_save(net, str(path))
+    raw = bytearray(path.read_bytes())
+    pos, layers = 16, 13
+    for i in range(layers):
+        cout, kp = struct.unpack_from("<ii", raw, pos)
+        pos += 8
+        if i == layers - 1:
+            w = np.frombuffer(bytes(raw[pos:pos + 4 * cout * kp]), dtype=np.float32) * np.float32(lam)
+            raw[pos:pos + 4 * cout * kp] = w.astype(np.float32).tobytes()
+        pos += 4 * cout * kp + 4 * cout
+    assert pos == len(raw)
+    path.write_bytes(bytes(raw))
+    ndl.ndl_net_load(net, str(path))
+    n = 32
+    plan, b, feat, w = PT.problem_3d(n, 5)
+    x = torch.zeros_like(b)
+    rc, reps = ndl.ndl_cg_solve([plan], [b], [x], rtol=1e-8, precond=1, net=net)
+    say("  rc", rc, "iters", reps[0].iters, "fell_back", reps[0].fell_back, "res", reps[0].rel_res_fp64)
+    assert rc == ndl.NDL_OK and reps[0].converged
+    if lam <= -50.0:
+        assert reps[0].fell_back == 1
+    P = O.Problem(dim=3, n=n, R=4, form="div", kernel="frac")
+    d64 = w["delta"].astype(np.float32).astype(np.float64)
+    c64 = w["coef"].astype(np.float32).astype(np.float64)
+    Ax = -O.apply(P, d64, c64, F.pad(x.cpu().numpy(), 4))
+    assert np.linalg.norm(w["b"] - Ax) / np.linalg.norm(w["b"]) <= 1.05e-8
+
+
 def test_operator_cache_survives_plan_reuse():
     """The cached operator and Jacobi diagonal of the linear preconditioner
     belong to one plan: plans of other sizes created and destroyed in between
