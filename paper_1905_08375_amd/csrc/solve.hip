@@ -38,6 +38,7 @@ struct Inst {
     const void* coef;
     double n2;               // n^2
     int norm;                // normalisation mode
+    int wtab;                // the batch's kmax < kW2K: the shell-weight table follows Tinv
     double expo, m2, contc, hd;
 };
 
@@ -83,6 +84,11 @@ __device__ __forceinline__ double block_sum(double v, double* red)
 //   a = (delta_i + delta_j) (n/2),  k_ij = ceil(a*a) - 1  (exactly the rule of case (b)),
 //   w = (c'_i + c'_j) |z|^e M / T_e[k_ij],  c' = c n^2 / 2.
 constexpr int kMaxOffs = 512;  // ball offsets staged per item (|z|^2 <= kmax)
+// Shell-weight table of small balls (kmax < kW2K), stored after the
+// normalisation table at kW2Off: W[s][k] = |z|^e M / T_e[k] for the shell
+// |z|^2 = s when s <= k, else 0.  One lookup at (|z|^2, k_ij) gives the ball
+// test and both factors of the pair weight.
+constexpr int kW2K = 16, kW2Off = 256;
 
 template <typename T, bool DIAG, bool DISC>
 __global__ __launch_bounds__(256) void k_div_items(const Inst* __restrict__ insts, const int2* __restrict__ items,
@@ -246,7 +252,9 @@ __global__ __launch_bounds__(256) void k_div_items(const Inst* __restrict__ inst
 // FP64 value from it, so that the larger haloed tile keeps two waves per
 // SIMD.  c n^2/2 and u are staged in the element type.  Per pair:
 //   t = a^2 in FP64 with a as above; the pair is in the ball iff |z|^2 < t,
-//   i.e. |z|^2 <= ceil(t) - 1 = k_ij;  w = (c'_i + c'_j) |z|^e M / T_e[k_ij].
+//   i.e. |z|^2 <= ceil(t) - 1 = k_ij;  w = (c'_i + c'_j) |z|^e M / T_e[k_ij]
+//   (for small balls, kmax < kW2K, one lookup of the shell-weight table at
+//   (|z|^2, k_ij) gives |z|^e M / T_e[k_ij], or 0 outside the ball).
 // The membership test is skipped for offsets inside every pair's ball of the
 // tile (|z|^2 < (2 min m)^2) and the loop ends past the largest
 // (|z|^2 >= (2 max m)^2); a partner outside Omega takes (delta_i, c_i), which
@@ -293,6 +301,7 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
     __shared__ T tinv_s[256];
     __shared__ int s_q[kMaxOffs];
     __shared__ T s_fw[kMaxOffs];  // profile weight |z|^expo of the offsets, in the vectors' type
+    __shared__ T s_w2[kW2K * kW2K];  // shell-weight table (small balls)
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -349,6 +358,8 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
         const double ch = 0.5 * I.n2;
         __syncthreads();  // the previous item's readers are done
         for (int k = threadIdx.x; k <= I.kmax && k < 256; k += blockDim.x) tinv_s[k] = (T)Tinv[k];
+        if (I.wtab)
+            for (int e = threadIdx.x; e < kW2K * kW2K; e += blockDim.x) s_w2[e] = (T)Tinv[kW2Off + e];
         const int nq = I.nq < kMaxOffs ? I.nq : kMaxOffs;
         for (int q = threadIdx.x; q < nq; q += blockDim.x) {
             s_q[q] = full[q].w;
@@ -468,9 +479,10 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
         const T* tcb = tcc + base;
         const T* tub = tu + base;
         // one range of offsets; the table entries are uniform (scalar loads)
-        auto run = [&](int pb, int pe, auto edge_c, auto mask_c) {
+        auto run = [&](int pb, int pe, auto edge_c, auto mask_c, auto tab_c) {
             constexpr bool EDGE = decltype(edge_c)::value;
             constexpr bool MASK = decltype(mask_c)::value;
+            constexpr bool TAB = decltype(tab_c)::value;
             if (pb >= pe) return;
             // the table entries of the next offset are loaded one iteration
             // ahead (the table carries one sentinel entry past its end)
@@ -478,7 +490,10 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
             for (int q = pb; q < pe; ++q) {
                 const int off = (DIM == 3 ? o.x * PLANE : 0) + o.y * PITCH + o.z;
                 const int qi = o.w;  // |z|^2 >= 1: the table holds no zero offset
-                const T fq = s_fw[q];
+                const T fq = TAB ? T(0) : s_fw[q];
+                // the row of the shell, shifted by one so that it is indexed
+                // by ceil(t) = k_ij + 1 (one address add per pair)
+                const T* wrow = s_w2 + (TAB ? qi * kW2K - 1 : 0);
                 o = full[q + 1];
 #pragma unroll
                 for (int j = 0; j < PY; ++j) {
@@ -493,11 +508,17 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
                     }
                     const double a = SC ? mi[j] + mj : fma(mj, nh, mh[j]);
                     const double t = a * a;
-                    int kij = (int)ceil(t) - 1;
+                    const int ct = (int)ceil(t);
+                    const int kij = ct - 1;
                     // |z|^2 < t  <=>  |z|^2 <= ceil(t) - 1 = k_ij for an integer |z|^2
-                    const bool inside = qi <= kij;
-                    T w = (cci[j] + ccj) * tinv_s[kij] * fq;
-                    if (MASK) w = inside ? w : T(0);
+                    T w;
+                    if (TAB) {
+                        w = (cci[j] + ccj) * wrow[ct];  // zero outside the ball
+                    } else {
+                        const bool inside = qi <= kij;
+                        w = (cci[j] + ccj) * tinv_s[kij] * fq;
+                        if (MASK) w = inside ? w : T(0);
+                    }
                     if (DIAG) {
                         dsum[j] += (double)w;
                     } else {
@@ -512,12 +533,20 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
         };
         using yes = std::integral_constant<bool, true>;
         using no = std::integral_constant<bool, false>;
-        if (edge) {
-            run(0, p_in, yes{}, no{});
-            run(p_in, p_end, yes{}, yes{});
+        if (I.wtab) {
+            if (edge) {
+                run(0, p_in, yes{}, no{}, yes{});
+                run(p_in, p_end, yes{}, yes{}, yes{});
+            } else {
+                run(0, p_in, no{}, no{}, yes{});
+                run(p_in, p_end, no{}, yes{}, yes{});
+            }
+        } else if (edge) {
+            run(0, p_in, yes{}, no{}, no{});
+            run(p_in, p_end, yes{}, yes{}, no{});
         } else {
-            run(0, p_in, no{}, no{});
-            run(p_in, p_end, no{}, yes{});
+            run(0, p_in, no{}, no{}, no{});
+            run(p_in, p_end, no{}, yes{}, no{});
         }
         T* qv = qvec + I.off;
 #pragma unroll
@@ -891,6 +920,7 @@ static int build_batch(const ndl_plan* plans, int nprob, Batch& B, bool f64_fiel
         B.dim = p.dim;
     }
     B.total = off;
+    for (auto& I : B.insts) I.wtab = B.kmax < kW2K ? 1 : 0;
     B.owner.assign(off / 1024, 0);
     for (int i = 0; i < nprob; ++i)
         for (int64_t c = B.insts[i].off / 1024; c < (B.insts[i].off + B.insts[i].N + 1023) / 1024; ++c) B.owner[c] = i;
@@ -1097,6 +1127,37 @@ static int launch_div_items(const Batch& B, const Inst* d_insts, const int2* d_i
     return NDL_OK;
 }
 
+// The batch's shared ball tables: the offsets sorted by |z|^2 (plus one
+// sentinel entry, as the 2D kernel reads one entry ahead), their profile
+// weights |z|^e, and the discrete normalisation M / T_e[k] for k <= kmax
+// (T_e[k] = sum over the offsets with |z|^2 <= k of |z|^(e+2)), followed by
+// the shell-weight table when kmax < kW2K.
+static void ball_tables(const Batch& B, double expo, double m2, std::vector<int4>& fb, std::vector<double>& fwv,
+                        std::vector<double>& Tinv)
+{
+    const std::vector<Off> full = ball_offsets(B.dim, B.kmax, false);
+    fb.clear();
+    fwv.clear();
+    for (auto& o : full) {
+        fb.push_back(box_offset(B.dim, o));
+        fwv.push_back(std::pow(std::sqrt((double)o.q), expo));
+    }
+    fb.push_back(make_int4(0, 0, 0, 1 << 30));
+    fwv.push_back(0.0);
+    std::vector<double> shell(B.kmax + 1, 0.0);
+    Tinv.assign(std::max<size_t>((size_t)B.kmax + 1, kW2Off + kW2K * kW2K), 0.0);
+    for (auto& o : full) shell[o.q] += std::pow(std::sqrt((double)o.q), expo + 2.0);
+    double acc = 0.0;
+    for (int64_t k = 0; k <= B.kmax; ++k) {
+        acc += shell[k];
+        Tinv[k] = acc > 0 ? m2 / acc : 0.0;
+    }
+    if (B.kmax < kW2K)
+        for (int sh = 1; sh <= B.kmax; ++sh)
+            for (int k = sh; k <= B.kmax; ++k)
+                Tinv[kW2Off + sh * kW2K + k] = std::pow(std::sqrt((double)sh), expo) * Tinv[k];
+}
+
 template <typename T>
 static int tune_div_batch(Batch& B, const Inst* di, const int2* dit, const T* p, T* q, const int4* full,
                           const double* fw, int nfull, const double* Tinv, hipStream_t s);
@@ -1122,22 +1183,9 @@ static int cg_solve_t(const ndl_plan* plans, int nprob, const double* const* b, 
     NDL_HIP(hipMemcpy(d_owner.p, B.owner.data(), B.owner.size() * sizeof(int), hipMemcpyHostToDevice));
     // full ball table sorted by |z|^2, weights |z|^e, and M / T_e[k]
     const Plan& p0 = *reinterpret_cast<const Plan*>(plans[0]);
-    std::vector<Off> full = ball_offsets(B.dim, B.kmax, false);
     std::vector<int4> fb;
-    std::vector<double> fwv;
-    for (auto& o : full) {
-        fb.push_back(box_offset(B.dim, o));
-        fwv.push_back(std::pow(std::sqrt((double)o.q), p0.expo));
-    }
-    fb.push_back(make_int4(0, 0, 0, 1 << 30));  // sentinel: the 2D kernel reads one entry ahead
-    fwv.push_back(0.0);
-    std::vector<double> shell(B.kmax + 1, 0.0), Tinv(B.kmax + 1, 0.0);
-    for (auto& o : full) shell[o.q] += std::pow(std::sqrt((double)o.q), p0.expo + 2.0);
-    double acc = 0.0;
-    for (int64_t k = 0; k <= B.kmax; ++k) {
-        acc += shell[k];
-        Tinv[k] = acc > 0 ? p0.m2 / acc : 0.0;
-    }
+    std::vector<double> fwv, Tinv;
+    ball_tables(B, p0.expo, p0.m2, fb, fwv, Tinv);
     NDL_TRY(alloc<int4>(d_full, fb.size()));
     NDL_TRY(alloc<double>(d_fw, fwv.size()));
     NDL_TRY(alloc<double>(d_Tinv, Tinv.size()));
@@ -1389,22 +1437,9 @@ static int op_tables(const ndl_plan* plans, int nprob, OpCache& oc)
     NDL_TRY(alloc<int2>(oc.items, oc.nitems));
     NDL_HIP(hipMemcpy(oc.insts.p, oc.B.insts.data(), nprob * sizeof(Inst), hipMemcpyHostToDevice));
     NDL_HIP(hipMemcpy(oc.items.p, oc.B.items.data(), oc.nitems * sizeof(int2), hipMemcpyHostToDevice));
-    std::vector<Off> full = ball_offsets(oc.B.dim, oc.B.kmax, false);
     std::vector<int4> fb;
-    std::vector<double> fwv;
-    for (auto& o : full) {
-        fb.push_back(box_offset(oc.B.dim, o));
-        fwv.push_back(std::pow(std::sqrt((double)o.q), P.expo));
-    }
-    fb.push_back(make_int4(0, 0, 0, 1 << 30));  // sentinel: the 2D kernel reads one entry ahead
-    fwv.push_back(0.0);
-    std::vector<double> shell(oc.B.kmax + 1, 0.0), Tinv(oc.B.kmax + 1, 0.0);
-    for (auto& o : full) shell[o.q] += std::pow(std::sqrt((double)o.q), P.expo + 2.0);
-    double acc = 0.0;
-    for (int64_t k = 0; k <= oc.B.kmax; ++k) {
-        acc += shell[k];
-        Tinv[k] = acc > 0 ? P.m2 / acc : 0.0;
-    }
+    std::vector<double> fwv, Tinv;
+    ball_tables(oc.B, P.expo, P.m2, fb, fwv, Tinv);
     NDL_TRY(alloc<int4>(oc.full, fb.size()));
     NDL_TRY(alloc<double>(oc.fw, fwv.size()));
     NDL_TRY(alloc<double>(oc.Tinv, Tinv.size()));
@@ -1695,22 +1730,9 @@ static int pcg_learned_t(const ndl_plan plan, const double* b, double* x, const 
     NDL_TRY(alloc<int2>(d_items, nitems));
     NDL_HIP(hipMemcpy(d_insts.p, B.insts.data(), sizeof(Inst), hipMemcpyHostToDevice));
     NDL_HIP(hipMemcpy(d_items.p, B.items.data(), nitems * sizeof(int2), hipMemcpyHostToDevice));
-    std::vector<Off> full = ball_offsets(B.dim, B.kmax, false);
     std::vector<int4> fb;
-    std::vector<double> fwv;
-    for (auto& o : full) {
-        fb.push_back(box_offset(B.dim, o));
-        fwv.push_back(std::pow(std::sqrt((double)o.q), P.expo));
-    }
-    fb.push_back(make_int4(0, 0, 0, 1 << 30));  // sentinel: the 2D kernel reads one entry ahead
-    fwv.push_back(0.0);
-    std::vector<double> shell(B.kmax + 1, 0.0), Tinv(B.kmax + 1, 0.0);
-    for (auto& o : full) shell[o.q] += std::pow(std::sqrt((double)o.q), P.expo + 2.0);
-    double acc = 0.0;
-    for (int64_t k = 0; k <= B.kmax; ++k) {
-        acc += shell[k];
-        Tinv[k] = acc > 0 ? P.m2 / acc : 0.0;
-    }
+    std::vector<double> fwv, Tinv;
+    ball_tables(B, P.expo, P.m2, fb, fwv, Tinv);
     NDL_TRY(alloc<int4>(d_full, fb.size()));
     NDL_TRY(alloc<double>(d_fw, fwv.size()));
     NDL_TRY(alloc<double>(d_Tinv, Tinv.size()));
