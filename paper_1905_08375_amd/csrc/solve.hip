@@ -38,7 +38,7 @@ struct Inst {
     const void* coef;
     double n2;               // n^2
     int norm;                // normalisation mode
-    int wtab;                // the batch's kmax < kW2K: the shell-weight table follows Tinv
+    int wtab;                // the batch's kmax < w2_width(dim, J): the shell-weight table follows Tinv
     double expo, m2, contc, hd;
 };
 
@@ -84,11 +84,13 @@ __device__ __forceinline__ double block_sum(double v, double* red)
 //   a = (delta_i + delta_j) (n/2),  k_ij = ceil(a*a) - 1  (exactly the rule of case (b)),
 //   w = (c'_i + c'_j) |z|^e M / T_e[k_ij],  c' = c n^2 / 2.
 constexpr int kMaxOffs = 512;  // ball offsets staged per item (|z|^2 <= kmax)
-// Shell-weight table of small balls (kmax < kW2K), stored after the
-// normalisation table at kW2Off: W[s][k] = |z|^e M / T_e[k] for the shell
-// |z|^2 = s when s <= k, else 0.  One lookup at (|z|^2, k_ij) gives the ball
-// test and both factors of the pair weight.
-constexpr int kW2K = 16, kW2Off = 256;
+// Shell-weight table of the batch's balls, stored after the normalisation
+// table at kW2Off with rows of w2_width(dim, J) entries (J the batch's reach,
+// so k_ij <= J^2 - 1 stays within a row): W[s][k] = |z|^e M / T_e[k] for the
+// shell |z|^2 = s when s <= k, else 0.  One lookup at (|z|^2, k_ij) gives the
+// ball test and both factors of the pair weight.
+constexpr int kW2Off = 256;
+__host__ __device__ constexpr int w2_width(int dim, int J) { return dim == 3 ? 16 : J * J; }
 
 template <typename T, bool DIAG, bool DISC>
 __global__ __launch_bounds__(256) void k_div_items(const Inst* __restrict__ insts, const int2* __restrict__ items,
@@ -253,7 +255,7 @@ __global__ __launch_bounds__(256) void k_div_items(const Inst* __restrict__ inst
 // SIMD.  c n^2/2 and u are staged in the element type.  Per pair:
 //   t = a^2 in FP64 with a as above; the pair is in the ball iff |z|^2 < t,
 //   i.e. |z|^2 <= ceil(t) - 1 = k_ij;  w = (c'_i + c'_j) |z|^e M / T_e[k_ij]
-//   (for small balls, kmax < kW2K, one lookup of the shell-weight table at
+//   (where the kernel holds the shell-weight table, one lookup of it at
 //   (|z|^2, k_ij) gives |z|^e M / T_e[k_ij], or 0 outside the ball).
 // The membership test is skipped for offsets inside every pair's ball of the
 // tile (|z|^2 < (2 min m)^2) and the loop ends past the largest
@@ -301,7 +303,11 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
     __shared__ T tinv_s[256];
     __shared__ int s_q[kMaxOffs];
     __shared__ T s_fw[kMaxOffs];  // profile weight |z|^expo of the offsets, in the vectors' type
-    __shared__ T s_w2[kW2K * kW2K];  // shell-weight table (small balls)
+    // shell-weight table: 3D, and 2D FP32 vectors up to reach 7 (a larger
+    // table would cost the 2D tile a block per unit)
+    constexpr int KW = w2_width(DIM, JT);
+    constexpr bool TABOK = DIM == 3 || (sizeof(T) == 4 && JT <= 7);
+    __shared__ T s_w2[TABOK ? KW * KW : 1];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -358,8 +364,9 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
         const double ch = 0.5 * I.n2;
         __syncthreads();  // the previous item's readers are done
         for (int k = threadIdx.x; k <= I.kmax && k < 256; k += blockDim.x) tinv_s[k] = (T)Tinv[k];
-        if (I.wtab)
-            for (int e = threadIdx.x; e < kW2K * kW2K; e += blockDim.x) s_w2[e] = (T)Tinv[kW2Off + e];
+        const bool tab = TABOK && I.wtab;
+        if (tab)
+            for (int e = threadIdx.x; e < KW * KW; e += blockDim.x) s_w2[e] = (T)Tinv[kW2Off + e];
         const int nq = I.nq < kMaxOffs ? I.nq : kMaxOffs;
         for (int q = threadIdx.x; q < nq; q += blockDim.x) {
             s_q[q] = full[q].w;
@@ -493,7 +500,7 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
                 const T fq = TAB ? T(0) : s_fw[q];
                 // the row of the shell, shifted by one so that it is indexed
                 // by ceil(t) = k_ij + 1 (one address add per pair)
-                const T* wrow = s_w2 + (TAB ? qi * kW2K - 1 : 0);
+                const T* wrow = s_w2 + (TAB ? qi * KW - 1 : 0);
                 o = full[q + 1];
 #pragma unroll
                 for (int j = 0; j < PY; ++j) {
@@ -533,7 +540,7 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
         };
         using yes = std::integral_constant<bool, true>;
         using no = std::integral_constant<bool, false>;
-        if (I.wtab) {
+        if (tab) {
             if (edge) {
                 run(0, p_in, yes{}, no{}, yes{});
                 run(p_in, p_end, yes{}, yes{}, yes{});
@@ -920,7 +927,7 @@ static int build_batch(const ndl_plan* plans, int nprob, Batch& B, bool f64_fiel
         B.dim = p.dim;
     }
     B.total = off;
-    for (auto& I : B.insts) I.wtab = B.kmax < kW2K ? 1 : 0;
+    for (auto& I : B.insts) I.wtab = B.kmax < w2_width(B.dim, B.Jmax) ? 1 : 0;
     B.owner.assign(off / 1024, 0);
     for (int i = 0; i < nprob; ++i)
         for (int64_t c = B.insts[i].off / 1024; c < (B.insts[i].off + B.insts[i].N + 1023) / 1024; ++c) B.owner[c] = i;
@@ -1131,7 +1138,7 @@ static int launch_div_items(const Batch& B, const Inst* d_insts, const int2* d_i
 // sentinel entry, as the 2D kernel reads one entry ahead), their profile
 // weights |z|^e, and the discrete normalisation M / T_e[k] for k <= kmax
 // (T_e[k] = sum over the offsets with |z|^2 <= k of |z|^(e+2)), followed by
-// the shell-weight table when kmax < kW2K.
+// the shell-weight table when kmax < w2_width(dim, J).
 static void ball_tables(const Batch& B, double expo, double m2, std::vector<int4>& fb, std::vector<double>& fwv,
                         std::vector<double>& Tinv)
 {
@@ -1145,17 +1152,18 @@ static void ball_tables(const Batch& B, double expo, double m2, std::vector<int4
     fb.push_back(make_int4(0, 0, 0, 1 << 30));
     fwv.push_back(0.0);
     std::vector<double> shell(B.kmax + 1, 0.0);
-    Tinv.assign(std::max<size_t>((size_t)B.kmax + 1, kW2Off + kW2K * kW2K), 0.0);
+    const int KW = w2_width(B.dim, B.Jmax);
+    Tinv.assign(std::max<size_t>((size_t)B.kmax + 1, (size_t)(kW2Off + KW * KW)), 0.0);
     for (auto& o : full) shell[o.q] += std::pow(std::sqrt((double)o.q), expo + 2.0);
     double acc = 0.0;
     for (int64_t k = 0; k <= B.kmax; ++k) {
         acc += shell[k];
         Tinv[k] = acc > 0 ? m2 / acc : 0.0;
     }
-    if (B.kmax < kW2K)
+    if (B.kmax < KW)
         for (int sh = 1; sh <= B.kmax; ++sh)
             for (int k = sh; k <= B.kmax; ++k)
-                Tinv[kW2Off + sh * kW2K + k] = std::pow(std::sqrt((double)sh), expo) * Tinv[k];
+                Tinv[kW2Off + sh * KW + k] = std::pow(std::sqrt((double)sh), expo) * Tinv[k];
 }
 
 template <typename T>
