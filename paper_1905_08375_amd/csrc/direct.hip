@@ -78,7 +78,8 @@ __global__ __launch_bounds__(256) void k_cutoffs(const T* __restrict__ delta, in
 
 // histogram of the integer cutoffs (for the average ball size): per block in
 // LDS when the nbins = k_max + 1 bins fit (kKhistLds), then one global add per
-// non-empty bin; else straight into the global bins
+// non-empty bin; else straight into the global bins, one add per wave where
+// its lanes agree
 constexpr int kKhistLds = 4096;
 __global__ __launch_bounds__(256) void k_khist(const int32_t* __restrict__ kk, int64_t N, int nbins,
                                                unsigned long long* __restrict__ hist)
@@ -90,8 +91,21 @@ __global__ __launch_bounds__(256) void k_khist(const int32_t* __restrict__ kk, i
         __syncthreads();
     }
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
-        if (in_lds) atomicAdd(&sh_hist[kk[i]], 1u);
-        else atomicAdd(&hist[kk[i]], 1ull);
+        const int b = kk[i];
+        if (in_lds) {
+            atomicAdd(&sh_hist[b], 1u);
+        } else {
+            // a wave whose active lanes share one bin (smooth or constant
+            // horizons) adds its count once instead of contending 64 times
+            const unsigned long long act = __ballot(1);
+            const int lead = __ffsll((unsigned long long)act) - 1;
+            const int bl = __shfl(b, lead, 64);
+            if (__all(b == bl)) {
+                if ((int)(threadIdx.x & 63) == lead) atomicAdd(&hist[b], (unsigned long long)__popcll(act));
+            } else {
+                atomicAdd(&hist[b], 1ull);
+            }
+        }
     }
     if (in_lds) {
         __syncthreads();

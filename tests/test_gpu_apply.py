@@ -452,3 +452,33 @@ def test_graph_replay_matches_eager(fast):
         assert torch.isfinite(scratch)
     ref = oracle_apply(2, n, R, delta, c, u, prec)
     assert rel_l2(out.cpu().numpy(), ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("m", [4.0, 70.0])
+def test_pairs_per_point_is_the_average_ball(m):
+    """The plan's pairs_per_point is the mean over nodes of the lattice-ball
+    size #{z != 0 : |z|^2 <= k_i}, k_i = ceil((delta_i n)^2) - 1 from the FP32
+    horizon in FP64; m = 4 bins the cutoffs in LDS, m = 70 (k up to 7655)
+    in the global bins."""
+    import torch
+    say(f"case pairs_per_point m={m}")
+    n = 256
+    X = F.mesh(n, 2)
+    mm = m * (1.0 + 0.25 * np.sin(2 * np.pi * X[0]) * np.cos(2 * np.pi * X[1]))
+    delta = (mm / n).astype(np.float32)
+    R = int(np.ceil(mm.max())) + 1
+    d_d = torch.from_numpy(delta).cuda()
+    d_c = torch.ones((n, n), dtype=torch.float32, device="cuda")
+    plan = ndl.ndl_plan_create(ndl.make_problem(2, n, R, d_d, d_c, prec=ndl.NDL_F32K), keep=(d_d, d_c))
+    got = plan.info().pairs_per_point
+    plan.close()
+    k = (np.ceil((delta.astype(np.float64) * n) ** 2) - 1).astype(np.int64)
+    kmax = int(k.max())
+    J = int(np.sqrt(kmax)) + 1
+    a = np.arange(-J, J + 1)
+    q = (a[:, None] ** 2 + a[None, :] ** 2).ravel()
+    q = q[(q > 0) & (q <= kmax)]
+    ball = np.cumsum(np.bincount(q, minlength=kmax + 1))
+    want = ball[k].mean()
+    say("  pairs_per_point", got, "expected", want, "kmax", kmax)
+    assert abs(got - want) <= 1e-12 * want
