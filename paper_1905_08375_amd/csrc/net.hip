@@ -30,8 +30,17 @@ namespace ndl {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint16_t bf16_t;  // storage type
+
+// a layer's BF16 output leaves through non-temporal stores (the launch does
+// not read it again)
+__device__ __forceinline__ void store_bf16x4_nt(bf16_t* p, bf16x4 o)
+{
+    __builtin_nontemporal_store(__builtin_bit_cast(u32x2, o), reinterpret_cast<u32x2*>(p));
+}
 
 __device__ __forceinline__ float bf2f(bf16_t v)
 {
@@ -306,7 +315,7 @@ __global__ __launch_bounds__(64 * NWV) void k_conv_fwd(const bf16_t* __restrict_
                         bf16x4 o;
 #pragma unroll
                         for (int e = 0; e < 4; ++e) o[e] = (__bf16)v[e];
-                        *reinterpret_cast<bf16x4*>(reinterpret_cast<bf16_t*>(out) + vo * COUT + c * 16 + 4 * kb) = o;
+                        store_bf16x4_nt(reinterpret_cast<bf16_t*>(out) + vo * COUT + c * 16 + 4 * kb, o);
                     }
                 }
             }
@@ -451,7 +460,7 @@ __global__ __launch_bounds__(64 * NWV) void k_conv_in1(const float* __restrict__
                     if (ACT == 1) v = v > 0.f ? v : 0.f;
                     o[e] = (__bf16)v;
                 }
-                *reinterpret_cast<bf16x4*>(out + (vrow + t * 16 + row) * COUT + 4 * kb) = o;
+                store_bf16x4_nt(out + (vrow + t * 16 + row) * COUT + 4 * kb, o);
             }
         }
         if (z + 1 < zend) {
