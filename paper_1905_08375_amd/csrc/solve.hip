@@ -285,10 +285,13 @@ struct DivShape {
     static constexpr int THREADS = 64 * TZ * TY / PY;
 };
 
+// offs: per ball offset, sorted by |z|^2, {the partner's offset in the staged
+// tile, |z|^2, the start of the shell's weight row less one, 0}, then a
+// sentinel (built with the batch's tables on the host).
 template <typename T, typename D, bool DIAG, int JT, int DIM, int PYV>
 __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items(
     const Inst* __restrict__ insts, const int2* __restrict__ items, int nitems, const T* __restrict__ pvec,
-    T* __restrict__ qvec, const int4* __restrict__ full, const double* __restrict__ fw, const double* __restrict__ Tinv,
+    T* __restrict__ qvec, const int4* __restrict__ offs, const double* __restrict__ fw, const double* __restrict__ Tinv,
     const Scal* __restrict__ sc, double* __restrict__ part)
 {
     using SH = DivShape<T, DIM, PYV>;
@@ -369,7 +372,7 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
             for (int e = threadIdx.x; e < KW * KW; e += blockDim.x) s_w2[e] = (T)Tinv[kW2Off + e];
         const int nq = I.nq < kMaxOffs ? I.nq : kMaxOffs;
         for (int q = threadIdx.x; q < nq; q += blockDim.x) {
-            s_q[q] = full[q].w;
+            s_q[q] = offs[q].y;
             s_fw[q] = (T)fw[q];
         }
         const int z0 = org[0] + sub * TZ, y0 = org[1], x0 = org[2];
@@ -493,15 +496,15 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
             if (pb >= pe) return;
             // the table entries of the next offset are loaded one iteration
             // ahead (the table carries one sentinel entry past its end)
-            int4 o = full[pb];
+            int4 o = offs[pb];
             for (int q = pb; q < pe; ++q) {
-                const int off = (DIM == 3 ? o.x * PLANE : 0) + o.y * PITCH + o.z;
-                const int qi = o.w;  // |z|^2 >= 1: the table holds no zero offset
+                const int off = o.x;  // the partner's offset in the staged tile
+                const int qi = o.y;   // |z|^2 >= 1: the table holds no zero offset
                 const T fq = TAB ? T(0) : s_fw[q];
                 // the row of the shell, shifted by one so that it is indexed
                 // by ceil(t) = k_ij + 1 (one address add per pair)
-                const T* wrow = s_w2 + (TAB ? qi * KW - 1 : 0);
-                o = full[q + 1];
+                const T* wrow = s_w2 + (TAB ? o.z : 0);
+                o = offs[q + 1];
 #pragma unroll
                 for (int j = 0; j < PY; ++j) {
                     const int jo = j * PITCH + off;
@@ -1086,8 +1089,8 @@ static int launch_div_items(const Batch& B, const Inst* d_insts, const int2* d_i
         const int key = B.dim * 16 + B.Jmax;
 #define NDL_DIV2_CASE(DD, JJ, DT)                                                                                 \
     case DD * 16 + JJ:                                                                                            \
-        launch_div2_v<T, DT, JJ, DD>(v, diag, (unsigned)nitems, lds, s, d_insts, d_items, p, q, full, fw, Tinv,   \
-                                     sc, part);                                                                   \
+        launch_div2_v<T, DT, JJ, DD>(v, diag, (unsigned)nitems, lds, s, d_insts, d_items, p, q, full + nfull, fw, \
+                                     Tinv, sc, part);                                                             \
         break;
         if (f32data && sizeof(T) == 8) {
             if constexpr (sizeof(T) == 8) {
@@ -1139,8 +1142,8 @@ static int launch_div_items(const Batch& B, const Inst* d_insts, const int2* d_i
 // weights |z|^e, and the discrete normalisation M / T_e[k] for k <= kmax
 // (T_e[k] = sum over the offsets with |z|^2 <= k of |z|^(e+2)), followed by
 // the shell-weight table when kmax < w2_width(dim, J).
-static void ball_tables(const Batch& B, double expo, double m2, std::vector<int4>& fb, std::vector<double>& fwv,
-                        std::vector<double>& Tinv)
+static int ball_tables(const Batch& B, double expo, double m2, std::vector<int4>& fb, std::vector<double>& fwv,
+                       std::vector<double>& Tinv)
 {
     const std::vector<Off> full = ball_offsets(B.dim, B.kmax, false);
     fb.clear();
@@ -1164,6 +1167,20 @@ static void ball_tables(const Batch& B, double expo, double m2, std::vector<int4
         for (int sh = 1; sh <= B.kmax; ++sh)
             for (int k = sh; k <= B.kmax; ++k)
                 Tinv[kW2Off + sh * KW + k] = std::pow(std::sqrt((double)sh), expo) * Tinv[k];
+    // after them, the batched kernel's form of the same offsets: the offset
+    // of the partner in its staged tile (rows of 64 + 2J, planes of TY + 2J
+    // rows; TY = 4 in 3D, 16 in 2D), |z|^2 and the start of the shell's
+    // weight row less one (the kernel indexes it by ceil(t) = k_ij + 1), plus
+    // a sentinel: no per-offset arithmetic in its pair loop
+    const int ngen = (int)fb.size();
+    const int J = B.Jmax, pitch = 64 + 2 * J, plane = ((B.dim == 3 ? 4 : 16) + 2 * J) * pitch;
+    for (auto& o : full) {
+        const int4 bo = box_offset(B.dim, o);
+        const int off = (B.dim == 3 ? bo.x * plane : 0) + bo.y * pitch + bo.z;
+        fb.push_back(make_int4(off, (int)o.q, (int)o.q * KW - 1, 0));
+    }
+    fb.push_back(make_int4(0, 1 << 30, 0, 0));
+    return ngen;
 }
 
 template <typename T>
@@ -1193,7 +1210,7 @@ static int cg_solve_t(const ndl_plan* plans, int nprob, const double* const* b, 
     const Plan& p0 = *reinterpret_cast<const Plan*>(plans[0]);
     std::vector<int4> fb;
     std::vector<double> fwv, Tinv;
-    ball_tables(B, p0.expo, p0.m2, fb, fwv, Tinv);
+    const int nfull = ball_tables(B, p0.expo, p0.m2, fb, fwv, Tinv);
     NDL_TRY(alloc<int4>(d_full, fb.size()));
     NDL_TRY(alloc<double>(d_fw, fwv.size()));
     NDL_TRY(alloc<double>(d_Tinv, Tinv.size()));
@@ -1202,7 +1219,6 @@ static int cg_solve_t(const ndl_plan* plans, int nprob, const double* const* b, 
     NDL_HIP(hipMemcpy(d_Tinv.p, Tinv.data(), Tinv.size() * sizeof(double), hipMemcpyHostToDevice));
     NDL_TRY(alloc<Scal>(d_sc, nprob));
     NDL_HIP(hipMemset(d_sc.p, 0, nprob * sizeof(Scal)));
-    int nfull = (int)fb.size();
 
     // FP64 fields for the outer residual of FP32 plans
     std::vector<DevBuf> f64f(2 * nprob);
@@ -1447,14 +1463,13 @@ static int op_tables(const ndl_plan* plans, int nprob, OpCache& oc)
     NDL_HIP(hipMemcpy(oc.items.p, oc.B.items.data(), oc.nitems * sizeof(int2), hipMemcpyHostToDevice));
     std::vector<int4> fb;
     std::vector<double> fwv, Tinv;
-    ball_tables(oc.B, P.expo, P.m2, fb, fwv, Tinv);
+    oc.nfull = ball_tables(oc.B, P.expo, P.m2, fb, fwv, Tinv);
     NDL_TRY(alloc<int4>(oc.full, fb.size()));
     NDL_TRY(alloc<double>(oc.fw, fwv.size()));
     NDL_TRY(alloc<double>(oc.Tinv, Tinv.size()));
     NDL_HIP(hipMemcpy(oc.full.p, fb.data(), fb.size() * sizeof(int4), hipMemcpyHostToDevice));
     NDL_HIP(hipMemcpy(oc.fw.p, fwv.data(), fwv.size() * sizeof(double), hipMemcpyHostToDevice));
     NDL_HIP(hipMemcpy(oc.Tinv.p, Tinv.data(), Tinv.size() * sizeof(double), hipMemcpyHostToDevice));
-    oc.nfull = (int)fb.size();
     return NDL_OK;
 }
 
@@ -1740,14 +1755,13 @@ static int pcg_learned_t(const ndl_plan plan, const double* b, double* x, const 
     NDL_HIP(hipMemcpy(d_items.p, B.items.data(), nitems * sizeof(int2), hipMemcpyHostToDevice));
     std::vector<int4> fb;
     std::vector<double> fwv, Tinv;
-    ball_tables(B, P.expo, P.m2, fb, fwv, Tinv);
+    const int nfull = ball_tables(B, P.expo, P.m2, fb, fwv, Tinv);
     NDL_TRY(alloc<int4>(d_full, fb.size()));
     NDL_TRY(alloc<double>(d_fw, fwv.size()));
     NDL_TRY(alloc<double>(d_Tinv, Tinv.size()));
     NDL_HIP(hipMemcpy(d_full.p, fb.data(), fb.size() * sizeof(int4), hipMemcpyHostToDevice));
     NDL_HIP(hipMemcpy(d_fw.p, fwv.data(), fwv.size() * sizeof(double), hipMemcpyHostToDevice));
     NDL_HIP(hipMemcpy(d_Tinv.p, Tinv.data(), Tinv.size() * sizeof(double), hipMemcpyHostToDevice));
-    const int nfull = (int)fb.size();
     // FP64 fields for the outer residual
     DevBuf dd64, dc64;
     Inst i64 = B.insts[0];
