@@ -321,6 +321,75 @@ def bench_pd(steps=5, batch=8, n=2048, fast=False):
     return res
 
 
+def bench_sym(n=1024, steps=400, cg_n=256):
+    """The kernel-averaged symmetric form omega_s = (omega_x(y) + omega_y(x))/2
+    on the 1024^2 workload (FP32 with Kahan sums, r^-3 profile): the direct sum
+    and the fast evaluation (hierarchical gather plus its adjoint scatter), ms
+    per apply from graph replays; and Jacobi-CG to 1e-8 in FP64 through the
+    direct apply on the same recipe at 256^2."""
+    import torch
+    from paper_1905_08375_amd import fields as F
+    from paper_1905_08375_amd import ndl
+    R = 6
+    w = F.diffusion_2d(n=n)
+    d = torch.from_numpy(w["delta"].astype(np.float32)).cuda()
+    c = torch.from_numpy(w["coef"].astype(np.float32)).cuda()
+    u = torch.from_numpy(F.pad(w["u"], R).astype(np.float32)).cuda()
+    out = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    res = {"n": n, "profile": "r^-3 (s = 1/2)", "precision": "fp32 storage, fp32 Kahan sums"}
+    for fast in (False, True):
+        plan = ndl.ndl_plan_create(ndl.make_problem(2, n, R, d, c, form=ndl.NDL_SYM, prec=ndl.NDL_F32K),
+                                   want_fast=int(fast), keep=(d, c))
+        fn = (lambda: ndl.ndl_apply_fast(plan, u, out, 1)) if fast else (lambda: ndl.ndl_apply(plan, u, out, 1))
+        secs, _ = timed_graph(fn, steps, 20)
+        res["fast_ms" if fast else "direct_ms"] = secs / steps * 1e3
+        plan.close()
+    w = F.diffusion_2d(n=cg_n)
+    d = torch.from_numpy(w["delta"]).cuda()
+    c = torch.from_numpy(w["coef"]).cuda()
+    b = torch.from_numpy(np.random.default_rng(cg_n).standard_normal((cg_n, cg_n))).cuda()
+    x = torch.zeros_like(b)
+    plan = ndl.ndl_plan_create(ndl.make_problem(2, cg_n, R, d, c, form=ndl.NDL_SYM, prec=ndl.NDL_F64), keep=(d, c))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, reps = ndl.ndl_cg_solve([plan], [b], [x], rtol=1e-8)
+    torch.cuda.synchronize()
+    res["cg_256_fp64"] = {"seconds": time.perf_counter() - t0, "iters": reps[0].iters, "rc": rc,
+                          "rel_res": reps[0].rel_res_fp64}
+    plan.close()
+    return res
+
+
+def bench_pd3d(n=128, steps=20):
+    """3D linear bond-based peridynamics on one 128^3 displacement field (3
+    components; m(x) = 3 + sin sin sin in [2, 4], lognormal c, GRF
+    displacements): the direct sum with the 1/r and the conical (1 - r)/r
+    micromoduli (FP32, Kahan sums), and the hierarchical path with the 1/r
+    profile (FP32 data, FP64 moments); ms per apply."""
+    import torch
+    from paper_1905_08375_amd import fields as F
+    from paper_1905_08375_amd import ndl
+    R = 5
+    w = F.diffusion_3d(n=n)
+    d = torch.from_numpy(w["delta"].astype(np.float32)).cuda()
+    c = torch.from_numpy(w["coef"].astype(np.float32)).cuda()
+    uu = np.stack([F.pad(1e-3 * F.grf(n, 3, 1.0, 0.1, 5, 300 + k), R) for k in range(3)])
+    u = torch.from_numpy(uu.astype(np.float32)).cuda()
+    out = torch.empty((3, n, n, n), dtype=torch.float32, device="cuda")
+    res = {"n": n, "components": 3}
+    for nm, kernel, prec, fast in [("direct_inv_r_ms", ndl.NDL_G_INV_R, ndl.NDL_F32K, False),
+                                   ("direct_cone_ms", ndl.NDL_G_CONE, ndl.NDL_F32K, False),
+                                   ("fast_inv_r_ms", ndl.NDL_G_INV_R, ndl.NDL_F32C, True)]:
+        plan = ndl.ndl_plan_create(ndl.make_problem(3, n, R, d, c, model=ndl.NDL_PERIDYNAMIC, kernel=kernel,
+                                                    prec=prec), want_fast=int(fast), keep=(d, c))
+        fn = (lambda: ndl.ndl_apply_fast(plan, u, out, 1)) if fast else (lambda: ndl.ndl_apply(plan, u, out, 1))
+        secs, _ = timed(fn, steps, 2)
+        res[nm] = secs / steps * 1e3
+        res["pairs_per_point"] = plan.info().pairs_per_point
+        plan.close()
+    return res
+
+
 def bench_example2(sizes=(4096, 8192, 16384)):
     """The paper's second example at growing N: 1D, delta(x) = (1/4)(1 +
     exp(-20 (x - 1/2)^2)) (N/4 to N/2 neighbours per side), the K = 3
@@ -449,7 +518,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-rows", action="store_true", help="headline only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", default="", help="run one row only (profiling): cg64, pcg3d, net, pd, pdfast, ex2, big, sweep, fast, f64, 1d, "
+    ap.add_argument("--only", default="", help="run one row only (profiling): cg64, pcg3d, net, pd, pdfast, pd3d, sym, ex2, big, sweep, fast, f64, 1d, "
                          "or calib (the counter calibration copy)")
     ap.add_argument("--cg-iters", type=int, default=0, help="cap the solver iterations (profiling)")
     ap.add_argument("--variant", type=int, default=None,
@@ -469,7 +538,8 @@ def main():
               "pcg3d": lambda: bench_pcg_3d(max_iter=args.cg_iters or None),
               "net": bench_net, "pd": bench_pd, "pdfast": lambda: bench_pd(fast=True), "ex2": bench_example2,
               "big": bench_big, "1d": bench_1d, "calib": calib_copy, "sweep": bench_sweep, "f64": lambda: bench_apply(ndl.NDL_F64, False, args.steps, args.warmup, args.variant)["seconds"],
-              "fast": lambda: bench_apply(ndl.NDL_F32C, True, args.steps, args.warmup)["seconds"]}[args.only]
+              "fast": lambda: bench_apply(ndl.NDL_F32C, True, args.steps, args.warmup)["seconds"],
+              "sym": bench_sym, "pd3d": bench_pd3d}[args.only]
         print(json.dumps({"only": args.only, "result": fn()}, default=str), flush=True)
         return
 
@@ -513,6 +583,10 @@ def main():
         rows["pd_2048x8_f32k"] = bench_pd()
         log("row: peridynamics 2048^2 x 8 fields, hierarchical")
         rows["pd_2048x8_fast_f32c"] = bench_pd(fast=True)
+        log("row: 3D peridynamics 128^3, 1/r and conical micromoduli")
+        rows["pd_3d_128"] = bench_pd3d()
+        log("row: kernel-averaged symmetric form, 1024^2")
+        rows["sym_2d_1024"] = bench_sym()
         log("row: the paper's second example (1D, K = 3) at growing N")
         rows["example2_1d_k3"] = bench_example2()
         log("row: 64 batched solves to 1e-8")
