@@ -56,7 +56,9 @@ static SymGeom sym_geom(const Plan& p, int E0, int E1, int E2)
 // padded state, the cutoff k and scale s of every node of the tile and its
 // halo (k = -1 marks the collar, whose partners keep omega_x).  DIAG: the
 // diagonal of -L_s (the sum of the weights) instead of L_s u.
-template <typename T, bool DIAG>
+// NPT nodes per thread, E[1] / NPT rows apart (2D: 8 x 64 tiles, so that the
+// per-offset work and the halo serve two nodes).
+template <typename T, bool DIAG, int NPT>
 __global__ __launch_bounds__(256) void k_direct_sym(const T* __restrict__ u, T* __restrict__ out,
                                                     const int32_t* __restrict__ kk, const T* __restrict__ sc,
                                                     const int4* __restrict__ full, const double* __restrict__ fw,
@@ -78,6 +80,7 @@ __global__ __launch_bounds__(256) void k_direct_sym(const T* __restrict__ u, T* 
         T u, s;
         int k;
     };
+    int kloc = -1;  // the largest cutoff this thread stages (tile and halo)
     stage_batched(
         tot,
         [&](int idx) {
@@ -99,30 +102,58 @@ __global__ __launch_bounds__(256) void k_direct_sym(const T* __restrict__ u, T* 
             tu[idx] = v.u;
             tk[idx] = v.k;
             ts[idx] = v.s;
+            kloc = max(kloc, v.k);
         });
+    // the block's largest cutoff: no pair of the tile lies past it (a pair
+    // counts if |z|^2 <= k_x or |z|^2 <= k_y, both staged here)
+    __shared__ int s_kmax[4];
+    kloc = wave_max(kloc);
+    if ((threadIdx.x & 63) == 0) s_kmax[threadIdx.x >> 6] = kloc;
     __syncthreads();
-    const int e2 = threadIdx.x % g.E[2], e1 = (threadIdx.x / g.E[2]) % g.E[1], e0 = threadIdx.x / (g.E[2] * g.E[1]);
-    const int x0 = org[0] + e0, x1 = org[1] + e1, x2 = org[2] + e2;
-    if (e0 >= g.E[0] || x0 >= g.ext[0] || x1 >= g.ext[1] || x2 >= g.ext[2]) return;
+    const int kb = min(kmax, max(max(s_kmax[0], s_kmax[1]), max(s_kmax[2], s_kmax[3])));
+    const int E1 = g.E[1] / NPT;  // rows of the tile that one pass of the threads covers
+    const int e2 = threadIdx.x % g.E[2], e1 = (threadIdx.x / g.E[2]) % E1, e0 = threadIdx.x / (g.E[2] * E1);
+    const int x0 = org[0] + e0, x2 = org[2] + e2;
+    if (e0 >= g.E[0] || x0 >= g.ext[0] || x2 >= g.ext[2]) return;
     const int ls1 = g.L[2], ls0 = g.L[1] * g.L[2];
-    const int c = (e0 + hal[0]) * ls0 + (e1 + hal[1]) * ls1 + (e2 + hal[2]);
-    const int kx = tk[c];
-    const T sx = ts[c], u0 = tu[c];
-    Acc<T> acc;
+    int c[NPT], kx[NPT];
+    T sx[NPT], u0[NPT];
+    bool valid[NPT];
+    Acc<T> acc[NPT];
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+        valid[j] = org[1] + e1 + j * E1 < g.ext[1];
+        c[j] = (e0 + hal[0]) * ls0 + (e1 + j * E1 + hal[1]) * ls1 + (e2 + hal[2]);
+        kx[j] = tk[c[j]];
+        sx[j] = ts[c[j]];
+        u0[j] = tu[c[j]];
+    }
     for (int q = 0; q < nfull; ++q) {
         const int4 o = full[q];
-        if (o.w > kmax) break;
+        if (o.w > kb) break;
         const int off = o.x * ls0 + o.y * ls1 + o.z;
-        const int ky = tk[c + off];
-        const T wx = o.w <= kx ? sx : T(0);
-        const T wy = ky < 0 ? wx : (o.w <= ky ? ts[c + off] : T(0));  // the collar keeps omega_x
-        const T w = T(0.5) * (wx + wy) * (T)fw[q];
-        if (DIAG) acc.add_(w);
-        else acc.fma_(w, tu[c + off] - u0);
-        if ((q & 7) == 7) acc.flush();
+        const T fq = (T)fw[q];
+#pragma unroll
+        for (int j = 0; j < NPT; ++j) {
+            const int ky = tk[c[j] + off];
+            const T wx = o.w <= kx[j] ? sx[j] : T(0);
+            const T wy = ky < 0 ? wx : (o.w <= ky ? ts[c[j] + off] : T(0));  // the collar keeps omega_x
+            const T w = T(0.5) * (wx + wy) * fq;
+            if (DIAG) acc[j].add_(w);
+            else acc[j].fma_(w, tu[c[j] + off] - u0[j]);
+        }
+        if ((q & 7) == 7) {
+#pragma unroll
+            for (int j = 0; j < NPT; ++j) acc[j].flush();
+        }
     }
-    const int64_t gi = ((int64_t)x0 * g.ext[1] + x1) * g.ext[2] + x2;
-    ob[gi] = acc.value();
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+        if (!valid[j]) continue;
+        const int x1 = org[1] + e1 + j * E1;
+        const int64_t gi = ((int64_t)x0 * g.ext[1] + x1) * g.ext[2] + x2;
+        ob[gi] = acc[j].value();
+    }
 }
 
 template <typename T>
@@ -130,25 +161,38 @@ static int launch_sym_t(Plan& p, const void* u, void* Lu, int batch, bool diag, 
 {
     int E[3];
     if (p.dim == 1) { E[0] = 1; E[1] = 1; E[2] = 256; }
-    else if (p.dim == 2) { E[0] = 1; E[1] = 4; E[2] = 64; }
+    else if (p.dim == 2) { E[0] = 1; E[1] = 8; E[2] = 64; }  // two nodes per thread
     else { E[0] = 2; E[1] = 2; E[2] = 64; }
     SymGeom g = sym_geom(p, E[0], E[1], E[2]);
+    // two nodes per thread only where the launch still has four blocks per
+    // unit: small 2D grids keep one node per thread (twice the blocks)
+    bool two = p.dim == 2;
+    if (two && (int64_t)g.tiles[1] * g.tiles[2] < 1024) {
+        two = false;
+        g = sym_geom(p, 1, 4, 64);
+    }
     const size_t lds = (size_t)g.L[0] * g.L[1] * g.L[2] * (2 * sizeof(T) + sizeof(int));
     if (lds > 144 * 1024) {
         set_error("kernel-averaged form: horizon too wide for the tile (%zu B of LDS)", lds);
         return NDL_EUNSUPPORTED;
     }
-    const void* fn = diag ? (const void*)k_direct_sym<T, true> : (const void*)k_direct_sym<T, false>;
+    const void* fn = diag ? (two ? (const void*)k_direct_sym<T, true, 2> : (const void*)k_direct_sym<T, true, 1>)
+                          : (two ? (const void*)k_direct_sym<T, false, 2> : (const void*)k_direct_sym<T, false, 1>);
     if (lds > 48 * 1024) NDL_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const unsigned nb = (unsigned)(g.tiles[0] * g.tiles[1] * g.tiles[2]);
-    if (diag)
-        k_direct_sym<T, true><<<dim3(nb, 1), 256, lds, s>>>(nullptr, static_cast<T*>(Lu), p.d_k, (const T*)p.d_scale,
-                                                            p.d_full, (const double*)p.d_fullw, p.nfull,
-                                                            (int)p.kmax, g);
-    else
-        k_direct_sym<T, false><<<dim3(nb, (unsigned)batch), 256, lds, s>>>(
-            static_cast<const T*>(u), static_cast<T*>(Lu), p.d_k, (const T*)p.d_scale, p.d_full,
-            (const double*)p.d_fullw, p.nfull, (int)p.kmax, g);
+    auto go = [&](auto npt) {
+        constexpr int NPT = decltype(npt)::value;
+        if (diag)
+            k_direct_sym<T, true, NPT><<<dim3(nb, 1), 256, lds, s>>>(nullptr, static_cast<T*>(Lu), p.d_k,
+                                                                    (const T*)p.d_scale, p.d_full,
+                                                                    (const double*)p.d_fullw, p.nfull, (int)p.kmax, g);
+        else
+            k_direct_sym<T, false, NPT><<<dim3(nb, (unsigned)batch), 256, lds, s>>>(
+                static_cast<const T*>(u), static_cast<T*>(Lu), p.d_k, (const T*)p.d_scale, p.d_full,
+                (const double*)p.d_fullw, p.nfull, (int)p.kmax, g);
+    };
+    if (two) go(std::integral_constant<int, 2>{});
+    else go(std::integral_constant<int, 1>{});
     NDL_HIP(hipGetLastError());
     return NDL_OK;
 }

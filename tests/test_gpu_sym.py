@@ -36,6 +36,51 @@ def test_sym_apply(prec, fast, dim, n, R, mlo, mhi, kernel):
     assert err <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", [ndl.NDL_F64, ndl.NDL_F32K])
+def test_sym_apply_large_2d(prec):
+    """The 2D direct sum on a grid large enough for its two-nodes-per-thread
+    tiles (8 x 64; 730 leaves ragged rows and columns), with collar data,
+    against the oracle."""
+    dim, n, R = 2, 730, 7
+    say(f"case sym large 2D n={n} prec={prec}")
+    delta, c, u = rand_problem(dim, n, R, 2.0, 6.0, seed=1300, smooth=True)
+    kw = dict(form=ndl.NDL_SYM, kernel=ndl.NDL_G_FRAC)
+    got, _ = gpu_apply(dim, n, R, delta, c, u, prec, **kw)
+    ref = oracle_apply(dim, n, R, delta, c, u, prec, **kw)
+    err = rel_l2(got, ref)
+    say("  rel l2", err)
+    assert err <= TOL[prec]
+
+
+def test_sym_cg_large_2d():
+    """Jacobi-CG (FP64) through the two-nodes-per-thread direct sum and its
+    diagonal at 730^2: the oracle's FP64 residual is <= 1e-8."""
+    import torch
+    dim, n, R = 2, 730, 7
+    say(f"case sym cg large n={n}")
+    g = np.random.default_rng(n)
+    X = F.mesh(n, dim)
+    m = 2.0 + 4.0 * 0.5 * (1 + np.sin(2 * np.pi * X[0]) * np.cos(2 * np.pi * X[-1]))
+    delta = m / n
+    c = np.exp(g.normal(0.0, 0.5, (n,) * dim))
+    b = g.standard_normal((n,) * dim)
+    d_d, d_c = dev(delta, ndl.NDL_F64), dev(c, ndl.NDL_F64)
+    plan = ndl.ndl_plan_create(ndl.make_problem(dim, n, R, d_d, d_c, form=ndl.NDL_SYM, kernel=ndl.NDL_G_FRAC,
+                                                prec=ndl.NDL_F64), keep=(d_d, d_c))
+    bb = torch.from_numpy(b).cuda()
+    x = torch.zeros_like(bb)
+    rc, reps = ndl.ndl_cg_solve([plan], [bb], [x], rtol=1e-8)
+    torch.cuda.synchronize()
+    say(f"  rc {rc} iters {reps[0].iters} res {reps[0].rel_res_fp64:.2e}")
+    assert rc == ndl.NDL_OK and reps[0].converged
+    P = O.Problem(dim=dim, n=n, R=R, form="sym", kernel="frac")
+    res = b + O.apply(P, delta, c, F.pad(x.cpu().numpy(), R))
+    rel = np.linalg.norm(res) / np.linalg.norm(b)
+    say(f"  oracle residual {rel:.2e}")
+    assert rel <= 1.05e-8
+    plan.close()
+
+
 @pytest.mark.parametrize("fast", [False, True])
 @pytest.mark.parametrize("dim,n,R,kernel", [(2, 24, 6, ndl.NDL_G_FRAC), (2, 28, 7, ndl.NDL_G_CONST),
                                             (3, 9, 4, ndl.NDL_G_FRAC)])
