@@ -242,11 +242,13 @@ __global__ __launch_bounds__(256) void k_div_items(const Inst* __restrict__ inst
 
 // The same operator for batches of 2D and 3D problems with the discrete
 // normalisation, mapped for gfx950: a block covers a 16 x 64 tile (2D, 4
-// waves of 4 rows) or an 8 x 4 x 64 tile (3D, 16 waves of two rows of one
-// plane), and each lane 4 (2D) or 2 (3D) nodes of one column along axis
-// dim-2, so the uniform per-offset work (offset, |z|^2, |z|^e) is shared by
-// those nodes and the partner reads of one offset use immediate LDS offsets
-// from one address.
+// waves of 4 rows) or an 8 x 4 x 64 tile (3D, 16 waves of 4 rows x 32
+// columns), and each lane 4 (2D) or 2 (3D) nodes of one column along
+// axis dim-2, so the uniform per-offset work (offset, |z|^2, |z|^e) is shared
+// by those nodes and the partner reads of one offset use immediate LDS
+// offsets from one address.  A 3D wave ends its offset loop at the bound of
+// its own block and the reach around it, which the compact block keeps close
+// to its nodes' horizons.
 // 2D tiles stage m = delta n/2 in FP64 (exact for FP32 delta, so that
 // m_i + m_j is exactly the (delta_i + delta_j) n/2 of the cutoff rule; FP64
 // data stage delta and form (delta_i + delta_j) n/2 as the rule writes it);
@@ -311,6 +313,11 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
     constexpr int KW = w2_width(DIM, JT);
     constexpr bool TABOK = DIM == 3 || (sizeof(T) == 4 && JT <= 7);
     __shared__ T s_w2[TABOK ? KW * KW : 1];
+    // 3D: per staged plane and column, the largest staged delta over the
+    // tile's rows (each wave's loop bound is read from it)
+    static_assert(DIM != 3 || (SH::TY == 4 && PYV >= 2), "3D waves cover the tile's 4 rows");
+    constexpr int kCM = DIM == 3 ? (SH::TZ + 2 * JT) * (64 + 2 * JT) : 1;
+    __shared__ float s_cmax[kCM];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -413,6 +420,16 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
                 lc(idx) = cc;
                 lu(idx) = v.u;
             });
+        if constexpr (DIM == 3) {
+            __syncthreads();  // the staged tile is complete
+            for (int e = threadIdx.x; e < SZ * PITCH; e += blockDim.x) {
+                const int sz = e / PITCH, c = e - sz * PITCH;
+                float v = 0.f;  // nodes outside Omega hold -1
+#pragma unroll
+                for (int r = 0; r < SY; ++r) v = fmaxf(v, (float)lm(sz * PLANE + r * PITCH + c));
+                s_cmax[e] = v;
+            }
+        }
         // block extremes of m (uniform loop bounds)
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) {
@@ -436,12 +453,33 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
         const bool edge = z0 - HZ < 0 || z0 + TZ + HZ > nz || y0 - J < 0 || x0 - J < 0 || y0 + TY + J > n ||
                           x0 + 64 + J > n;
 
-        const int x = x0 + lane;
-        // wave wv holds PY rows of one plane: 2D rows 4 wv .. 4 wv + 3; 3D plane
-        // wv / 2, rows 2 (wv mod 2) .. + 1 (8 planes, or a 4-plane slab for FP64 vectors)
-        constexpr int WPP = SH::TY / PY;  // waves per plane
-        const int wz = wv / WPP, wy = (wv % WPP) * PY;
-        const int base = (wz + HZ) * PLANE + (wy + J) * PITCH + lane + J;
+        // the lane's nodes: column wx, rows wy .. wy + PY - 1 of plane wz.
+        // 2D: wave wv holds rows PY wv .. PY wv + PY - 1, one node column per
+        // lane.  3D: wave wv holds a 32-column x 4-row x PY/2-plane block
+        // (column half xh, plane group zg), each half-wave 32 consecutive
+        // columns (stride-3 LDS words, distinct banks), so that its nodes'
+        // horizons, and with them its offset loop, span less than a full
+        // tile row would (the horizon varies along the rows).  Waves wv and
+        // wv + 4 share a SIMD and take opposite halves, which balances the
+        // SIMDs' loops.
+        constexpr int ZL = DIM == 3 ? PY / 2 : 1;  // planes per wave
+        const int xh = NWAVES >= 8 ? (wv >> 2) & 1 : wv & 1;
+        const int zg = NWAVES >= 8 ? (wv & 3) + 4 * (wv >> 3) : wv >> 1;
+        int wx, wy, wz;
+        if constexpr (DIM == 3) {
+            constexpr int YG = SH::TY / PY;  // row groups of a wave (2 or 1)
+            const int h = lane >> 5;
+            wx = xh * 32 + (lane & 31);
+            wy = (h % YG) * PY;
+            wz = zg * ZL + h / YG;
+        } else {
+            constexpr int WPP = SH::TY / PY;  // waves per plane
+            wx = lane;
+            wy = (wv % WPP) * PY;
+            wz = wv / WPP;
+        }
+        const int x = x0 + wx;
+        const int base = (wz + HZ) * PLANE + (wy + J) * PITCH + wx + J;
         double mi[PY], mh[PY];  // m of the node (scaled by n/2 when SC), and m n / 2
         T cci[PY], ui[PY];
         bool valid[PY];
@@ -474,8 +512,27 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
             }
             return lo;
         };
-        const int p_in = first_at_least(tmin);
-        const int p_end = first_at_least(tmax);
+        double tend = tmax;
+        if constexpr (DIM == 3) {
+            // a 3D wave's pairs join nodes of its planes and columns widened by
+            // the reach J (all rows of the tile): (2 max m)^2 over that region
+            // bounds their t, computed as the tile's bound is
+            const int zb = zg * ZL, xb = xh * 32;
+            constexpr int RW = 32 + 2 * J;  // region columns, one per lane
+            static_assert(RW <= 64, "one region column per lane");
+            float wm = 0.f;
+            if (lane < RW) {
+#pragma unroll
+                for (int pz = 0; pz < ZL + 2 * HZ; ++pz) wm = fmaxf(wm, s_cmax[(zb + pz) * PITCH + xb + lane]);
+            }
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) wm = fmaxf(wm, __shfl_xor(wm, o, 64));
+            wm = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wm)));
+            const double ws = (double)wm * nh;
+            tend = fmin(tmax, 4.0 * ws * ws);
+        }
+        const int p_end = first_at_least(tend);
+        const int p_in = min(first_at_least(tmin), p_end);
         // per-lane bases of the staged fields: a partner read is the base plus
         // the uniform offset (one add per offset for the interleaved tile, one
         // per field for the three arrays)
