@@ -377,3 +377,51 @@ def test_batched_apply_every_variant(dim, prec, sizes, R, mhi):
     say(f"  tuned variant {used}")
     assert 0 <= used < nvar
     assert all(np.array_equal(y.cpu().numpy(), b) for y, b in zip(ys, first))
+
+
+def test_batched_apply_3d_horizon_spikes():
+    """The 3D batched case (b) apply ends each wave's offset loop at the largest
+    horizon within reach of its block (its 32 columns and 4 rows widened by the
+    reach, every plane within the reach).  A flat horizon m = 2 with isolated
+    nodes of m = 3.9 (reach 3: m = 4 would round past k = 15 in FP32) at and
+    beside those block edges, in the halo of a wave's block, on the grid's
+    faces and in a ragged tile: every variant must still sum each spike's
+    pairs (t = 8.7 against 4 for the flat field), element by element against
+    the FP64 oracle."""
+    import torch
+    R = 4
+    sizes = [70, 29]
+    say(f"case 3D batched apply with horizon spikes sizes={sizes}")
+    plans, xs, refs = [], [], []
+    for i, n in enumerate(sizes):
+        g = np.random.default_rng(880 + i)
+        m = np.full((n, n, n), 2.0)
+        cols = [c for c in (0, 1, 28, 29, 30, 31, 32, 33, 34, 35, 36, 63, 64, 66, 69) if c < n]
+        for k, c in enumerate(cols):
+            z, y = (5 * k + 3 * i) % n, (7 * k + 1) % n
+            m[z, y, c] = 3.9
+            m[(z + 9) % n, (y + 4) % n, c] = 3.9  # another plane and row block
+        m[n - 1, n - 1, n - 1] = 3.9
+        c = np.exp(g.normal(0.0, 0.5, (n,) * 3))
+        x = g.standard_normal((n,) * 3)
+        delta = (m / n).astype(np.float32)
+        c32, x32 = c.astype(np.float32), x.astype(np.float32)
+        d_d, d_c = dev(delta, ndl.NDL_F32C), dev(c32, ndl.NDL_F32C)
+        plans.append(ndl.ndl_plan_create(ndl.make_problem(3, n, R, d_d, d_c, form=ndl.NDL_DIV, prec=ndl.NDL_F32C),
+                                         keep=(d_d, d_c)))
+        xs.append(dev(x32, ndl.NDL_F32C))
+        P = O.Problem(dim=3, n=n, R=R, form="div", kernel="frac")
+        refs.append(-O.apply(P, delta.astype(np.float64), c32.astype(np.float64),
+                             F.pad(x32.astype(np.float64), R)))
+    v, nvar = 0, None
+    while nvar is None or v < nvar:
+        ys = [torch.full((n,) * 3, float("nan"), dtype=torch.float32, device="cuda") for n in sizes]
+        used, nvar = ndl.ndl_div_batch_apply(plans, xs, ys, v)
+        assert used == v
+        for y, ref, n in zip(ys, refs, sizes):
+            got = y.cpu().numpy()
+            err = rel_l2(got, ref)
+            worst = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+            say(f"  variant {v}/{nvar} n={n} rel l2 {err:.2e} worst node {worst:.2e}")
+            assert err <= 1e-6 and worst <= 1e-5
+        v += 1
