@@ -262,7 +262,7 @@ __global__ __launch_bounds__(256) void k_div_items(const Inst* __restrict__ inst
 // The membership test is skipped for offsets inside every pair's ball of the
 // tile (|z|^2 < (2 min m)^2) and the loop ends past the largest
 // (|z|^2 >= (2 max m)^2); a partner outside Omega takes (delta_i, c_i), which
-// only tiles within J of the boundary test for.
+// only waves with nodes within J of the boundary test for.
 // 3D: 2 nodes per lane, 16 waves per 8 x 4 x 64 tile (the haloed tile leaves
 // room for one block per CU, so the occupancy comes from the block's waves)
 // Tile of one block: 16 x 64 (2D) or 8 x 4 x 64 (3D) nodes, PY nodes per
@@ -450,8 +450,6 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
         }
         const double tmax = 4.0 * mmax * mmax;  // (2 max m)^2 >= every t of the tile
         const double tmin = 4.0 * mmin * mmin;
-        const bool edge = z0 - HZ < 0 || z0 + TZ + HZ > nz || y0 - J < 0 || x0 - J < 0 || y0 + TY + J > n ||
-                          x0 + 64 + J > n;
 
         // the lane's nodes: column wx, rows wy .. wy + PY - 1 of plane wz.
         // 2D: wave wv holds rows PY wv .. PY wv + PY - 1, one node column per
@@ -480,6 +478,18 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
         }
         const int x = x0 + wx;
         const int base = (wz + HZ) * PLANE + (wy + J) * PITCH + wx + J;
+        // a partner of one of the wave's nodes lies outside Omega (or the wave
+        // holds nodes past the grid): the wave takes the pair loop that
+        // substitutes the node's own horizon and coefficient for such partners
+        bool edge;
+        if constexpr (DIM == 3) {
+            const int zb = z0 + zg * ZL, xb = x0 + xh * 32;
+            edge = zb - HZ < 0 || zb + ZL + HZ > nz || y0 - J < 0 || y0 + TY + J > n || xb - J < 0 ||
+                   xb + 32 + J > n;
+        } else {
+            const int yb = y0 + wy;  // the wave's first row
+            edge = yb - J < 0 || yb + PY + J > n || x0 - J < 0 || x0 + 64 + J > n;
+        }
         double mi[PY], mh[PY];  // m of the node (scaled by n/2 when SC), and m n / 2
         T cci[PY], ui[PY];
         bool valid[PY];
