@@ -455,7 +455,7 @@ __global__ __launch_bounds__((DivShape<T, DIM, PYV>::THREADS)) void k_div2_items
         // 2D: wave wv holds rows PY wv .. PY wv + PY - 1, one node column per
         // lane.  3D: wave wv holds a 32-column x 4-row x PY/2-plane block
         // (column half xh, plane group zg), each half-wave 32 consecutive
-        // columns (stride-3 LDS words, distinct banks), so that its nodes'
+        // columns (consecutive nodes of the staged tile), so that its nodes'
         // horizons, and with them its offset loop, span less than a full
         // tile row would (the horizon varies along the rows).  Waves wv and
         // wv + 4 share a SIMD and take opposite halves, which balances the
